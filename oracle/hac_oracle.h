@@ -1,0 +1,90 @@
+/*
+ * Plain CPU oracle for the HeatACO decode loop (heatmap-guided Max-Min Ant
+ * System).  TEST INFRASTRUCTURE: only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code with the HIP
+ * library; both are fed by the seeded input generators.
+ *
+ * Everything here is single-threaded FP64 (FP32 where the method stores
+ * FP32 state), compiled without contraction or fast-math.
+ */
+#ifndef HAC_ORACLE_H
+#define HAC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_COORDS = 0, ORC_MATRIX = 1 };
+
+typedef struct {
+  /* instance: coords [n][2] (Euclidean, symmetric) or dist [n][n] row-major */
+  int32_t n, kind, symmetric;
+  const double* coords;
+  const double* dist;
+  /* heatmap h as consumed, CSR */
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+  /* MMAS / HeatACO parameters (Section IV-C) */
+  int32_t ants, iterations, k, k_ls, local_search;
+  double alpha, beta, rho, p_best, c_cap, theta_h, eps, xi_bf, lambda_bf, clip;
+  int32_t degree_target, bf_period, restart_stall, ugb_max, baseline_scope;
+  uint64_t seed;
+} orc_problem;
+
+/* optional outputs; any pointer may be NULL */
+typedef struct {
+  int32_t k_eff;
+  double q90, r_hat, kappa, l_nn, l_nn_raw;
+  int64_t ant_steps, fallback_steps;
+  int32_t restarts;
+  double* l_ib;        /* [iterations] iteration-best length (after LS)  */
+  double* l_gb;        /* [iterations] global-best length after the iteration */
+  int32_t* elite_rb;   /* [iterations] 1 if the restart-best tour deposited  */
+  int32_t* cand;       /* [n*k_eff] candidate lists                          */
+  float* heur;         /* [n*k_eff] folded eta^beta * e^kappa                */
+  float* tau;          /* [n*k_eff] pheromone after the last iteration       */
+  float* weight;       /* [n*k_eff] choice weights after the last iteration  */
+  int32_t* ant_tours;  /* [ants*n] tours of the last iteration, as built     */
+  double* ant_len;     /* [ants] their lengths                               */
+  int32_t* nn_tour;    /* [n] the (optionally 2-opted) NN tour               */
+} orc_trace;
+
+/* Philox4x32-10 block */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* 64-bit uniform for (seed, iteration t, ant a, step s) */
+uint64_t orc_draw(uint64_t seed, uint32_t t, uint32_t a, uint32_t s);
+
+/* Candidate lists (eq. 3): writes n*k_eff ids, returns k_eff or <0 on error */
+int32_t orc_candidates(const orc_problem* p, int32_t* cand);
+/* Geometric nearest-neighbour lists of size kk (for local search) */
+int32_t orc_nearest_lists(const orc_problem* p, int32_t kk, int32_t* out);
+
+/* Evidence (eq. 9-11), scale (eq. 12-14) and fold.  Inputs: candidates.
+ * Outputs (each may be NULL): conf c [n*k], base b [n], evid e [n*k],
+ * heur S [n*k]; returns kappa, and q90 / r_hat through pointers. */
+double orc_evidence(const orc_problem* p, const int32_t* cand, int32_t k_eff, double* conf,
+                    double* base, double* evid, float* heur, double* q90, double* r_hat);
+
+/* One roulette decision: chooses among the unvisited slots of a row.
+ * Returns the chosen slot, or -1 if every slot is visited. */
+int32_t orc_select(int32_t k, const int32_t* cand_row, const float* w_row,
+                   const uint8_t* visited, uint64_t u);
+
+/* Nearest-neighbour tour from node 0 (Alg. 1 preparation); returns length */
+double orc_nn_tour(const orc_problem* p, int32_t* tour);
+/* Tour length, summed in array order with the closing edge last (eq. 1) */
+double orc_tour_length(const orc_problem* p, const int32_t* tour);
+/* First-improvement neighbour-list 2-opt with a don't-look queue. */
+void orc_two_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min_gain,
+                 int32_t* tour);
+
+/* Whole decode (Alg. 1).  tour_out [n] canonical, len_out.  0 on success. */
+int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc_trace* tr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

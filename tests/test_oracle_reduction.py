@@ -1,0 +1,192 @@
+"""Reduction pin: with no heatmap evidence the decoder is plain MMAS.
+
+Section III-A and III-C: when kappa = 0 (no edge has e > 1) the transition
+weights take the classical MMAS form over the candidate list.  This file
+holds a second, independently written MMAS in pure Python (its own Philox,
+its own candidate lists, roulette, bounds and update, written from the same
+definitions) and checks that the oracle's whole decode returns the identical
+tour and length on small instances with an empty heatmap.  It also checks
+the u_gb elite choice and the restart path by forcing them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_19041_amd import workloads as wl
+
+M32 = 0xFFFFFFFF
+
+
+def philox(ctr, key):
+    x0, x1, x2, x3 = ctr
+    k0, k1 = key
+    for r in range(10):
+        if r:
+            k0 = (k0 + 0x9E3779B9) & M32
+            k1 = (k1 + 0xBB67AE85) & M32
+        p0 = 0xD2511F53 * x0
+        p1 = 0xCD9E8D57 * x2
+        x0, x1, x2, x3 = (p1 >> 32) ^ x1 ^ k0, p1 & M32, (p0 >> 32) ^ x3 ^ k1, p0 & M32
+    return x0, x1, x2, x3
+
+
+def u64(seed, t, a, s):
+    o = philox((s, a, t, 0), (seed & M32, seed >> 32))
+    return o[0] | (o[1] << 32)
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+class TextbookMMAS:
+    def __init__(self, inst, ugb_max=25, bf_period=100, restart_stall=250, xi=0.05, lam=1 + 1e-5):
+        self.inst = inst
+        self.n = n = inst.n
+        self.xy = inst.coords
+        self.k = min(inst.k, n - 1)
+        self.m, self.I, self.rho, self.seed = inst.ants, inst.iterations, inst.rho, inst.seed
+        self.ugb_max, self.bf_period, self.restart_stall, self.xi, self.lam = ugb_max, bf_period, restart_stall, xi, lam
+        # squared-distance keys computed as (dx*dx + dy*dy) in doubles
+        self.key = [[(self.xy[i, 0] - self.xy[j, 0]) * (self.xy[i, 0] - self.xy[j, 0])
+                     + (self.xy[i, 1] - self.xy[j, 1]) * (self.xy[i, 1] - self.xy[j, 1])
+                     for j in range(n)] for i in range(n)]
+        self.d = [[math.sqrt(self.key[i][j]) for j in range(n)] for i in range(n)]
+        self.nn = [sorted((j for j in range(n) if j != i), key=lambda j: (self.key[i][j], j))[: self.k]
+                   for i in range(n)]
+        self.heur = [[f32((1.0 / self.d[i][j]) * (1.0 / self.d[i][j])) for j in self.nn[i]] for i in range(n)]
+
+    def length(self, t):
+        s = 0.0
+        for q in range(self.n - 1):
+            s += self.d[t[q]][t[q + 1]]
+        return s + self.d[t[-1]][t[0]]
+
+    def bounds(self, L):
+        tmax = 1.0 / (self.rho * L)
+        px = math.pow(0.05, 1.0 / self.n)
+        tmin = tmax * (1.0 - px) / (((self.k - 1) / 2.0) * px)
+        return f32(tmax), f32(tmin)
+
+    def nearest_free(self, i, vis):
+        return min((j for j in range(self.n) if not vis[j]), key=lambda j: (self.key[i][j], j))
+
+    def ant(self, w, t, a):
+        n = self.n
+        vis = [False] * n
+        cur = (u64(self.seed, t, a, 0) * n) >> 64
+        tour = [cur]
+        vis[cur] = True
+        for s in range(1, n):
+            i = tour[-1]
+            open_ = [q for q in range(self.k) if not vis[self.nn[i][q]]]
+            if not open_:
+                j = self.nearest_free(i, vis)
+            else:
+                E = max(math.frexp(w[i][q])[1] - 1 for q in open_)
+                qs = [max(1, math.floor(math.ldexp(w[i][q], 31 - E))) for q in open_]
+                r = (u64(self.seed, t, a, s) * sum(qs)) >> 64
+                acc = 0
+                for q, wq in zip(open_, qs):
+                    acc += wq
+                    if acc > r:
+                        j = self.nn[i][q]
+                        break
+            tour.append(j)
+            vis[j] = True
+        return tour
+
+    def run(self):
+        n = self.n
+        vis = [False] * n
+        nn_t = [0]
+        vis[0] = True
+        for _ in range(n - 1):
+            j = self.nearest_free(nn_t[-1], vis)
+            nn_t.append(j)
+            vis[j] = True
+        gb, Lgb = nn_t, self.length(nn_t)
+        tmax, tmin = self.bounds(Lgb)
+        tau = [[tmax] * self.k for _ in range(n)]
+        w = [[f32(tau[i][q] * self.heur[i][q]) for q in range(self.k)] for i in range(n)]
+        rb, Lrb, stall, ugb = None, None, 0, self.ugb_max
+        self.elite_log = []
+        for t in range(1, self.I + 1):
+            tours = [self.ant(w, t, a) for a in range(self.m)]
+            lens = [self.length(x) for x in tours]
+            ib = min(range(self.m), key=lambda a: (lens[a], a))
+            Tib, Lib = tours[ib], lens[ib]
+            if rb is None or Lib < Lrb:
+                rb, Lrb, stall = Tib, Lib, 0
+            else:
+                stall += 1
+            if Lib < Lgb:
+                gb, Lgb = Tib, Lib
+                tmax, tmin = self.bounds(Lgb)
+            elite, Le = (rb, Lrb) if t % ugb == 0 else (Tib, Lib)
+            self.elite_log.append(t % ugb == 0)
+            on = set()
+            for q in range(n):
+                on.add((elite[q], elite[(q + 1) % n]))
+                on.add((elite[(q + 1) % n], elite[q]))
+            dep = f32(1.0 / Le)
+            keep = f32(1.0 - self.rho)
+            for i in range(n):
+                for q, j in enumerate(self.nn[i]):
+                    v = f32(keep * tau[i][q])
+                    if (i, j) in on:
+                        v = f32(v + dep)
+                    tau[i][q] = min(tmax, max(tmin, v))
+                    w[i][q] = f32(tau[i][q] * self.heur[i][q])
+            if self.bf_period and t % self.bf_period == 0:
+                br = 0
+                for i in range(n):
+                    lo, hi = min(tau[i]), max(tau[i])
+                    br += sum(1 for v in tau[i] if v >= lo + self.xi * (hi - lo))
+                if br / (2.0 * n) < self.lam and stall > self.restart_stall:
+                    tau = [[tmax] * self.k for _ in range(n)]
+                    w = [[f32(tmax * self.heur[i][q]) for q in range(self.k)] for i in range(n)]
+                    rb, stall = None, 0
+            ugb = (self.ugb_max if stall < 25 else 5 if stall < 75 else 3 if stall < 125 else 2 if stall < 250 else 1)
+        # canonical rotation
+        r0 = gb.index(0)
+        out = gb[r0:] + gb[:r0]
+        if out[1] > out[-1]:
+            out = [out[0]] + out[1:][::-1]
+        return out, Lgb
+
+
+@pytest.mark.parametrize("n,k,m,I,seed", [(12, 5, 4, 30, 3), (25, 6, 5, 20, 7), (18, 17, 3, 12, 11)])
+def test_empty_heatmap_equals_textbook_mmas(n, k, m, I, seed):
+    inst = wl.random_instance(n, seed=seed, heat="empty", k=k, ants=m, iterations=I)
+    want_t, want_L = TextbookMMAS(inst).run()
+    st, tour, L, info = oracle.decode(inst)
+    assert st == 0 and info["kappa"] == 0.0
+    assert list(tour) == want_t
+    assert L == want_L
+
+
+def test_capped_zero_equals_textbook_mmas():
+    # c_cap = 0 makes kappa = 0 even with an informative heatmap
+    inst = wl.random_instance(20, seed=4, topk=6, k=6, ants=4, iterations=15)
+    want_t, want_L = TextbookMMAS(inst).run()
+    st, tour, L, info = oracle.decode(inst, c_cap=0.0)
+    assert info["kappa"] == 0.0
+    assert list(tour) == want_t and L == want_L
+
+
+def test_elite_schedule_and_restart_forced():
+    # u_gb = 2 makes the restart-best deposit on every even iteration; a
+    # branching-factor check every 3 iterations with a tiny stall limit and a
+    # threshold above any reachable value forces restarts.
+    inst = wl.random_instance(14, seed=9, heat="empty", k=4, ants=3, iterations=40)
+    ref = TextbookMMAS(inst, ugb_max=2, bf_period=3, restart_stall=1, lam=1e9)
+    want_t, want_L = ref.run()
+    st, tour, L, info = oracle.decode(inst, trace=True, ugb_max=2, bf_period=3, restart_stall=1,
+                                      lambda_bf=1e9)
+    assert list(tour) == want_t and L == want_L
+    assert list(info["elite_rb"].astype(bool)) == ref.elite_log
+    assert info["restarts"] > 0
