@@ -1,0 +1,1027 @@
+// C ABI and host runtime of the decoder: validation, device slots,
+// preparation, launch shapes, iteration replay and results.  Every search
+// step runs in the kernels of hac_kernels.hip; the host only marshals
+// inputs, folds the evidence factor once per instance (hac_fold.cpp) and
+// sequences launches.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hac_runtime.h"
+
+namespace hac {
+
+// ------------------------------------------------------------------------
+// device arena
+// ------------------------------------------------------------------------
+DeviceArena::~DeviceArena() { release(); }
+
+void DeviceArena::release() {
+  if (base_) (void)hipFree(base_);
+  base_ = nullptr;
+  cap_ = used_ = 0;
+}
+
+hipError_t DeviceArena::reserve(size_t bytes) {
+  used_ = 0;
+  if (bytes <= cap_) return hipSuccess;
+  release();
+  hipError_t e = hipMalloc((void**)&base_, bytes);
+  if (e != hipSuccess) {
+    base_ = nullptr;
+    return e;
+  }
+  cap_ = bytes;
+  return hipSuccess;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void* DeviceArena::carve(size_t bytes) {
+  void* p = base_ + used_;
+  used_ += align256(bytes);
+  return p;
+}
+
+// ------------------------------------------------------------------------
+// validation (the same checks before any device work)
+// ------------------------------------------------------------------------
+int32_t degree_target_of(const hac_instance* inst, const hac_params* p) {
+  if (p->degree_target > 0) return p->degree_target;
+  return (inst->kind == HAC_COORDS_EUC2D || inst->symmetric) ? 2 : 1;
+}
+
+static bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_params* p,
+                    std::string* why) {
+  auto fail = [&](hac_status s, const char* m) {
+    if (why) *why = m;
+    return s;
+  };
+  if (!inst || !csr || !p) return fail(HAC_EINVAL, "null argument");
+  const int32_t n = inst->n;
+  if (n < 1) return fail(HAC_EINVAL, "n < 1");
+  if (n > HAC_MAX_N) return fail(HAC_EUNSUPPORTED, "n above HAC_MAX_N");
+  if (csr->n != n) return fail(HAC_EINVAL, "heatmap size differs from n");
+  if (inst->kind == HAC_COORDS_EUC2D) {
+    if (!inst->coords) return fail(HAC_EINVAL, "coords missing");
+    for (int64_t x = 0; x < 2 * (int64_t)n; ++x)
+      if (!std::isfinite(inst->coords[x])) return fail(HAC_EINVAL, "non-finite coordinate");
+  } else if (inst->kind == HAC_MATRIX) {
+    if (!inst->dist) return fail(HAC_EINVAL, "distance matrix missing");
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t j = 0; j < n; ++j) {
+        const double v = inst->dist[(int64_t)i * n + j];
+        if (!std::isfinite(v) || (i != j && v < 0.0)) return fail(HAC_EINVAL, "bad distance entry");
+        if (inst->symmetric && j < i && v != inst->dist[(int64_t)j * n + i])
+          return fail(HAC_EINVAL, "symmetric matrix is not symmetric");
+      }
+  } else {
+    return fail(HAC_EINVAL, "unknown instance kind");
+  }
+  if (!csr->row_ptr) return fail(HAC_EINVAL, "row_ptr missing");
+  if (csr->row_ptr[0] != 0 || csr->row_ptr[n] != csr->nnz || csr->nnz < 0)
+    return fail(HAC_EINVAL, "row_ptr does not span nnz");
+  if (csr->nnz > 0 && (!csr->col || !csr->val)) return fail(HAC_EINVAL, "col/val missing");
+  {
+    std::vector<int32_t> seen(n, -1);
+    for (int32_t i = 0; i < n; ++i) {
+      if (csr->row_ptr[i + 1] < csr->row_ptr[i]) return fail(HAC_EINVAL, "row_ptr not monotone");
+      for (int32_t e = csr->row_ptr[i]; e < csr->row_ptr[i + 1]; ++e) {
+        const int32_t j = csr->col[e];
+        if (j < 0 || j >= n) return fail(HAC_EINVAL, "column out of range");
+        if (seen[j] == i) return fail(HAC_EINVAL, "duplicate column in a row");
+        seen[j] = i;
+        const float v = csr->val[e];
+        if (!std::isfinite(v) || v < 0.0f) return fail(HAC_EINVAL, "heatmap value not finite/>=0");
+      }
+    }
+  }
+  if (p->ants < 1 || p->iterations < 0 || p->k < 1) return fail(HAC_EINVAL, "ants/k/iterations");
+  if (!(p->rho > 0.0 && p->rho < 1.0)) return fail(HAC_EINVAL, "rho outside (0,1)");
+  if (!(p->p_best > 0.0 && p->p_best < 1.0)) return fail(HAC_EINVAL, "p_best outside (0,1)");
+  if (!finite_nonneg(p->beta) || !finite_nonneg(p->c_cap) || !finite_nonneg(p->theta_h) ||
+      !(p->eps > 0.0 && std::isfinite(p->eps)) || !(p->xi_bf >= 0.0 && p->xi_bf <= 1.0) ||
+      !std::isfinite(p->lambda_bf) || !finite_nonneg(p->clip))
+    return fail(HAC_EINVAL, "parameter out of range");
+  if (p->degree_target < 0 || p->bf_period < 0 || p->restart_stall < 0 || p->ugb_max < 1 ||
+      (p->baseline_scope != 0 && p->baseline_scope != 1) ||
+      (p->local_search != 0 && p->local_search != 1) || (p->local_search && p->k_ls < 1))
+    return fail(HAC_EINVAL, "integer parameter out of range");
+  if (p->alpha != 1.0) return fail(HAC_EUNSUPPORTED, "only alpha = 1 is supported");
+  if (p->k > HAC_MAX_K) return fail(HAC_EUNSUPPORTED, "k above HAC_MAX_K");
+  if (p->local_search && p->k_ls > HAC_MAX_KLS) return fail(HAC_EUNSUPPORTED, "k_ls above HAC_MAX_KLS");
+  if (p->local_search && inst->kind == HAC_MATRIX && !inst->symmetric)
+    return fail(HAC_EUNSUPPORTED, "2-opt needs a symmetric instance");
+  return HAC_OK;
+}
+
+// ------------------------------------------------------------------------
+// slots
+// ------------------------------------------------------------------------
+Layout make_layout(const hac_instance* inst, const hac_csr* csr, const hac_params* p) {
+  Layout L;
+  L.n = inst->n;
+  L.k = std::min(p->k, inst->n - 1);
+  L.kg = std::min(inst->n - 1, 32);
+  L.kls = p->local_search ? std::min(p->k_ls, inst->n - 1) : 0;
+  L.ants = p->ants;
+  L.iterations = p->iterations;
+  L.coords = inst->kind == HAC_COORDS_EUC2D;
+  L.ls = p->local_search != 0;
+  L.staged16 = inst->n <= 65535;
+  L.nnz = csr->nnz;
+  return L;
+}
+
+size_t Layout::bytes() const {
+  const size_t nn = (size_t)n, nk = nn * (size_t)k;
+  size_t b = 0;
+  b += align256(coords ? 16 * nn : 8 * nn * nn);
+  b += align256(4 * (nn + 1)) + align256(4 * (size_t)nnz) + align256(4 * (size_t)nnz);
+  b += align256(4 * nk) + (staged16 ? align256(2 * nk + 16) : 0) + 3 * align256(4 * nk + 16);
+  b += align256(4 * nn * (size_t)kg);
+  b += align256(4 * nn * (size_t)ants) + align256(8 * (size_t)ants);
+  b += 6 * align256(4 * nn);
+  b += ls ? align256(12 * nn) : 0;
+  b += align256(sizeof(State));
+  b += 3 * align256(8 * (size_t)std::max(iterations, 1));
+  return b;
+}
+
+void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve) {
+  const Layout& L = h.lay;
+  const size_t nn = (size_t)L.n, nk = nn * (size_t)L.k;
+  InstDesc& d = h.d;
+  d.xy = L.coords ? (const double*)carve(16 * nn) : nullptr;
+  d.dist = L.coords ? nullptr : (const double*)carve(8 * nn * nn);
+  d.row_ptr = (const int32_t*)carve(4 * (nn + 1));
+  d.col = (const int32_t*)carve(4 * (size_t)L.nnz);
+  d.val = (const float*)carve(4 * (size_t)L.nnz);
+  d.cand = (int32_t*)carve(4 * nk);
+  d.cand16 = L.staged16 ? (const uint16_t*)carve(2 * nk + 16) : nullptr;
+  d.heur = (const float*)carve(4 * nk + 16);
+  d.tau = (float*)carve(4 * nk + 16);
+  d.w = (float*)carve(4 * nk + 16);
+  d.geo = (int32_t*)carve(4 * nn * (size_t)L.kg);
+  d.tours = (int32_t*)carve(4 * nn * (size_t)L.ants);
+  d.lens = (double*)carve(8 * (size_t)L.ants);
+  d.t_gb = (int32_t*)carve(4 * nn);
+  d.t_rb = (int32_t*)carve(4 * nn);
+  d.t_ib = (int32_t*)carve(4 * nn);
+  d.nn_tour = (int32_t*)carve(4 * nn);
+  d.succ = (int32_t*)carve(4 * nn);
+  d.pred = (int32_t*)carve(4 * nn);
+  d.ls_work = L.ls ? (int32_t*)carve(12 * nn) : nullptr;
+  d.st = (State*)carve(sizeof(State));
+  const size_t it = 8 * (size_t)std::max(L.iterations, 1);
+  d.tr_lib = (double*)carve(it);
+  d.tr_lgb = (double*)carve(it);
+  d.tr_elite = (int32_t*)carve(it);
+}
+
+void fill_desc_scalars(HostInst& h) {
+  const Layout& L = h.lay;
+  const hac_params& p = h.p;
+  InstDesc& d = h.d;
+  d.n = L.n;
+  d.k = L.k;
+  d.kg = L.kg;
+  d.kls = L.kls;
+  d.kind = h.inst.kind;
+  d.sym = h.sym;
+  d.dstar = h.dstar;
+  d.ants = p.ants;
+  d.iterations = p.iterations;
+  d.local_search = p.local_search;
+  d.bf_period = p.bf_period;
+  d.restart_stall = p.restart_stall;
+  d.ugb_max = p.ugb_max;
+  d.seed_lo = (uint32_t)h.seed;
+  d.seed_hi = (uint32_t)(h.seed >> 32);
+  d.rho = p.rho;
+  d.p_x = h.p_x;
+  d.xi_bf = p.xi_bf;
+  d.lambda_bf = p.lambda_bf;
+  d.min_gain = 0.0;
+  d.keep_f = (float)(1.0 - p.rho);
+  d.theta_h = p.theta_h;
+}
+
+hipError_t upload_inputs(const HostInst& h, hipStream_t s) {
+  const Layout& L = h.lay;
+  const size_t nn = (size_t)L.n;
+  const hac_instance& I = h.from_device ? h.dev_inst : h.inst;
+  const hac_csr& C = h.from_device ? h.dev_csr : h.csr;
+  const hipMemcpyKind kind = h.from_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  hipError_t e;
+  if (L.coords)
+    e = hipMemcpyAsync((void*)h.d.xy, I.coords, 16 * nn, kind, s);
+  else
+    e = hipMemcpyAsync((void*)h.d.dist, I.dist, 8 * nn * nn, kind, s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync((void*)h.d.row_ptr, C.row_ptr, 4 * (nn + 1), kind, s);
+  if (e != hipSuccess) return e;
+  if (L.nnz > 0) {
+    e = hipMemcpyAsync((void*)h.d.col, C.col, 4 * (size_t)L.nnz, kind, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync((void*)h.d.val, C.val, 4 * (size_t)L.nnz, kind, s);
+  }
+  return e;
+}
+
+// ------------------------------------------------------------------------
+// preparation
+// ------------------------------------------------------------------------
+#define HAC_HIP(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      if (err) *err = std::string(#expr) + ": " + hipGetErrorString(e_);    \
+      return HAC_EDEVICE;                                                    \
+    }                                                                        \
+  } while (0)
+
+static void parallel_for(int count, const std::function<void(int)>& fn) {
+  const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int workers = std::min(count, hw);
+  if (workers <= 1) {
+    for (int x = 0; x < count; ++x) fn(x);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  for (int w = 0; w < workers; ++w)
+    pool.emplace_back([&] {
+      for (int x = next++; x < count; x = next++) fn(x);
+    });
+  for (auto& t : pool) t.join();
+}
+
+hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipStream_t s,
+                             std::string* err) {
+  const int count = (int)hs.size();
+  int32_t max_n = 0;
+  for (auto& h : hs) max_n = std::max(max_n, h.lay.n);
+  // candidate and geometric lists (eq. 3)
+  for (int x = 0; x < count; ++x) HAC_HIP(launch_candidates(d_descs, x, hs[x].lay.n, s));
+  std::vector<std::vector<int32_t>> geo0(count);
+  for (int x = 0; x < count; ++x) {
+    HostInst& h = hs[x];
+    const size_t nk = (size_t)h.lay.n * h.lay.k;
+    h.cand_h.resize(nk);
+    geo0[x].resize((size_t)h.lay.n * h.lay.kg);
+    HAC_HIP(hipMemcpyAsync(h.cand_h.data(), h.d.cand, 4 * nk, hipMemcpyDeviceToHost, s));
+    HAC_HIP(hipMemcpyAsync(geo0[x].data(), h.d.geo, 4 * geo0[x].size(), hipMemcpyDeviceToHost, s));
+  }
+  HAC_HIP(hipStreamSynchronize(s));
+  // host fold (eq. 9-14)
+  std::vector<std::vector<float>> heur(count);
+  std::vector<std::vector<uint16_t>> c16(count);
+  std::vector<int> frc(count, FOLD_OK);
+  std::vector<double> lbs(count, 0.0);
+  parallel_for(count, [&](int x) {
+    HostInst& h = hs[x];
+    const Layout& L = h.lay;
+    FoldInput in{};
+    in.n = L.n;
+    in.k = L.k;
+    in.dstar = h.dstar;
+    in.local_search = h.p.local_search;
+    in.baseline_scope = h.p.baseline_scope;
+    in.coords = h.inst.kind == HAC_COORDS_EUC2D ? h.inst.coords : nullptr;
+    in.dist = h.inst.kind == HAC_MATRIX ? h.inst.dist : nullptr;
+    in.row_ptr = h.csr.row_ptr;
+    in.col = h.csr.col;
+    in.val = h.csr.val;
+    in.theta_h = h.p.theta_h;
+    in.eps = h.p.eps;
+    in.c_cap = h.p.c_cap;
+    in.alpha = h.p.alpha;
+    in.beta = h.p.beta;
+    in.clip = h.p.clip;
+    in.p_best = h.p.p_best;
+    in.rho = h.p.rho;
+    const size_t nk = (size_t)L.n * L.k;
+    heur[x].assign(nk + 4, 0.0f);
+    frc[x] = fold_instance(in, h.cand_h.data(), heur[x].data(), &h.fold);
+    if (L.staged16) {
+      c16[x].assign(nk + 8, 0);
+      for (size_t q = 0; q < nk; ++q) c16[x][q] = (uint16_t)h.cand_h[q];
+    }
+    // lower bound on any tour: every node leaves once, at least to its nearest
+    double lb = 0.0;
+    for (int32_t i = 0; i < L.n; ++i) {
+      const int32_t j = geo0[x][(size_t)i * L.kg];
+      if (in.coords) {
+        const double dx = in.coords[2 * i] - in.coords[2 * j];
+        const double dy = in.coords[2 * i + 1] - in.coords[2 * j + 1];
+        lb += std::sqrt(dx * dx + dy * dy);
+      } else {
+        lb += in.dist[(int64_t)i * L.n + j];
+      }
+    }
+    lbs[x] = lb;
+  });
+  for (int x = 0; x < count; ++x) {
+    if (frc[x] == FOLD_BAD_DISTANCE) {
+      if (err) *err = "instance " + std::to_string(x) + ": a candidate edge has distance <= 0";
+      return HAC_EINVAL;
+    }
+    if (frc[x] == FOLD_RANGE) {
+      if (err) *err = "instance " + std::to_string(x) + ": heuristic weight outside FP32 range";
+      return HAC_ERANGE;
+    }
+  }
+  for (int x = 0; x < count; ++x) {
+    HostInst& h = hs[x];
+    const size_t nk = (size_t)h.lay.n * h.lay.k;
+    HAC_HIP(hipMemcpyAsync((void*)h.d.heur, heur[x].data(), 4 * nk, hipMemcpyHostToDevice, s));
+    if (h.lay.staged16)
+      HAC_HIP(hipMemcpyAsync((void*)h.d.cand16, c16[x].data(), 2 * nk, hipMemcpyHostToDevice, s));
+  }
+  // NN tour (+ 2-opt), then the range check on the first bounds
+  HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
+  bool any_ls = false;
+  for (auto& h : hs) any_ls |= h.p.local_search != 0;
+  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n, s));
+  std::vector<State> sts(count);
+  for (int x = 0; x < count; ++x)
+    HAC_HIP(hipMemcpyAsync(&sts[x], hs[x].d.st, sizeof(State), hipMemcpyDeviceToHost, s));
+  HAC_HIP(hipStreamSynchronize(s));
+  for (int x = 0; x < count; ++x) {
+    HostInst& h = hs[x];
+    h.l_nn = sts[x].l_gb;
+    FoldInput in{};
+    in.n = h.lay.n;
+    in.k = h.lay.k;
+    in.local_search = h.p.local_search;
+    in.rho = h.p.rho;
+    if (fold_check_range(in, h.fold, lbs[x], h.l_nn, h.p_x) != FOLD_OK) {
+      if (err) *err = "instance " + std::to_string(x) + ": choice weights would leave FP32 range";
+      return HAC_ERANGE;
+    }
+  }
+  HAC_HIP(launch_init(d_descs, count, s));
+  return HAC_OK;
+}
+
+// ------------------------------------------------------------------------
+// XCD-aware block map.  Workgroups are dealt to the 8 XCDs round-robin by
+// block index, so block b = 8 r + x lands on XCD x; each instance's ant
+// groups are kept on one XCD (its rows then live in that XCD's L2) unless
+// it is large enough to fill several.
+// ------------------------------------------------------------------------
+static constexpr int kXcds = 8;
+
+std::vector<BlockMap> build_block_map(const std::vector<HostInst>& hs, int32_t apb) {
+  std::vector<std::vector<BlockMap>> bins(kXcds);
+  std::vector<double> load(kXcds, 0.0);
+  std::vector<int> order(hs.size());
+  for (size_t x = 0; x < hs.size(); ++x) order[x] = (int)x;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    double la = (double)hs[a].lay.n * hs[a].p.ants, lb = (double)hs[b].lay.n * hs[b].p.ants;
+    return la > lb || (la == lb && a < b);
+  });
+  for (int x : order) {
+    const int groups = (hs[x].p.ants + apb - 1) / apb;
+    const double per_group = (double)hs[x].lay.n * apb;
+    if (groups >= 64) {
+      for (int g = 0; g < groups; ++g) {
+        int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bins[b].push_back({x, g * apb});
+        load[b] += per_group;
+      }
+    } else {
+      int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      for (int g = 0; g < groups; ++g) bins[b].push_back({x, g * apb});
+      load[b] += per_group * groups;
+    }
+  }
+  size_t rounds = 0;
+  for (auto& b : bins) rounds = std::max(rounds, b.size());
+  std::vector<BlockMap> map(rounds * kXcds, BlockMap{-1, 0});
+  for (int b = 0; b < kXcds; ++b)
+    for (size_t r = 0; r < bins[b].size(); ++r) map[r * kXcds + b] = bins[b][r];
+  return map;
+}
+
+// ------------------------------------------------------------------------
+// launch-shape autotuner
+// ------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::string, LaunchShape> g_tune_cache;
+static bool g_tune_loaded = false;
+
+static const char* tune_cache_path() { return std::getenv("HAC_TUNE_CACHE"); }
+
+static void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[256];
+  int a, st;
+  while (std::fscanf(f, "%255s %d %d", key, &a, &st) == 3) g_tune_cache[key] = LaunchShape{a, st};
+  std::fclose(f);
+}
+
+static void tune_cache_store() {
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : g_tune_cache)
+    std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged);
+  std::fclose(f);
+}
+
+static bool shape_fits(const std::vector<HostInst>& hs, LaunchShape sh) {
+  for (auto& h : hs) {
+    if (sh.staged && !h.lay.staged16) return false;
+    if (construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.staged) > (size_t)max_lds_bytes())
+      return false;
+  }
+  return true;
+}
+
+size_t shape_lds(const std::vector<HostInst>& hs, LaunchShape sh) {
+  size_t b = 0;
+  for (auto& h : hs) b = std::max(b, construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.staged));
+  return b;
+}
+
+static std::string shape_key(const std::vector<HostInst>& hs) {
+  int32_t max_n = 0, k = 0;
+  int64_t ants = 0;
+  for (auto& h : hs) {
+    max_n = std::max(max_n, h.lay.n);
+    k = std::max(k, h.lay.k);
+    ants += h.p.ants;
+  }
+  int nb = 0;
+  while ((1 << nb) < max_n) nb++;
+  int ab = 0;
+  while ((1ll << ab) < ants) ab++;
+  return "gfx950/n" + std::to_string(nb) + "/k" + std::to_string(k) + "/a" + std::to_string(ab) +
+         (hs[0].lay.coords ? "/euc" : "/mat");
+}
+
+LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs, hipStream_t s,
+                       DeviceArena& scratch, bool* ok) {
+  *ok = true;
+  if (const char* force = std::getenv("HAC_SHAPE")) {
+    // "A,staged" pins the launch shape (used to show shape independence)
+    LaunchShape sh{1, 0};
+    if (std::sscanf(force, "%d,%d", &sh.ants_per_block, &sh.staged) == 2 && shape_fits(hs, sh) &&
+        sh.ants_per_block >= 1 && sh.ants_per_block <= 16)
+      return sh;
+  }
+  const std::string key = shape_key(hs);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end() && shape_fits(hs, it->second)) return it->second;
+  }
+  std::vector<LaunchShape> cands;
+  for (int apb : {1, 2, 4, 8, 16})
+    for (int st : {0, 1}) {
+      LaunchShape sh{apb, st};
+      if (shape_fits(hs, sh)) cands.push_back(sh);
+    }
+  LaunchShape best{1, 0};
+  float best_ms = 1e30f;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    *ok = false;
+    return best;
+  }
+  for (const LaunchShape& sh : cands) {
+    std::vector<BlockMap> map = build_block_map(hs, sh.ants_per_block);
+    scratch.reset();
+    if (scratch.reserve(map.size() * sizeof(BlockMap)) != hipSuccess) {
+      *ok = false;
+      break;
+    }
+    BlockMap* d_map = (BlockMap*)scratch.carve(map.size() * sizeof(BlockMap));
+    if (hipMemcpyAsync(d_map, map.data(), map.size() * sizeof(BlockMap), hipMemcpyHostToDevice, s) !=
+        hipSuccess) {
+      *ok = false;
+      break;
+    }
+    // construction only reads the state, so repeating it is harmless
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(e0, s);
+      (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block, sh.staged,
+                             shape_lds(hs, sh), s);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        *ok = false;
+        break;
+      }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    if (!*ok) break;
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = sh;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (*ok) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = best;
+    tune_cache_store();
+  }
+  return best;
+}
+
+}  // namespace hac
+
+using namespace hac;
+
+// ------------------------------------------------------------------------
+// context
+// ------------------------------------------------------------------------
+struct hac_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t budget = 0;
+  std::string err;
+  hac_stats stats{};
+  bool timing = false;
+  DeviceArena arena, scratch;
+  std::vector<HostInst> last;  // descriptors of the last call (debug hooks)
+  std::vector<hipEvent_t> events;
+};
+
+static hac_status set_err(hac_ctx* c, hac_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+extern "C" {
+
+void hac_params_default(hac_params* p) {
+  if (!p) return;
+  p->ants = 32;
+  p->iterations = 5000;
+  p->k = 20;
+  p->k_ls = 20;
+  p->local_search = 0;
+  p->alpha = 1.0;
+  p->beta = 2.0;
+  p->rho = 0.2;
+  p->p_best = 0.05;
+  p->c_cap = 0.5;
+  p->theta_h = 1e-4;
+  p->eps = 1e-9;
+  p->xi_bf = 0.05;
+  p->lambda_bf = 1.0 + 1e-5;
+  p->clip = 40.0;
+  p->degree_target = 0;
+  p->bf_period = 100;
+  p->restart_stall = 250;
+  p->ugb_max = 25;
+  p->baseline_scope = 0;
+}
+
+const char* hac_strerror(hac_status s) {
+  switch (s) {
+    case HAC_OK: return "ok";
+    case HAC_EINVAL: return "invalid argument";
+    case HAC_ENOMEM: return "out of device memory or budget";
+    case HAC_EDEVICE: return "HIP device error";
+    case HAC_EUNSUPPORTED: return "unsupported by this library";
+    case HAC_EBUSY: return "not finished";
+    case HAC_ECANCELLED: return "cancelled";
+    case HAC_ERANGE: return "weights outside the FP32 range";
+    default: return "unknown status";
+  }
+}
+
+hac_status hac_validate(const hac_instance* inst, const hac_csr* heat, const hac_params* p) {
+  return validate(inst, heat, p, nullptr);
+}
+
+hac_status hac_create(hac_ctx** out, int32_t device, void* stream, uint64_t hbm_budget_bytes) {
+  if (!out) return HAC_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return HAC_EDEVICE;
+  if (device < 0 || device >= ndev) return HAC_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return HAC_EDEVICE;
+  hac_ctx* c = new hac_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return HAC_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return HAC_OK;
+}
+
+void hac_destroy(hac_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto e : c->events) (void)hipEventDestroy(e);
+  c->arena.release();
+  c->scratch.release();
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* hac_last_error(const hac_ctx* c) { return c ? c->err.c_str() : ""; }
+
+hac_status hac_set_timing(hac_ctx* c, int32_t enable) {
+  if (!c) return HAC_EINVAL;
+  c->timing = enable != 0;
+  return HAC_OK;
+}
+
+hac_status hac_last_stats(const hac_ctx* c, hac_stats* out) {
+  if (!c || !out) return HAC_EINVAL;
+  *out = c->stats;
+  return HAC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// the batch engine behind hac_decode / hac_decode_batch / hac_decode_dev
+// ------------------------------------------------------------------------
+namespace {
+
+using Clock = std::chrono::steady_clock;
+static double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+#define CTX_HIP(expr)                                                           \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return set_err(c, HAC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// out_dev: per-instance device tour pointers (or null: results to host)
+// Host copies of inputs that live in device memory: validation and the
+// evidence fold read them on the host.
+struct Mirror {
+  std::vector<double> xy, dm;
+  std::vector<int32_t> rp, col;
+  std::vector<float> val;
+};
+
+hac_status mirror_inputs(hac_ctx* c, int32_t count, const hac_instance* insts, const hac_csr* csrs,
+                         std::vector<Mirror>& mir, std::vector<hac_instance>& hi,
+                         std::vector<hac_csr>& hc) {
+  mir.resize(count);
+  hi.assign(insts, insts + count);
+  hc.assign(csrs, csrs + count);
+  for (int32_t x = 0; x < count; ++x) {
+    const int32_t n = insts[x].n;
+    if (n < 1 || n > HAC_MAX_N || csrs[x].n != n || csrs[x].nnz < 0 || !csrs[x].row_ptr)
+      return set_err(c, HAC_EINVAL, "instance " + std::to_string(x) + ": bad sizes");
+    Mirror& m = mir[x];
+    if (insts[x].kind == HAC_COORDS_EUC2D) {
+      if (!insts[x].coords) return set_err(c, HAC_EINVAL, "coords missing");
+      m.xy.resize(2 * (size_t)n);
+      CTX_HIP(hipMemcpyAsync(m.xy.data(), insts[x].coords, 16 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+      hi[x].coords = m.xy.data();
+    } else {
+      if (!insts[x].dist) return set_err(c, HAC_EINVAL, "distance matrix missing");
+      m.dm.resize((size_t)n * n);
+      CTX_HIP(hipMemcpyAsync(m.dm.data(), insts[x].dist, 8 * (size_t)n * n, hipMemcpyDeviceToHost, c->stream));
+      hi[x].dist = m.dm.data();
+    }
+    m.rp.resize(n + 1);
+    m.col.resize(std::max(csrs[x].nnz, 1));
+    m.val.resize(std::max(csrs[x].nnz, 1));
+    CTX_HIP(hipMemcpyAsync(m.rp.data(), csrs[x].row_ptr, 4 * (size_t)(n + 1), hipMemcpyDeviceToHost, c->stream));
+    if (csrs[x].nnz > 0) {
+      if (!csrs[x].col || !csrs[x].val) return set_err(c, HAC_EINVAL, "col/val missing");
+      CTX_HIP(hipMemcpyAsync(m.col.data(), csrs[x].col, 4 * (size_t)csrs[x].nnz, hipMemcpyDeviceToHost, c->stream));
+      CTX_HIP(hipMemcpyAsync(m.val.data(), csrs[x].val, 4 * (size_t)csrs[x].nnz, hipMemcpyDeviceToHost, c->stream));
+    }
+    hc[x].row_ptr = m.rp.data();
+    hc[x].col = m.col.data();
+    hc[x].val = m.val.data();
+  }
+  CTX_HIP(hipStreamSynchronize(c->stream));
+  return HAC_OK;
+}
+
+hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, const hac_csr* csrs_in,
+                     const hac_params* params, const uint64_t* seeds, int32_t* const* tours_out,
+                     double* lengths_out, bool outputs_on_device, bool inputs_on_device) {
+  const auto t0 = Clock::now();
+  c->err.clear();
+  c->stats = hac_stats{};
+  if (count < 1 || !insts_in || !csrs_in || !params || !seeds || !tours_out || !lengths_out)
+    return set_err(c, HAC_EINVAL, "null or empty batch");
+  std::vector<Mirror> mir;
+  std::vector<hac_instance> hi;
+  std::vector<hac_csr> hc;
+  if (inputs_on_device) {
+    CTX_HIP(hipSetDevice(c->device));
+    hac_status ms = mirror_inputs(c, count, insts_in, csrs_in, mir, hi, hc);
+    if (ms != HAC_OK) return ms;
+  }
+  const hac_instance* insts = inputs_on_device ? hi.data() : insts_in;
+  const hac_csr* csrs = inputs_on_device ? hc.data() : csrs_in;
+  for (int32_t x = 0; x < count; ++x) {
+    std::string why;
+    hac_status s = validate(&insts[x], &csrs[x], &params[x], &why);
+    if (s != HAC_OK) return set_err(c, s, "instance " + std::to_string(x) + ": " + why);
+    if (!tours_out[x]) return set_err(c, HAC_EINVAL, "null tour output");
+  }
+  CTX_HIP(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+
+  // trivial instances (n = 1) need no search
+  std::vector<HostInst> hs;
+  std::vector<int32_t> which;
+  for (int32_t x = 0; x < count; ++x) {
+    if (insts[x].n == 1) continue;
+    HostInst h{};
+    h.inst = insts[x];
+    h.csr = csrs[x];
+    h.p = params[x];
+    h.seed = seeds[x];
+    h.lay = make_layout(&insts[x], &csrs[x], &params[x]);
+    h.dstar = degree_target_of(&insts[x], &params[x]);
+    h.sym = (insts[x].kind == HAC_COORDS_EUC2D || insts[x].symmetric) ? 1 : 0;
+    h.p_x = fold_p_x(params[x].p_best, insts[x].n);
+    h.from_device = inputs_on_device;
+    if (inputs_on_device) {
+      h.dev_inst = insts_in[x];
+      h.dev_csr = csrs_in[x];
+    }
+    hs.push_back(h);
+    which.push_back(x);
+  }
+  const int32_t m = (int32_t)hs.size();
+  size_t total = align256(sizeof(InstDesc) * (size_t)std::max(m, 1)) +
+                 align256(sizeof(int32_t*) * (size_t)std::max(m, 1)) + align256(8 * (size_t)std::max(m, 1));
+  for (auto& h : hs) total += h.lay.bytes() + (outputs_on_device ? 0 : align256(4 * (size_t)h.lay.n));
+  if (c->budget && total > c->budget) return set_err(c, HAC_ENOMEM, "batch exceeds the context budget");
+  if (m > 0) {
+    hipError_t e = c->arena.reserve(total);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      return set_err(c, HAC_ENOMEM, "device memory");
+    CTX_HIP(e);
+  }
+  InstDesc* d_descs = m ? (InstDesc*)c->arena.carve(sizeof(InstDesc) * m) : nullptr;
+  int32_t** d_out_ptrs = m ? (int32_t**)c->arena.carve(sizeof(int32_t*) * m) : nullptr;
+  double* d_out_lens = m ? (double*)c->arena.carve(8 * (size_t)m) : nullptr;
+  std::vector<int32_t*> out_ptrs(m);
+  for (int32_t y = 0; y < m; ++y) {
+    HostInst& h = hs[y];
+    assign_slot(h, [&](size_t b) { return c->arena.carve(b); });
+    fill_desc_scalars(h);
+    out_ptrs[y] = outputs_on_device ? tours_out[which[y]] : (int32_t*)c->arena.carve(4 * (size_t)h.lay.n);
+    CTX_HIP(upload_inputs(h, s));
+  }
+  if (m > 0) {
+    std::vector<InstDesc> descs(m);
+    for (int32_t y = 0; y < m; ++y) descs[y] = hs[y].d;
+    CTX_HIP(hipMemcpyAsync(d_descs, descs.data(), sizeof(InstDesc) * m, hipMemcpyHostToDevice, s));
+    CTX_HIP(hipMemcpyAsync(d_out_ptrs, out_ptrs.data(), sizeof(int32_t*) * m, hipMemcpyHostToDevice, s));
+    std::string err;
+    hac_status ps = prepare_instances(hs, d_descs, s, &err);
+    if (ps != HAC_OK) return set_err(c, ps, err);
+  }
+  const double prep_ms = ms_since(t0);
+  const auto t1 = Clock::now();
+
+  double construct_ms = 0.0;
+  int64_t launches = 0;
+  if (m > 0) {
+    bool any_ls = false;
+    int32_t max_iter = 0, max_n = 0;
+    for (auto& h : hs) {
+      any_ls |= h.p.local_search != 0;
+      max_iter = std::max(max_iter, h.p.iterations);
+      max_n = std::max(max_n, h.lay.n);
+    }
+    LaunchShape shape{1, 0};
+    if (max_iter > 0) {
+      bool ok = true;
+      shape = tune_shape(hs, d_descs, s, c->scratch, &ok);
+      if (!ok) return set_err(c, HAC_EDEVICE, "autotuner launch failed");
+      CTX_HIP(launch_init(d_descs, m, s));  // undo the tuner's fallback counts
+    }
+    std::vector<BlockMap> map = build_block_map(hs, shape.ants_per_block);
+    c->scratch.reset();
+    CTX_HIP(c->scratch.reserve(map.size() * sizeof(BlockMap)));
+    BlockMap* d_map = (BlockMap*)c->scratch.carve(map.size() * sizeof(BlockMap));
+    CTX_HIP(hipMemcpyAsync(d_map, map.data(), map.size() * sizeof(BlockMap), hipMemcpyHostToDevice, s));
+    const size_t lds = shape_lds(hs, shape);
+    const int32_t blocks = (int32_t)map.size();
+    auto one_iteration = [&]() -> hipError_t {
+      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, lds, s);
+      if (e != hipSuccess) return e;
+      if (any_ls) {
+        e = launch_local_search(d_descs, m, max_n, s);
+        if (e != hipSuccess) return e;
+      }
+      return launch_iter_end(d_descs, m, s);
+    };
+    if (c->timing) {
+      // per-iteration launches with HIP events around each construction
+      while ((int)c->events.size() < 2 * max_iter) {
+        hipEvent_t e;
+        CTX_HIP(hipEventCreate(&e));
+        c->events.push_back(e);
+      }
+      for (int32_t it = 0; it < max_iter; ++it) {
+        CTX_HIP(hipEventRecord(c->events[2 * it], s));
+        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, lds, s));
+        CTX_HIP(hipEventRecord(c->events[2 * it + 1], s));
+        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, s));
+        CTX_HIP(launch_iter_end(d_descs, m, s));
+      }
+      CTX_HIP(hipStreamSynchronize(s));
+      for (int32_t it = 0; it < max_iter; ++it) {
+        float ms = 0;
+        CTX_HIP(hipEventElapsedTime(&ms, c->events[2 * it], c->events[2 * it + 1]));
+        construct_ms += ms;
+      }
+      launches = max_iter;
+    } else if (max_iter > 0) {
+      // a graph of G iterations replayed; surplus iterations are no-ops
+      const int32_t G = std::min<int32_t>(max_iter, 16);
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      CTX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = hipSuccess;
+      for (int32_t g = 0; g < G && ce == hipSuccess; ++g) ce = one_iteration();
+      hipError_t ee = hipStreamEndCapture(s, &graph);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return set_err(c, HAC_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+      }
+      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) return set_err(c, HAC_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+      const int32_t reps = (max_iter + G - 1) / G;
+      hipError_t le = hipSuccess;
+      for (int32_t r = 0; r < reps && le == hipSuccess; ++r) le = hipGraphLaunch(exec, s);
+      hipError_t se = hipStreamSynchronize(s);
+      (void)hipGraphExecDestroy(exec);
+      if (le != hipSuccess || se != hipSuccess)
+        return set_err(c, HAC_EDEVICE, std::string("graph replay: ") + hipGetErrorString(le != hipSuccess ? le : se));
+      launches = (int64_t)reps * G;
+    }
+    CTX_HIP(launch_finish(d_descs, m, d_out_ptrs, d_out_lens, s));
+  }
+  // results
+  std::vector<double> lens(m);
+  std::vector<State> sts(m);
+  if (m > 0) {
+    CTX_HIP(hipMemcpyAsync(lens.data(), d_out_lens, 8 * (size_t)m, hipMemcpyDeviceToHost, s));
+    for (int32_t y = 0; y < m; ++y)
+      CTX_HIP(hipMemcpyAsync(&sts[y], hs[y].d.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    if (!outputs_on_device)
+      for (int32_t y = 0; y < m; ++y)
+        CTX_HIP(hipMemcpyAsync(tours_out[which[y]], out_ptrs[y], 4 * (size_t)hs[y].lay.n,
+                               hipMemcpyDeviceToHost, s));
+    CTX_HIP(hipStreamSynchronize(s));
+  }
+  for (int32_t x = 0, y = 0; x < count; ++x) {
+    if (insts[x].n == 1) {
+      if (outputs_on_device) {
+        const int32_t zero = 0;
+        const double zl = 0.0;
+        CTX_HIP(hipMemcpy(tours_out[x], &zero, 4, hipMemcpyHostToDevice));
+        CTX_HIP(hipMemcpy(&lengths_out[x], &zl, 8, hipMemcpyHostToDevice));
+      } else {
+        tours_out[x][0] = 0;
+        lengths_out[x] = 0.0;
+      }
+      continue;
+    }
+    if (outputs_on_device)
+      CTX_HIP(hipMemcpy(&lengths_out[x], &lens[y], 8, hipMemcpyHostToDevice));
+    else
+      lengths_out[x] = lens[y];
+    ++y;
+  }
+  hac_stats& st = c->stats;
+  st.instances = count;
+  st.prep_ms = prep_ms;
+  st.search_ms = ms_since(t1);
+  st.total_ms = ms_since(t0);
+  st.construct_ms = construct_ms;
+  st.construct_launches = launches;
+  for (int32_t y = 0; y < m; ++y) {
+    st.ant_steps += (int64_t)hs[y].p.ants * (hs[y].lay.n - 1) * hs[y].p.iterations;
+    st.fallback_steps += (int64_t)sts[y].fallbacks;
+    st.restarts += sts[y].restarts;
+  }
+  if (m > 0) {
+    st.kappa = hs[0].fold.kappa;
+    st.q90 = hs[0].fold.q90;
+    st.r_hat = hs[0].fold.r_hat;
+    st.l_nn = hs[0].l_nn;
+  }
+  c->last = hs;
+  for (auto& h : c->last) h.cand_h.clear();
+  return HAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hac_status hac_decode(hac_ctx* c, const hac_instance* inst, const hac_csr* heat, const hac_params* p,
+                      uint64_t seed, int32_t* tour_out, double* length_out) {
+  if (!c) return HAC_EINVAL;
+  int32_t* tours[1] = {tour_out};
+  return run_batch(c, 1, inst, heat, p, &seed, tours, length_out, false, false);
+}
+
+hac_status hac_decode_batch(hac_ctx* c, int32_t count, const hac_instance* insts, const hac_csr* heats,
+                            const hac_params* params, const uint64_t* seeds, int32_t* const* tours_out,
+                            double* lengths_out) {
+  if (!c) return HAC_EINVAL;
+  return run_batch(c, count, insts, heats, params, seeds, tours_out, lengths_out, false, false);
+}
+
+hac_status hac_decode_batch_dev(hac_ctx* c, int32_t count, const hac_instance* insts_dev,
+                                const hac_csr* heats_dev, const hac_params* params, const uint64_t* seeds,
+                                int32_t* const* tours_out_dev, double* lengths_out_dev) {
+  if (!c) return HAC_EINVAL;
+  return run_batch(c, count, insts_dev, heats_dev, params, seeds, tours_out_dev, lengths_out_dev, true,
+                   true);
+}
+
+hac_status hac_decode_dev(hac_ctx* c, const hac_instance* inst_dev, const hac_csr* heat_dev,
+                          const hac_params* p, uint64_t seed, int32_t* tour_out_dev,
+                          double* length_out_dev) {
+  if (!c) return HAC_EINVAL;
+  int32_t* tours[1] = {tour_out_dev};
+  return run_batch(c, 1, inst_dev, heat_dev, p, &seed, tours, length_out_dev, true, true);
+}
+
+hac_status hac_debug_state(hac_ctx* c, int32_t which, int32_t* cand, float* heur, float* tau,
+                           float* weight, int32_t* ant_tours, double* ant_len, int32_t* nn_tour) {
+  if (!c || which < 0 || which >= (int32_t)c->last.size()) return HAC_EINVAL;
+  const HostInst& h = c->last[which];
+  const size_t nn = (size_t)h.lay.n, nk = nn * h.lay.k;
+  hipStream_t s = c->stream;
+  if (cand) CTX_HIP(hipMemcpyAsync(cand, h.d.cand, 4 * nk, hipMemcpyDeviceToHost, s));
+  if (heur) CTX_HIP(hipMemcpyAsync(heur, h.d.heur, 4 * nk, hipMemcpyDeviceToHost, s));
+  if (tau) CTX_HIP(hipMemcpyAsync(tau, h.d.tau, 4 * nk, hipMemcpyDeviceToHost, s));
+  if (weight) CTX_HIP(hipMemcpyAsync(weight, h.d.w, 4 * nk, hipMemcpyDeviceToHost, s));
+  if (ant_tours) CTX_HIP(hipMemcpyAsync(ant_tours, h.d.tours, 4 * nn * h.p.ants, hipMemcpyDeviceToHost, s));
+  if (ant_len) CTX_HIP(hipMemcpyAsync(ant_len, h.d.lens, 8 * (size_t)h.p.ants, hipMemcpyDeviceToHost, s));
+  if (nn_tour) CTX_HIP(hipMemcpyAsync(nn_tour, h.d.nn_tour, 4 * nn, hipMemcpyDeviceToHost, s));
+  CTX_HIP(hipStreamSynchronize(s));
+  return HAC_OK;
+}
+
+hac_status hac_debug_trace(hac_ctx* c, int32_t which, double* l_ib, double* l_gb, int32_t* elite_rb) {
+  if (!c || which < 0 || which >= (int32_t)c->last.size()) return HAC_EINVAL;
+  const HostInst& h = c->last[which];
+  const size_t it = (size_t)h.p.iterations;
+  hipStream_t s = c->stream;
+  if (it == 0) return HAC_OK;
+  if (l_ib) CTX_HIP(hipMemcpyAsync(l_ib, h.d.tr_lib, 8 * it, hipMemcpyDeviceToHost, s));
+  if (l_gb) CTX_HIP(hipMemcpyAsync(l_gb, h.d.tr_lgb, 8 * it, hipMemcpyDeviceToHost, s));
+  if (elite_rb) CTX_HIP(hipMemcpyAsync(elite_rb, h.d.tr_elite, 4 * it, hipMemcpyDeviceToHost, s));
+  CTX_HIP(hipStreamSynchronize(s));
+  return HAC_OK;
+}
+
+}  // extern "C"

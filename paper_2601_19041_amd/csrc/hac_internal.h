@@ -1,0 +1,86 @@
+// Internal declarations shared by the host runtime (hac_api.cpp,
+// hac_fold.cpp, hac_server.cpp) and the HIP kernels (hac_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hac {
+
+// Device-resident search state of one instance (Alg. 1 bookkeeping).
+struct State {
+  int32_t t;         // next iteration to run, 1-based
+  int32_t stall;     // iterations without restart-best improvement
+  int32_t ugb;       // current u_gb
+  int32_t rb_valid;  // restart-best tour exists
+  int32_t restarts;
+  int32_t ib;        // ant index of the last iteration best
+  double l_gb, l_rb, l_ib;
+  double tmax, tmin;    // FP64 bounds (eq. 5-6)
+  float tmax_f, tmin_f; // their FP32 casts, used by the update
+  double min_gain;              // 2-opt gain threshold, 1e-9 L_nn / n
+  unsigned long long fallbacks;  // nearest-unvisited steps so far
+};
+
+// Everything a kernel needs to know about one instance.  Pointers are
+// device pointers into the instance's slot.
+struct InstDesc {
+  int32_t n, k, kg, kls;      // k = candidates per node, kg = geometric list
+  int32_t kind, sym, dstar;
+  int32_t ants, iterations, local_search;
+  int32_t bf_period, restart_stall, ugb_max;
+  uint32_t seed_lo, seed_hi;
+  double rho, p_x, xi_bf, lambda_bf, min_gain;
+  float keep_f;               // (float)(1 - rho)
+  double theta_h;
+  const double* xy;           // [n][2] or null
+  const double* dist;         // [n][n] or null
+  const int32_t* row_ptr;     // heatmap CSR
+  const int32_t* col;
+  const float* val;
+  int32_t* cand;              // [n][k]
+  const uint16_t* cand16;     // [n][k] (n <= 65535) for LDS staging, or null
+  const float* heur;          // [n][k]  S = eta^beta e^kappa
+  float* tau;                 // [n][k]
+  float* w;                   // [n][k]  tau * S
+  int32_t* geo;               // [n][kg] geometric nearest neighbours
+  int32_t* tours;             // [ants][n]
+  double* lens;               // [ants]
+  int32_t* t_gb;              // [n]
+  int32_t* t_rb;              // [n]
+  int32_t* t_ib;              // [n] local-search copy of the iteration best
+  int32_t* nn_tour;           // [n]
+  int32_t* succ;              // [n]
+  int32_t* pred;              // [n]
+  int32_t* ls_work;           // [3n] pos, queue, in-queue for 2-opt
+  State* st;
+  double* tr_lib;             // [iterations] or null
+  double* tr_lgb;             // [iterations] or null
+  int32_t* tr_elite;          // [iterations] or null
+};
+
+// One entry per construction block: instance and first ant (inst < 0: idle)
+struct BlockMap {
+  int32_t inst;
+  int32_t ant0;
+};
+
+// ---- launchers (defined in hac_kernels.hip) ----
+hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s);
+hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
+hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
+hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
+hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
+                            int32_t ants_per_block, int32_t staged, size_t lds_bytes,
+                            hipStream_t s);
+hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
+                               hipStream_t s);
+hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s);
+hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const* d_out_tours,
+                         double* d_out_lens, hipStream_t s);
+
+// LDS the construction kernel needs for one block
+size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t staged);
+int32_t max_lds_bytes();
+
+}  // namespace hac

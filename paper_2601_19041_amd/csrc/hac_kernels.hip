@@ -1,0 +1,951 @@
+// HIP kernels of the heatmap-guided MMAS decoder, written for gfx950
+// (CDNA4, 64-lane wavefronts).
+//
+// Layout conventions (per instance, all row-major):
+//   cand  int32[n][k]   candidate list of node i (eq. 3), ascending (distance, index)
+//   heur  f32  [n][k]   S = eta^beta e^kappa (folded on the host)
+//   tau   f32  [n][k]   pheromone on candidate edges only
+//   w     f32  [n][k]   choice weights tau * S (rewritten by every update)
+//   geo   int32[n][kg]  geometric nearest neighbours, kg = min(n-1, 32)
+//
+// Numerical contract: this file is compiled with -ffp-contract=off and
+// without fast-math, so every FP32/FP64 expression rounds exactly as
+// written.  The only FP64 library routine used is sqrt, which the gfx950
+// lowering computes with a correctly rounded final residual step.
+// Selection is integer arithmetic on the bits of the FP32 weights.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hac_internal.h"
+
+namespace hac {
+
+static constexpr int WAVE = 64;
+
+// ------------------------------------------------------------------------
+// wave primitives
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+__device__ __forceinline__ int rd_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ double rd_lane_d(double v, int l) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ uint64_t rd_lane_u64(uint64_t v, int l) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int CTRL, int ROWM>
+__device__ __forceinline__ uint32_t dpp_or0(uint32_t x) {
+  // lanes whose source is outside the row (or in a masked row) read 0
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWM, 0xf, false);
+}
+
+// Inclusive prefix sum over the 64 lanes (Hillis-Steele inside each
+// 16-lane row, then row broadcasts).  Must run with all lanes active.
+__device__ __forceinline__ uint64_t wave_scan_u64(uint64_t v) {
+#define HAC_SCAN_STEP(C, R)                                                        \
+  {                                                                               \
+    uint32_t lo_ = (uint32_t)v, hi_ = (uint32_t)(v >> 32);                        \
+    v += ((uint64_t)dpp_or0<C, R>(hi_) << 32) | (uint64_t)dpp_or0<C, R>(lo_);     \
+  }
+  HAC_SCAN_STEP(0x111, 0xf)
+  HAC_SCAN_STEP(0x112, 0xf)
+  HAC_SCAN_STEP(0x114, 0xf)
+  HAC_SCAN_STEP(0x118, 0xf)
+  HAC_SCAN_STEP(0x142, 0xa)
+  HAC_SCAN_STEP(0x143, 0xc)
+#undef HAC_SCAN_STEP
+  return v;
+}
+
+// Maximum over the 64 lanes, returned to every lane.  All lanes active.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, dpp_or0<0x111, 0xf>(v));
+  v = max(v, dpp_or0<0x112, 0xf>(v));
+  v = max(v, dpp_or0<0x114, 0xf>(v));
+  v = max(v, dpp_or0<0x118, 0xf>(v));
+  v = max(v, dpp_or0<0x142, 0xa>(v));
+  v = max(v, dpp_or0<0x143, 0xc>(v));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ bool key_less(double ka, int ia, double kb, int ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+// Lexicographic (key, index) minimum over the wave, returned to all lanes.
+__device__ __forceinline__ void wave_argmin(double& key, int& idx) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    double ok = __shfl_xor(key, off);
+    int oi = __shfl_xor(idx, off);
+    if (key_less(ok, oi, key, idx)) {
+      key = ok;
+      idx = oi;
+    }
+  }
+  key = rd_lane_d(key, 0);
+  idx = rd_lane(idx, 0);
+}
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): two 32x32 multiplies
+// per round, key bumped by the golden-ratio Weyl constants.  Returns the
+// first two output words as one 64-bit uniform.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t philox_u64(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
+    uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return ((uint64_t)c1 << 32) | c0;
+}
+
+// ------------------------------------------------------------------------
+// distances
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double order_key(const InstDesc& D, int i, int j) {
+  if (D.xy) {
+    double dx = D.xy[2 * i] - D.xy[2 * j];
+    double dy = D.xy[2 * i + 1] - D.xy[2 * j + 1];
+    return dx * dx + dy * dy;
+  }
+  return D.dist[(int64_t)i * D.n + j];
+}
+
+__device__ __forceinline__ double edge_len(const InstDesc& D, int i, int j) {
+  if (D.xy) return sqrt(order_key(D, i, j));
+  return D.dist[(int64_t)i * D.n + j];
+}
+
+// Sum of the n edges of a tour in array order, closing edge last (eq. 1).
+// Lanes compute 64 edges at a time; the additions are sequential.
+__device__ double tour_length_wave(const InstDesc& D, const int32_t* tour) {
+  const int n = D.n, lane = lane_id();
+  double len = 0.0;
+  for (int b0 = 0; b0 < n; b0 += WAVE) {
+    int s = b0 + lane;
+    double d = 0.0;
+    if (s >= 1 && s < n) d = edge_len(D, tour[s - 1], tour[s]);
+    int last = min(WAVE, n - b0);
+    for (int l = (b0 == 0 ? 1 : 0); l < last; ++l) len += rd_lane_d(d, l);
+  }
+  len += edge_len(D, tour[n - 1], tour[0]);
+  return len;
+}
+
+// Nearest unvisited node to i by (key, index).  `vis` is the wave's LDS
+// bitset (bits >= n set).  The geometric list holds the kg nearest nodes in
+// that order, so its first unvisited entry, if any, is the answer;
+// otherwise every node is scanned.
+__device__ int nearest_unvisited(const InstDesc& D, int i, const uint32_t* vis) {
+  const int lane = lane_id(), n = D.n, kg = D.kg;
+  int g = 0;
+  bool open = false;
+  if (lane < kg) {
+    g = D.geo[(int64_t)i * kg + lane];
+    open = !((vis[g >> 5] >> (g & 31)) & 1u);
+  }
+  uint64_t m = __ballot(open);
+  if (m) return rd_lane(g, __ffsll((unsigned long long)m) - 1);
+  double bk = __builtin_huge_val();
+  int bj = 0x7fffffff;
+  for (int b0 = 0; b0 < n; b0 += WAVE) {
+    uint32_t w0 = vis[b0 >> 5], w1 = vis[(b0 >> 5) + 1];
+    if ((w0 & w1) == 0xffffffffu) continue;
+    uint32_t word = lane < 32 ? w0 : w1;
+    int j = b0 + lane;
+    if (!((word >> (lane & 31)) & 1u)) {
+      double kj = order_key(D, i, j);
+      if (kj < bk) {
+        bk = kj;
+        bj = j;
+      }
+    }
+  }
+  wave_argmin(bk, bj);
+  return bj < n ? bj : n - 1;  // always a node index, even on a broken bitset
+}
+
+// ------------------------------------------------------------------------
+// Candidate lists (eq. 3) and geometric neighbour lists.
+// One wave per row.  The k nearest heatmap-supported nodes, or all of them
+// plus the nearest unsupported ones; the final list is in ascending
+// (key, index) order.  Top-K lists live in lanes 0..K-1, kept sorted.
+// ------------------------------------------------------------------------
+struct WaveTopK {
+  double key;
+  int id;
+  int cnt;
+  int K;
+};
+
+__device__ __forceinline__ void topk_init(WaveTopK& t, int K) {
+  t.key = __builtin_huge_val();
+  t.id = 0x7fffffff;
+  t.cnt = 0;
+  t.K = K;
+}
+
+__device__ void topk_offer(WaveTopK& t, double key, int id, bool valid) {
+  const int lane = lane_id();
+  double tk = __builtin_huge_val();
+  int ti = 0x7fffffff;
+  if (t.cnt == t.K) {
+    tk = rd_lane_d(t.key, t.K - 1);
+    ti = rd_lane(t.id, t.K - 1);
+  }
+  uint64_t m = __ballot(valid && key_less(key, id, tk, ti));
+  while (m) {
+    int l = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    double nk = rd_lane_d(key, l);
+    int ni = rd_lane(id, l);
+    if (t.cnt == t.K) {
+      tk = rd_lane_d(t.key, t.K - 1);
+      ti = rd_lane(t.id, t.K - 1);
+      if (!key_less(nk, ni, tk, ti)) continue;
+    }
+    int rank = __popcll(__ballot(lane < t.cnt && key_less(t.key, t.id, nk, ni)));
+    double pk = __shfl_up(t.key, 1);
+    int pi = __shfl_up(t.id, 1);
+    if (lane > rank) {
+      t.key = pk;
+      t.id = pi;
+    } else if (lane == rank) {
+      t.key = nk;
+      t.id = ni;
+    }
+    if (t.cnt < t.K) t.cnt++;
+  }
+}
+
+__global__ void __launch_bounds__(256) candidates_kernel(const InstDesc* insts, int inst) {
+  const InstDesc& D = insts[inst];
+  const int n = D.n, k = D.k, kg = D.kg, lane = lane_id();
+  const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+  if (i >= n) return;
+  // heatmap-supported members of row i, nearest k of them
+  WaveTopK sup;
+  topk_init(sup, k);
+  const int e_beg = D.row_ptr[i], e_end = D.row_ptr[i + 1];
+  for (int e0 = e_beg; e0 < e_end; e0 += WAVE) {
+    int e = e0 + lane;
+    bool mem = false;
+    int j = 0;
+    double key = 0.0;
+    if (e < e_end) {
+      j = D.col[e];
+      mem = j != i && (double)D.val[e] > D.theta_h;
+      if (mem) key = order_key(D, i, j);
+    }
+    topk_offer(sup, key, j, mem);
+  }
+  const int s = sup.cnt;  // = min(|P_i|, k)
+  const int need = k - s;
+  // one pass over all nodes: geometric list, and fill when needed
+  WaveTopK geo, fill;
+  topk_init(geo, kg);
+  topk_init(fill, k);
+  for (int j0 = 0; j0 < n; j0 += WAVE) {
+    int j = j0 + lane;
+    bool valid = j < n && j != i;
+    double key = valid ? order_key(D, i, j) : 0.0;
+    topk_offer(geo, key, j, valid);
+    if (need > 0) {
+      // |P_i| < k here, so every member of P_i is in `sup`
+      bool member = false;
+      for (int q = 0; q < s; ++q) member |= (j == rd_lane(sup.id, q));
+      topk_offer(fill, key, j, valid && !member);
+    }
+  }
+  // merge sup[0..s) and fill[0..need) by (key, index): each entry's
+  // place is its index plus the number of smaller entries of the other list
+  int rank_s = lane, rank_f = lane;
+  for (int b = 0; b < need; ++b)
+    if (key_less(rd_lane_d(fill.key, b), rd_lane(fill.id, b), sup.key, sup.id)) rank_s++;
+  for (int a = 0; a < s; ++a)
+    if (key_less(rd_lane_d(sup.key, a), rd_lane(sup.id, a), fill.key, fill.id)) rank_f++;
+  int32_t* out = D.cand + (int64_t)i * k;
+  if (lane < s) out[rank_s] = sup.id;
+  if (lane < need) out[rank_f] = fill.id;
+  if (lane < kg) D.geo[(int64_t)i * kg + lane] = geo.id;
+}
+
+// ------------------------------------------------------------------------
+// Nearest-neighbour tour from node 0 (one wave per instance).  Writes the
+// tour and, in the state, its length and the 2-opt gain threshold.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) nn_tour_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.x];
+  extern __shared__ uint32_t vis[];
+  const int n = D.n, lane = lane_id();
+  const int words2 = ((n + 63) >> 6) << 1;
+  for (int w = lane; w < words2; w += WAVE) {
+    int lo = w * 32;
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b)
+      if (lo + b >= n) v |= 1u << b;
+    vis[w] = v;
+  }
+  __syncthreads();
+  int32_t* tour = D.nn_tour;
+  int cur = 0;
+  if (lane == 0) {
+    tour[0] = 0;
+    vis[0] |= 1u;
+  }
+  __syncthreads();
+  for (int s = 1; s < n; ++s) {
+    int j = nearest_unvisited(D, cur, vis);
+    if (lane == 0) {
+      tour[s] = j;
+      vis[j >> 5] |= 1u << (j & 31);
+    }
+    __syncthreads();
+    cur = j;
+  }
+  __threadfence_block();
+  double len = tour_length_wave(D, tour);
+  if (lane == 0) {
+    D.st->l_gb = len;
+    D.st->l_ib = len;
+    D.st->min_gain = 1e-9 * len / (double)n;
+  }
+}
+
+// ------------------------------------------------------------------------
+// First-improvement 2-opt over the geometric lists with a FIFO don't-look
+// queue (Section III-D).  One wave.  Candidate moves of node a are
+// evaluated in parallel (lanes 0..31: succ direction, 32..63: pred), and
+// the first improving one in (direction, list position) order is applied,
+// exactly as a sequential scan would find it.  tour/pos may live in LDS or
+// global memory; the queue and in-queue flags are touched by lane 0 only.
+// ------------------------------------------------------------------------
+__device__ void reverse_path_wave(int n, int32_t* tour, int32_t* pos, int x, int y) {
+  const int lane = lane_id();
+  int i = pos[x], j = pos[y];
+  int len = ((j - i + n) % n) + 1;
+  if (2 * len > n) {
+    int ni = (j + 1) % n, nj = (i - 1 + n) % n;
+    i = ni;
+    j = nj;
+    len = n - len;
+  }
+  const int half = len / 2;
+  for (int s = lane; s < half; s += WAVE) {
+    int pi = (i + s) % n;
+    int pj = (j - s + n) % n;
+    int ti = tour[pi], tj = tour[pj];
+    tour[pi] = tj;
+    tour[pj] = ti;
+    pos[tj] = pi;
+    pos[ti] = pj;
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ void two_opt_wave(const InstDesc& D, int32_t* tour, int32_t* pos, int32_t* queue,
+                             int32_t* inq, double min_gain) {
+  const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id();
+  if (n < 5 || kls < 1) return;
+  for (int s = lane; s < n; s += WAVE) {
+    int v = tour[s];
+    pos[v] = s;
+    queue[s] = v;
+    inq[v] = 1;
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  int head = 0, count = n;
+  const bool pred_dir = lane >= 32;
+  const int q = lane & 31;
+  const bool in_list = q < kls;
+  while (count > 0) {
+    int a = 0;
+    if (lane == 0) {
+      a = queue[head];
+      inq[a] = 0;
+    }
+    a = rd_lane(a, 0);
+    head = head + 1 == n ? 0 : head + 1;
+    count--;
+    for (;;) {
+      int pa = pos[a];
+      int b = pred_dir ? tour[pa == 0 ? n - 1 : pa - 1] : tour[pa + 1 == n ? 0 : pa + 1];
+      double dab = edge_len(D, a, b);
+      int c = in_list ? D.geo[(int64_t)a * kg + q] : a;
+      double dac = in_list ? edge_len(D, a, c) : 0.0;
+      double g1 = dab - dac;
+      // a direction stops at the first list entry that cannot gain
+      uint64_t stop = __ballot(in_list && !(g1 > 0.0));
+      uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
+      int lim_s = stop_s ? __ffsll((unsigned long long)stop_s) - 1 : 32;
+      int lim_p = stop_p ? __ffsll((unsigned long long)stop_p) - 1 : 32;
+      bool ok = in_list && q < (pred_dir ? lim_p : lim_s);
+      int e = 0;
+      bool imp = false;
+      if (ok) {
+        int pc = pos[c];
+        e = pred_dir ? tour[pc == 0 ? n - 1 : pc - 1] : tour[pc + 1 == n ? 0 : pc + 1];
+        if (e != a && c != b) {
+          double gain = (dab + edge_len(D, c, e)) - (dac + edge_len(D, b, e));
+          imp = gain > min_gain;
+        }
+      }
+      uint64_t mi = __ballot(imp);
+      if (!mi) break;
+      int l = __ffsll((unsigned long long)mi) - 1;
+      int bb = rd_lane(b, l), cc = rd_lane(c, l), ee = rd_lane(e, l);
+      if (l < 32)
+        reverse_path_wave(n, tour, pos, bb, cc);
+      else
+        reverse_path_wave(n, tour, pos, cc, bb);
+      if (lane == 0) {
+        int ends[4] = {a, bb, cc, ee};
+        for (int z = 0; z < 4; ++z) {
+          int x = ends[z];
+          if (!inq[x]) {
+            int slot = head + count;
+            if (slot >= n) slot -= n;
+            queue[slot] = x;
+            count++;
+            inq[x] = 1;
+          }
+        }
+      }
+      count = rd_lane(count, 0);
+    }
+  }
+}
+
+// 2-opt of the NN tour (preparation, local search enabled).  One wave per
+// instance; working arrays in LDS when they fit.
+__global__ void __launch_bounds__(64) two_opt_nn_kernel(const InstDesc* insts, int use_lds) {
+  const InstDesc& D = insts[blockIdx.x];
+  if (!D.local_search) return;
+  extern __shared__ int32_t ls_lds[];
+  const int n = D.n;
+  int32_t* pos = use_lds ? ls_lds : D.ls_work;
+  int32_t* queue = pos + n;
+  int32_t* inq = queue + n;
+  two_opt_wave(D, D.nn_tour, pos, queue, inq, D.st->min_gain);
+  __threadfence_block();
+  double len = tour_length_wave(D, D.nn_tour);
+  if (lane_id() == 0) {
+    D.st->l_gb = len;
+    D.st->l_ib = len;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Bounds and pheromone initialisation (eq. 5-6): tau <- tau_max.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void bounds_from_length(const InstDesc& D, double len, double& tmax,
+                                                   double& tmin) {
+  tmax = 1.0 / (D.rho * len);
+  if (D.local_search)
+    tmin = tmax / (2.0 * (double)D.n);
+  else
+    tmin = tmax * (1.0 - D.p_x) / (((double)(D.k - 1) / 2.0) * D.p_x);
+}
+
+__global__ void __launch_bounds__(256) init_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.x];
+  State* st = D.st;
+  __shared__ float s_tmax;
+  if (threadIdx.x == 0) {
+    double len = st->l_gb;
+    double tmax, tmin;
+    bounds_from_length(D, len, tmax, tmin);
+    st->tmax = tmax;
+    st->tmin = tmin;
+    st->tmax_f = (float)tmax;
+    st->tmin_f = (float)tmin;
+    st->t = 1;
+    st->stall = 0;
+    st->ugb = D.ugb_max;
+    st->rb_valid = 0;
+    st->restarts = 0;
+    st->ib = 0;
+    st->fallbacks = 0;
+    s_tmax = (float)tmax;
+  }
+  __syncthreads();
+  const float tm = s_tmax;
+  const int64_t nk = (int64_t)D.n * D.k;
+  for (int64_t x = threadIdx.x; x < nk; x += blockDim.x) {
+    D.tau[x] = tm;
+    D.w[x] = tm * D.heur[x];
+  }
+  for (int s = threadIdx.x; s < D.n; s += blockDim.x) D.t_gb[s] = D.nn_tour[s];
+}
+
+// ------------------------------------------------------------------------
+// Ant construction (Alg. 2, eq. 4).  One wavefront per ant; lane u holds
+// candidate slot u of the current node.  Per step:
+//   open slots  = candidates whose visited bit is clear (LDS bitset)
+//   E           = largest biased exponent of the open weights
+//   q_u         = max(1, floor(w_u 2^(31-E)))  by integer shifts of the
+//                 FP32 mantissa (exact)
+//   r           = floor(U * sum q / 2^64) for the step's 64-bit uniform U
+//   choice      = first open slot whose inclusive prefix sum exceeds r
+// and when no slot is open the nearest unvisited node.  The Philox blocks
+// for 64 consecutive steps are computed at once, one per lane; the tour is
+// buffered 64 steps per register and its length is summed in step order.
+// STAGED copies the instance's candidate ids (16 bit) and weights to LDS.
+// ------------------------------------------------------------------------
+template <bool STAGED>
+__global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* insts, const BlockMap* map,
+                                                         int ants_per_block) {
+  const BlockMap bm = map[blockIdx.x];
+  if (bm.inst < 0) return;
+  const InstDesc& D = insts[bm.inst];
+  const int t = D.st->t;
+  if (t > D.iterations) return;
+  extern __shared__ uint32_t lds[];
+  const int n = D.n, k = D.k, lane = lane_id(), wave = threadIdx.x / WAVE;
+  const int words2 = ((n + 63) >> 6) << 1;
+  const int vis_words = ((words2 + 3) >> 2) << 2;
+  uint32_t* vis = lds + wave * vis_words;
+  const uint16_t* c16 = nullptr;
+  const float* wl = nullptr;
+  if (STAGED) {
+    uint32_t* base = lds + ants_per_block * vis_words;
+    const int64_t nk = (int64_t)n * k;
+    const int c_vec = (int)((nk * 2 + 15) / 16);
+    const int w_vec = (int)((nk * 4 + 15) / 16);
+    uint4* dc = reinterpret_cast<uint4*>(base);
+    uint4* dw = reinterpret_cast<uint4*>(base + c_vec * 4);
+    const uint4* sc = reinterpret_cast<const uint4*>(D.cand16);
+    const uint4* sw = reinterpret_cast<const uint4*>(D.w);
+    for (int x = threadIdx.x; x < c_vec; x += blockDim.x) dc[x] = sc[x];
+    for (int x = threadIdx.x; x < w_vec; x += blockDim.x) dw[x] = sw[x];
+    c16 = reinterpret_cast<const uint16_t*>(dc);
+    wl = reinterpret_cast<const float*>(dw);
+    __syncthreads();
+  }
+  const int ant = bm.ant0 + wave;
+  if (ant >= D.ants) return;
+
+  for (int w = lane; w < vis_words; w += WAVE) {
+    int lo = w * 32;
+    uint32_t v = 0;
+    if (lo + 32 <= n)
+      v = 0;
+    else if (lo >= n)
+      v = 0xffffffffu;
+    else
+      v = ~((1u << (n - lo)) - 1u);
+    vis[w] = v;
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  const uint32_t k0 = D.seed_lo, k1 = D.seed_hi;
+  // uniforms for steps 0..63, one per lane
+  uint64_t rnd = philox_u64((uint32_t)lane, (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
+  int cur = (int)__umul64hi(rd_lane_u64(rnd, 0), (uint64_t)n);
+  const int start = cur;
+  if (lane == 0) vis[cur >> 5] |= 1u << (cur & 31);
+  int tb = cur;        // lane (s & 63) holds T[s] of the current 64-step block
+  int carry = cur;     // last node of the previous block
+  double len = 0.0;
+  uint32_t fallbacks = 0;
+  int32_t* my_tour = D.tours + (int64_t)ant * n;
+  const bool in_row = lane < k;
+
+  for (int s = 1; s < n; ++s) {
+    const int sl = s & 63;
+    if (sl == 0) rnd = philox_u64((uint32_t)(s + lane), (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
+    const int i = cur;
+    int c = 0;
+    uint32_t wb = 0;
+    if (in_row) {
+      const int64_t x = (int64_t)i * k + lane;
+      if (STAGED) {
+        c = c16[x];
+        wb = __float_as_uint(wl[x]);
+      } else {
+        c = D.cand[x];
+        wb = __float_as_uint(D.w[x]);
+      }
+    }
+    const bool open = in_row && !((vis[c >> 5] >> (c & 31)) & 1u);
+    const uint64_t om = __ballot(open);
+    int j;
+    if (om) {
+      const uint32_t be = open ? (wb >> 23) : 0u;
+      const uint32_t be_max = wave_max_u32(be);
+      const int sh = (int)be - (int)be_max + 8;
+      const uint32_t m24 = (wb & 0x7fffffu) | 0x800000u;
+      uint32_t qv = sh >= 0 ? (m24 << sh) : (sh > -32 ? (m24 >> (-sh)) : 0u);
+      qv = qv < 1u ? 1u : qv;
+      const uint64_t pre = wave_scan_u64(open ? (uint64_t)qv : 0ull);
+      const uint64_t tot = rd_lane_u64(pre, 63);
+      const uint64_t r = __umul64hi(rd_lane_u64(rnd, sl), tot);
+      const uint64_t sm = __ballot(open && pre > r);
+      j = rd_lane(c, __ffsll((unsigned long long)sm) - 1);
+    } else {
+      j = nearest_unvisited(D, i, vis);
+      fallbacks++;
+    }
+    if (lane == 0) vis[j >> 5] |= 1u << (j & 31);
+    if (lane == sl) tb = j;
+    if (sl == 63 || s == n - 1) {
+      const int b0 = s & ~63;
+      if (lane <= sl) my_tour[b0 + lane] = tb;
+      int prev = __shfl_up(tb, 1);
+      if (lane == 0) prev = carry;
+      double d = 0.0;
+      if (lane <= sl && b0 + lane >= 1) d = edge_len(D, prev, tb);
+      for (int l = (b0 == 0 ? 1 : 0); l <= sl; ++l) len += rd_lane_d(d, l);
+      carry = rd_lane(tb, sl);
+    }
+    cur = j;
+  }
+  len += edge_len(D, carry, start);
+  if (lane == 0) {
+    D.lens[ant] = len;
+    if (fallbacks) atomicAdd(&D.st->fallbacks, (unsigned long long)fallbacks);
+  }
+}
+
+// ------------------------------------------------------------------------
+// Local search on the iteration-best tour (one wave per instance).
+// ------------------------------------------------------------------------
+__device__ void iteration_best_wave(const InstDesc& D, int& ib, double& lib) {
+  const int lane = lane_id();
+  double bk = __builtin_huge_val();
+  int bi = 0x7fffffff;
+  for (int a = lane; a < D.ants; a += WAVE) {
+    double v = D.lens[a];
+    if (key_less(v, a, bk, bi)) {
+      bk = v;
+      bi = a;
+    }
+  }
+  wave_argmin(bk, bi);
+  ib = bi;
+  lib = bk;
+}
+
+__global__ void __launch_bounds__(64) local_search_kernel(const InstDesc* insts, int use_lds) {
+  const InstDesc& D = insts[blockIdx.x];
+  if (!D.local_search || D.st->t > D.iterations) return;
+  extern __shared__ int32_t ls_lds[];
+  const int n = D.n, lane = lane_id();
+  int ib;
+  double lib;
+  iteration_best_wave(D, ib, lib);
+  const int32_t* src = D.tours + (int64_t)ib * n;
+  for (int s = lane; s < n; s += WAVE) D.t_ib[s] = src[s];
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  int32_t* pos = use_lds ? ls_lds : D.ls_work;
+  int32_t* queue = pos + n;
+  int32_t* inq = queue + n;
+  two_opt_wave(D, D.t_ib, pos, queue, inq, D.st->min_gain);
+  __threadfence_block();
+  double len = tour_length_wave(D, D.t_ib);
+  if (lane == 0) {
+    D.st->ib = ib;
+    D.st->l_ib = len;
+  }
+}
+
+// ------------------------------------------------------------------------
+// End of an iteration (Alg. 1): iteration/restart/global best, bounds,
+// elite choice, fused evaporate + deposit + clamp + weights (eq. 7-8),
+// branching-factor restart, u_gb schedule.  One block per instance.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int ugb_tier(int stall, int ugb_max) {
+  if (stall < 25) return ugb_max;
+  if (stall < 75) return 5;
+  if (stall < 125) return 3;
+  if (stall < 250) return 2;
+  return 1;
+}
+
+__global__ void __launch_bounds__(1024) iter_end_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.x];
+  State* st = D.st;
+  const int t = st->t;
+  if (t > D.iterations) return;
+  const int n = D.n, k = D.k, tid = threadIdx.x, nthr = blockDim.x;
+  __shared__ double s_key[32];
+  __shared__ int s_idx[32];
+  __shared__ unsigned long long s_cnt[32];
+  __shared__ int s_ib, s_rb_upd, s_gb_upd, s_use_rb, s_restart;
+  __shared__ double s_lib, s_lel;
+  __shared__ float s_tmax, s_tmin;
+
+  // iteration best (first ant with the smallest length)
+  const int32_t* t_ib;
+  if (D.local_search) {
+    if (tid == 0) {
+      s_ib = st->ib;
+      s_lib = st->l_ib;
+    }
+    __syncthreads();
+    t_ib = D.t_ib;
+  } else {
+    double bk = __builtin_huge_val();
+    int bi = 0x7fffffff;
+    for (int a = tid; a < D.ants; a += nthr) {
+      double v = D.lens[a];
+      if (key_less(v, a, bk, bi)) {
+        bk = v;
+        bi = a;
+      }
+    }
+    wave_argmin(bk, bi);
+    if (lane_id() == 0) {
+      s_key[tid / WAVE] = bk;
+      s_idx[tid / WAVE] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double k0 = s_key[0];
+      int i0 = s_idx[0];
+      for (int w = 1; w < nthr / WAVE; ++w)
+        if (key_less(s_key[w], s_idx[w], k0, i0)) {
+          k0 = s_key[w];
+          i0 = s_idx[w];
+        }
+      s_ib = i0;
+      s_lib = k0;
+    }
+    __syncthreads();
+    t_ib = D.tours + (int64_t)s_ib * n;
+  }
+
+  // restart-best, global best, bounds, elite choice
+  if (tid == 0) {
+    const double lib = s_lib;
+    int rb_upd = (!st->rb_valid || lib < st->l_rb);
+    if (rb_upd) {
+      st->l_rb = lib;
+      st->rb_valid = 1;
+      st->stall = 0;
+    } else {
+      st->stall += 1;
+    }
+    int gb_upd = lib < st->l_gb;
+    if (gb_upd) {
+      st->l_gb = lib;
+      double tmax, tmin;
+      bounds_from_length(D, lib, tmax, tmin);
+      st->tmax = tmax;
+      st->tmin = tmin;
+      st->tmax_f = (float)tmax;
+      st->tmin_f = (float)tmin;
+    }
+    int use_rb = (t % st->ugb) == 0;
+    s_rb_upd = rb_upd;
+    s_gb_upd = gb_upd;
+    s_use_rb = use_rb;
+    s_lel = use_rb ? st->l_rb : lib;
+    s_tmax = st->tmax_f;
+    s_tmin = st->tmin_f;
+    st->ib = s_ib;
+    st->l_ib = lib;
+    if (D.tr_lib) D.tr_lib[t - 1] = lib;
+    if (D.tr_lgb) D.tr_lgb[t - 1] = st->l_gb;
+    if (D.tr_elite) D.tr_elite[t - 1] = use_rb;
+  }
+  __syncthreads();
+  // the elite tour: the restart-best one (as just updated) or the iteration best
+  const int32_t* elite = (s_use_rb && !s_rb_upd) ? D.t_rb : t_ib;
+  for (int s = tid; s < n; s += nthr) {
+    int v = elite[s];
+    D.succ[v] = elite[s + 1 == n ? 0 : s + 1];
+    D.pred[v] = elite[s == 0 ? n - 1 : s - 1];
+  }
+  if (s_rb_upd)
+    for (int s = tid; s < n; s += nthr) D.t_rb[s] = t_ib[s];
+  if (s_gb_upd)
+    for (int s = tid; s < n; s += nthr) D.t_gb[s] = t_ib[s];
+  __syncthreads();
+
+  // eq. (7)-(8) on every candidate slot, then the choice weights
+  const float keep = D.keep_f;
+  const float delta = (float)(1.0 / s_lel);
+  const float tmax_f = s_tmax, tmin_f = s_tmin;
+  const int nk = n * k;
+  const bool sym = D.sym != 0;
+  for (int x = tid; x < nk; x += nthr) {
+    const int i = x / k;
+    const int j = D.cand[x];
+    const bool on = j == D.succ[i] || (sym && j == D.pred[i]);
+    float v = keep * D.tau[x];
+    v = v + (on ? delta : 0.0f);
+    v = fmaxf(tmin_f, v);
+    v = fminf(tmax_f, v);
+    D.tau[x] = v;
+    D.w[x] = v * D.heur[x];
+  }
+
+  // branching-factor restart
+  if (D.bf_period > 0 && t % D.bf_period == 0) {
+    __syncthreads();
+    unsigned long long cnt = 0;
+    for (int i = tid; i < n; i += nthr) {
+      const float* row = D.tau + (int64_t)i * k;
+      double lo = row[0], hi = lo;
+      for (int u = 1; u < k; ++u) {
+        double v = row[u];
+        if (v < lo) lo = v;
+        if (v > hi) hi = v;
+      }
+      double cut = lo + D.xi_bf * (hi - lo);
+      for (int u = 0; u < k; ++u)
+        if ((double)row[u] >= cut) cnt++;
+    }
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane_id() == 0) s_cnt[tid / WAVE] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long total = 0;
+      for (int w = 0; w < nthr / WAVE; ++w) total += s_cnt[w];
+      double bf = (double)total / ((double)n * (double)D.dstar);
+      int restart = bf < D.lambda_bf && st->stall > D.restart_stall;
+      if (restart) {
+        st->rb_valid = 0;
+        st->stall = 0;
+        st->restarts += 1;
+      }
+      s_restart = restart;
+    }
+    __syncthreads();
+    if (s_restart) {
+      for (int x = tid; x < nk; x += nthr) {
+        D.tau[x] = tmax_f;
+        D.w[x] = tmax_f * D.heur[x];
+      }
+    }
+  }
+  if (tid == 0) {
+    st->ugb = ugb_tier(st->stall, D.ugb_max);
+    st->t = t + 1;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Output: the global best rotated to start at node 0 and, for symmetric
+// instances, read in the direction whose second node is the smaller.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) finish_kernel(const InstDesc* insts, int32_t* const* outs,
+                                                    double* out_lens) {
+  const InstDesc& D = insts[blockIdx.x];
+  const int n = D.n, lane = lane_id();
+  const int32_t* tg = D.t_gb;
+  int r0 = 0x7fffffff;
+  for (int s = lane; s < n; s += WAVE)
+    if (tg[s] == 0) r0 = s;
+  for (int off = 32; off >= 1; off >>= 1) r0 = min(r0, __shfl_xor(r0, off));
+  int32_t* out = outs[blockIdx.x];
+  bool rev = false;
+  if (D.sym && n >= 3) {
+    int t1 = tg[(r0 + 1) % n], tl = tg[(r0 - 1 + n) % n];
+    rev = t1 > tl;
+  }
+  for (int s = lane; s < n; s += WAVE) out[s] = rev ? tg[(r0 - s + n) % n] : tg[(r0 + s) % n];
+  if (lane == 0) out_lens[blockIdx.x] = D.st->l_gb;
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+int32_t max_lds_bytes() { return 160 * 1024; }
+
+size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t staged) {
+  const size_t words2 = (size_t)(((n + 63) >> 6) << 1);
+  const size_t vis_words = ((words2 + 3) >> 2) << 2;
+  size_t bytes = (size_t)ants_per_block * vis_words * 4;
+  if (staged) {
+    const size_t nk = (size_t)n * k;
+    bytes += ((nk * 2 + 15) / 16) * 16 + ((nk * 4 + 15) / 16) * 16;
+  }
+  return bytes;
+}
+
+hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s) {
+  const int waves = 4;
+  hipLaunchKernelGGL(candidates_kernel, dim3((n + waves - 1) / waves), dim3(waves * WAVE), 0, s,
+                     d_insts, inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s) {
+  size_t lds = (size_t)(((max_n + 63) >> 6) << 1) * 4;
+  hipLaunchKernelGGL(nn_tour_kernel, dim3(count), dim3(WAVE), lds, s, d_insts);
+  return hipGetLastError();
+}
+
+static size_t ls_lds_bytes(int32_t max_n) { return (size_t)3 * max_n * 4; }
+
+hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s) {
+  const int use_lds = ls_lds_bytes(max_n) <= (size_t)max_lds_bytes();
+  hipLaunchKernelGGL(two_opt_nn_kernel, dim3(count), dim3(WAVE), use_lds ? ls_lds_bytes(max_n) : 0,
+                     s, d_insts, use_lds);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s) {
+  hipLaunchKernelGGL(init_kernel, dim3(count), dim3(256), 0, s, d_insts);
+  return hipGetLastError();
+}
+
+hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
+                            int32_t ants_per_block, int32_t staged, size_t lds_bytes,
+                            hipStream_t s) {
+  if (staged)
+    hipLaunchKernelGGL(construct_kernel<true>, dim3(blocks), dim3(ants_per_block * WAVE), lds_bytes,
+                       s, d_insts, d_map, ants_per_block);
+  else
+    hipLaunchKernelGGL(construct_kernel<false>, dim3(blocks), dim3(ants_per_block * WAVE),
+                       lds_bytes, s, d_insts, d_map, ants_per_block);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
+                               hipStream_t s) {
+  const int use_lds = ls_lds_bytes(max_n) <= (size_t)max_lds_bytes();
+  hipLaunchKernelGGL(local_search_kernel, dim3(count), dim3(WAVE),
+                     use_lds ? ls_lds_bytes(max_n) : 0, s, d_insts, use_lds);
+  return hipGetLastError();
+}
+
+hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s) {
+  hipLaunchKernelGGL(iter_end_kernel, dim3(count), dim3(1024), 0, s, d_insts);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const* d_out_tours,
+                         double* d_out_lens, hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel, dim3(count), dim3(WAVE), 0, s, d_insts, d_out_tours,
+                     d_out_lens);
+  return hipGetLastError();
+}
+
+}  // namespace hac

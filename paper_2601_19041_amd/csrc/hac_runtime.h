@@ -1,0 +1,105 @@
+// Host runtime shared by the C ABI (hac_api.cpp) and the request loop
+// (hac_server.cpp).
+#pragma once
+
+#include <stdint.h>
+
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/hac.h"
+#include "hac_fold.h"
+#include "hac_internal.h"
+
+namespace hac {
+
+// Grow-only device buffer with 256-byte aligned carving.
+class DeviceArena {
+ public:
+  ~DeviceArena();
+  hipError_t reserve(size_t bytes);
+  void reset() { used_ = 0; }
+  void* carve(size_t bytes);
+  size_t capacity() const { return cap_; }
+  void release();
+
+ private:
+  char* base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+};
+
+// Sizes of the device arrays of one instance.
+struct Layout {
+  int32_t n, k, kg, kls, ants, iterations;
+  bool coords, ls, staged16;
+  int64_t nnz;
+  size_t bytes() const;
+};
+Layout make_layout(const hac_instance* inst, const hac_csr* csr, const hac_params* p);
+
+// Host view of one instance inside a batch.
+struct HostInst {
+  hac_instance inst;  // host pointers
+  hac_csr csr;        // host pointers
+  hac_params p;
+  uint64_t seed;
+  Layout lay;
+  int32_t dstar, sym;
+  double p_x;
+  FoldOutput fold;
+  double l_nn;
+  InstDesc d;  // device pointers
+  std::vector<int32_t> cand_h;  // host copy, used by the fold
+  // inputs that already live in device memory are copied device-to-device
+  bool from_device = false;
+  hac_instance dev_inst{};
+  hac_csr dev_csr{};
+};
+
+// Chosen construction launch shape.
+struct LaunchShape {
+  int32_t ants_per_block;
+  int32_t staged;
+};
+
+// One decode batch: everything from uploaded inputs to results.
+struct Engine {
+  hipStream_t stream = nullptr;
+  std::string* err = nullptr;
+  bool timing = false;
+  bool use_graph = true;
+  // results of the last run
+  double construct_ms = 0.0;
+  int64_t construct_launches = 0;
+  LaunchShape shape{4, 0};
+};
+
+hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_params* p,
+                    std::string* why);
+int32_t degree_target_of(const hac_instance* inst, const hac_params* p);
+
+// Builds the XCD-aware construction block map.
+std::vector<BlockMap> build_block_map(const std::vector<HostInst>& hs, int32_t ants_per_block);
+
+// Launch-shape autotuner: picks ants-per-block and LDS staging by timing
+// the construction kernel; cached per shape class.
+LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs, hipStream_t s,
+                       DeviceArena& scratch, bool* ok);
+
+// Prepares instances whose inputs are already uploaded into their slots:
+// candidates, host fold, NN tour (+2-opt), range checks, initialisation.
+hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipStream_t s,
+                             std::string* err);
+
+// Fills the device pointers of h.d from a carver (256-byte aligned pieces).
+void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve);
+// Fills the scalar fields of h.d from h's parameters.
+void fill_desc_scalars(HostInst& h);
+size_t align256(size_t bytes);
+size_t shape_lds(const std::vector<HostInst>& hs, LaunchShape sh);
+
+// Copies the host inputs of h into its slot (asynchronous on s).
+hipError_t upload_inputs(const HostInst& h, hipStream_t s);
+
+}  // namespace hac

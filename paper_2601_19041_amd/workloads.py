@@ -146,6 +146,8 @@ def softdist_heatmap(
     `row_sum`, stored as FP32 CSR."""
     n = coords.shape[0]
     topk = min(topk, n - 1)
+    if topk < 1:
+        return empty_heatmap(n)
     rows_l, cols_l, vals_l = [], [], []
     for a in range(0, n, chunk):
         rows = np.arange(a, min(n, a + chunk))
@@ -208,6 +210,8 @@ def atsp_heatmap(dist: np.ndarray, topk: int = 20, temp: float = 0.05, plant: fl
     rows rescaled to `row_sum`."""
     n = dist.shape[0]
     topk = min(topk, n - 1)
+    if topk < 1:
+        return empty_heatmap(n)
     rows = np.arange(n)
     idx = _topk_rows(dist, rows, topk)
     dsel = np.take_along_axis(dist, idx, axis=1)
@@ -327,7 +331,10 @@ def random_instance(n: int, seed: int, topk: int = 10, k: int = 10, ants: int = 
     if kind == "coords":
         xy = uniform_coords(n, rng)
         if grid:
-            xy = np.floor(xy * grid) / grid
+            # distinct points of a grid x grid lattice: many equal distances
+            assert n <= grid * grid
+            cells = rng.permutation(grid * grid)[:n]
+            xy = np.stack([cells % grid, cells // grid], 1).astype(np.float64) / grid
         hm = softdist_heatmap(xy, topk) if heat == "softdist" else empty_heatmap(n)
         return Instance(n, "coords", True, xy, None, hm, ants=ants, iterations=iterations, k=k,
                         local_search=local_search, k_ls=k_ls, seed=seed, name=f"rand{n}#{seed}")

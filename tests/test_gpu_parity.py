@@ -1,0 +1,141 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Tours must be identical and lengths equal within 1e-12 relative (they are
+summed in the same order, so in practice they are bit-identical).  Small
+cases also compare the internal state (candidate lists, folded weights,
+pheromone, choice weights, the last iteration's ant tours) bit for bit and
+the per-iteration trace.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_19041_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2601_19041_amd as hac
+    c = hac.Context(0)
+    yield c
+    c.close()
+
+
+def _same(gpu, ref, what=""):
+    gt, gl = gpu
+    st, ot, ol, _ = ref
+    assert st == 0
+    assert np.array_equal(gt, ot), f"{what}: tours differ at {np.flatnonzero(gt != ot)[:5]}"
+    assert abs(gl - ol) <= REL * ol, (what, gl, ol)
+
+
+def _state_parity(ctx, inst, which=0, **over):
+    n, ants = inst.n, over.get("ants", inst.ants)
+    k = over.get("k", inst.k)
+    g = ctx.debug_state(which, n, k, ants)
+    st, tour, L, info = oracle.decode(inst, trace=True, state=True, **over)
+    assert st == 0
+    for name in ("cand", "heur", "tau", "weight", "ant_tours", "nn_tour"):
+        assert np.array_equal(g[name], info[name]), f"{name} differs"
+    assert np.array_equal(g["ant_len"], info["ant_len"]), "ant lengths differ"
+    tr = ctx.debug_trace(which, over.get("iterations", inst.iterations))
+    assert np.array_equal(tr["l_ib"], info["l_ib"])
+    assert np.array_equal(tr["l_gb"], info["l_gb"])
+    assert np.array_equal(tr["elite_rb"], info["elite_rb"])
+    return info
+
+
+def test_tsp100_full(ctx):
+    """The n=100 workload at its full size (k=10, 20 ants, 100 iterations)."""
+    inst = wl.tsp100()
+    print("case tsp100 full", flush=True)
+    gpu = ctx.decode(inst)
+    ref = oracle.decode(inst, trace=True)
+    _same(gpu, ref, "tsp100")
+    info = _state_parity(ctx, inst)
+    assert ctx.stats()["fallback_steps"] == info["fallback_steps"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_tsp100_seeds(ctx, seed):
+    inst = wl.tsp100(instance=seed, seed=seed, iterations=40)
+    print(f"case tsp100 seed {seed}", flush=True)
+    _same(ctx.decode(inst), oracle.decode(inst), f"seed{seed}")
+
+
+@pytest.mark.parametrize("name", ["atsp", "symmatrix", "ls", "empty", "grid_ties", "k_full",
+                                  "scope1", "ugb_restart"])
+def test_small_variants(ctx, name):
+    over = {}
+    if name == "atsp":
+        inst = wl.random_instance(60, seed=5, kind="matrix", symmetric=False, k=8, ants=12, iterations=30)
+    elif name == "symmatrix":
+        inst = wl.random_instance(60, seed=6, kind="matrix", symmetric=True, k=8, ants=12, iterations=30)
+    elif name == "ls":
+        inst = wl.random_instance(150, seed=7, k=10, ants=12, iterations=25, local_search=1, k_ls=12)
+    elif name == "empty":
+        inst = wl.random_instance(80, seed=8, heat="empty", k=8, ants=10, iterations=30)
+    elif name == "grid_ties":
+        inst = wl.random_instance(90, seed=9, grid=12, k=10, ants=10, iterations=30)
+    elif name == "k_full":
+        inst = wl.random_instance(12, seed=10, k=11, ants=20, iterations=40)
+    elif name == "scope1":
+        inst = wl.random_instance(70, seed=11, k=6, ants=10, iterations=20)
+        over = dict(baseline_scope=1)
+    else:
+        inst = wl.random_instance(40, seed=12, k=5, ants=6, iterations=60)
+        over = dict(ugb_max=3, bf_period=7, restart_stall=2, lambda_bf=1e9)
+    print(f"case {name}", flush=True)
+    gpu = ctx.decode(inst, **over)
+    ref = oracle.decode(inst, **over)
+    _same(gpu, ref, name)
+    _state_parity(ctx, inst, **over)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7])
+def test_tiny_instances(ctx, n):
+    inst = wl.random_instance(n, seed=20 + n, k=10, ants=3, iterations=5)
+    print(f"case tiny n={n}", flush=True)
+    gpu = ctx.decode(inst)
+    ref = oracle.decode(inst)
+    _same(gpu, ref, f"n{n}")
+
+
+def test_batch_equals_alone(ctx):
+    insts = [wl.random_instance(40 + 17 * x, seed=30 + x, k=8 + x % 3, ants=6 + x, iterations=15 + x)
+             for x in range(6)]
+    insts.append(wl.random_instance(50, seed=99, kind="matrix", symmetric=False, k=7, ants=5, iterations=12))
+    print("case batch", flush=True)
+    got = ctx.decode_batch(insts)
+    for x, inst in enumerate(insts):
+        _same(got[x], oracle.decode(inst), f"batch{x}")
+        alone = ctx.decode(inst)
+        assert np.array_equal(alone[0], got[x][0]) and alone[1] == got[x][1]
+
+
+@pytest.mark.parametrize("shape", ["1,0", "4,0", "16,0", "1,1", "8,1"])
+def test_launch_shape_independence(ctx, shape, monkeypatch):
+    inst = wl.tsp100(instance=4, seed=4, iterations=25)
+    monkeypatch.setenv("HAC_SHAPE", shape)
+    print(f"case shape {shape}", flush=True)
+    _same(ctx.decode(inst), oracle.decode(inst), shape)
+
+
+def test_invalid_inputs_leave_outputs(ctx):
+    import paper_2601_19041_amd as hac
+    inst = wl.random_instance(30, seed=3)
+    bad = wl.random_instance(30, seed=3)
+    bad.heat = wl.Heatmap(30, inst.heat.row_ptr.copy(), inst.heat.col.copy(), inst.heat.val.copy())
+    bad.heat.col[1] = bad.heat.col[0]
+    assert ctx.decode_status(bad) == hac.HAC_EINVAL
+    assert ctx.decode_status(inst, rho=0.0) == hac.HAC_EINVAL
+    assert ctx.decode_status(inst, alpha=2.0) == hac.HAC_EUNSUPPORTED
+    assert ctx.decode_status(inst, k=65) == hac.HAC_EUNSUPPORTED
+    assert ctx.decode_status(inst) == hac.HAC_OK

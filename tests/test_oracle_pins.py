@@ -79,7 +79,7 @@ def brute_candidates(inst, k, theta=1e-4):
 
 
 @pytest.mark.parametrize("n,topk,k,grid", [(40, 10, 8, None), (40, 4, 10, None), (60, 10, 10, None),
-                                          (50, 10, 12, 6), (30, 6, 29, 4), (12, 3, 20, None)])
+                                          (50, 10, 12, 9), (30, 6, 29, 6), (12, 3, 20, None)])
 def test_candidates_match_brute_force(n, topk, k, grid):
     inst = wl.random_instance(n, seed=n + topk + k, topk=topk, k=k, grid=grid)
     got = oracle.candidates(inst)
@@ -340,7 +340,7 @@ def brute_nn_tour(inst):
 
 
 def test_nn_tour_brute_force_with_ties():
-    for inst in [wl.random_instance(60, seed=2), wl.random_instance(60, seed=3, grid=5),
+    for inst in [wl.random_instance(60, seed=2), wl.random_instance(60, seed=3, grid=8),
                  wl.random_instance(45, seed=4, kind="matrix", symmetric=False)]:
         t, L = oracle.nn_tour(inst)
         assert np.array_equal(t, brute_nn_tour(inst))
