@@ -66,7 +66,9 @@ class hac_stats(ctypes.Structure):
                 ("construct_launches", ctypes.c_int64), ("ant_steps", ctypes.c_int64),
                 ("fallback_steps", ctypes.c_int64), ("restarts", ctypes.c_int32),
                 ("instances", ctypes.c_int32), ("kappa", ctypes.c_double), ("q90", ctypes.c_double),
-                ("r_hat", ctypes.c_double), ("l_nn", ctypes.c_double)]
+                ("r_hat", ctypes.c_double), ("l_nn", ctypes.c_double),
+                ("ants_per_block", ctypes.c_int32), ("lds_staged", ctypes.c_int32),
+                ("lanes_per_ant", ctypes.c_int32)]
 
 
 # every symbol include/hac.h declares

@@ -144,7 +144,6 @@ Layout make_layout(const hac_instance* inst, const hac_csr* csr, const hac_param
   L.iterations = p->iterations;
   L.coords = inst->kind == HAC_COORDS_EUC2D;
   L.ls = p->local_search != 0;
-  L.staged16 = inst->n <= 65535;
   L.nnz = csr->nnz;
   return L;
 }
@@ -154,7 +153,7 @@ size_t Layout::bytes() const {
   size_t b = 0;
   b += align256(coords ? 16 * nn : 8 * nn * nn);
   b += align256(4 * (nn + 1)) + align256(4 * (size_t)nnz) + align256(4 * (size_t)nnz);
-  b += align256(4 * nk) + (staged16 ? align256(2 * nk + 16) : 0) + 3 * align256(4 * nk + 16);
+  b += align256(4 * nk) + align256(8 * nk + 16) + 3 * align256(4 * nk + 16);
   b += align256(4 * nn * (size_t)kg);
   b += align256(4 * nn * (size_t)ants) + align256(8 * (size_t)ants);
   b += 6 * align256(4 * nn);
@@ -174,7 +173,7 @@ void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve) {
   d.col = (const int32_t*)carve(4 * (size_t)L.nnz);
   d.val = (const float*)carve(4 * (size_t)L.nnz);
   d.cand = (int32_t*)carve(4 * nk);
-  d.cand16 = L.staged16 ? (const uint16_t*)carve(2 * nk + 16) : nullptr;
+  d.cw = (uint2*)carve(8 * nk + 16);
   d.heur = (const float*)carve(4 * nk + 16);
   d.tau = (float*)carve(4 * nk + 16);
   d.w = (float*)carve(4 * nk + 16);
@@ -292,7 +291,6 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   HAC_HIP(hipStreamSynchronize(s));
   // host fold (eq. 9-14)
   std::vector<std::vector<float>> heur(count);
-  std::vector<std::vector<uint16_t>> c16(count);
   std::vector<int> frc(count, FOLD_OK);
   std::vector<double> lbs(count, 0.0);
   parallel_for(count, [&](int x) {
@@ -320,10 +318,6 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
     const size_t nk = (size_t)L.n * L.k;
     heur[x].assign(nk + 4, 0.0f);
     frc[x] = fold_instance(in, h.cand_h.data(), heur[x].data(), &h.fold);
-    if (L.staged16) {
-      c16[x].assign(nk + 8, 0);
-      for (size_t q = 0; q < nk; ++q) c16[x][q] = (uint16_t)h.cand_h[q];
-    }
     // lower bound on any tour: every node leaves once, at least to its nearest
     double lb = 0.0;
     for (int32_t i = 0; i < L.n; ++i) {
@@ -352,8 +346,6 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
     HostInst& h = hs[x];
     const size_t nk = (size_t)h.lay.n * h.lay.k;
     HAC_HIP(hipMemcpyAsync((void*)h.d.heur, heur[x].data(), 4 * nk, hipMemcpyHostToDevice, s));
-    if (h.lay.staged16)
-      HAC_HIP(hipMemcpyAsync((void*)h.d.cand16, c16[x].data(), 2 * nk, hipMemcpyHostToDevice, s));
   }
   // NN tour (+ 2-opt), then the range check on the first bounds
   HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
@@ -438,8 +430,8 @@ static void tune_cache_load() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char key[256];
-  int a, st;
-  while (std::fscanf(f, "%255s %d %d", key, &a, &st) == 3) g_tune_cache[key] = LaunchShape{a, st};
+  int a, st, ln;
+  while (std::fscanf(f, "%255s %d %d %d", key, &a, &st, &ln) == 4) g_tune_cache[key] = LaunchShape{a, st, ln};
   std::fclose(f);
 }
 
@@ -449,17 +441,23 @@ static void tune_cache_store() {
   FILE* f = std::fopen(path, "w");
   if (!f) return;
   for (auto& kv : g_tune_cache)
-    std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged);
+    std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged,
+                 kv.second.lanes);
   std::fclose(f);
 }
 
 static bool shape_fits(const std::vector<HostInst>& hs, LaunchShape sh) {
   for (auto& h : hs) {
-    if (sh.staged && !h.lay.staged16) return false;
     if (construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.staged) > (size_t)max_lds_bytes())
       return false;
   }
   return true;
+}
+
+int32_t batch_max_k(const std::vector<HostInst>& hs) {
+  int32_t k = 1;
+  for (auto& h : hs) k = std::max(k, h.lay.k);
+  return k;
 }
 
 size_t shape_lds(const std::vector<HostInst>& hs, LaunchShape sh) {
@@ -487,12 +485,19 @@ static std::string shape_key(const std::vector<HostInst>& hs) {
 LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs, hipStream_t s,
                        DeviceArena& scratch, bool* ok) {
   *ok = true;
+  // lanes per ant: at least the candidate width, at most a whole wave
+  const int32_t gmin = construct_group_lanes(batch_max_k(hs));
   if (const char* force = std::getenv("HAC_SHAPE")) {
-    // "A,staged" pins the launch shape (used to show shape independence)
-    LaunchShape sh{1, 0};
-    if (std::sscanf(force, "%d,%d", &sh.ants_per_block, &sh.staged) == 2 && shape_fits(hs, sh) &&
-        sh.ants_per_block >= 1 && sh.ants_per_block <= 16)
-      return sh;
+    // "A,staged[,lanes]" pins the launch shape (used to show shape
+    // independence); A is rounded up to whole waves
+    LaunchShape sh{1, 0, gmin};
+    const int got = std::sscanf(force, "%d,%d,%d", &sh.ants_per_block, &sh.staged, &sh.lanes);
+    if (got >= 2 && sh.ants_per_block >= 1) {
+      if (got < 3 || (sh.lanes != 16 && sh.lanes != 32 && sh.lanes != 64) || sh.lanes < gmin) sh.lanes = gmin;
+      const int32_t per_wave = 64 / sh.lanes;
+      sh.ants_per_block = (sh.ants_per_block + per_wave - 1) / per_wave * per_wave;
+      if (sh.ants_per_block <= 16 * per_wave && shape_fits(hs, sh)) return sh;
+    }
   }
   const std::string key = shape_key(hs);
   {
@@ -502,12 +507,15 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     if (it != g_tune_cache.end() && shape_fits(hs, it->second)) return it->second;
   }
   std::vector<LaunchShape> cands;
-  for (int apb : {1, 2, 4, 8, 16})
-    for (int st : {0, 1}) {
-      LaunchShape sh{apb, st};
-      if (shape_fits(hs, sh)) cands.push_back(sh);
-    }
-  LaunchShape best{1, 0};
+  for (int lanes : {16, 32, 64}) {
+    if (lanes < gmin) continue;
+    for (int waves : {1, 2, 4, 8, 16})
+      for (int st : {0, 1}) {
+        LaunchShape sh{waves * (64 / lanes), st, lanes};
+        if (shape_fits(hs, sh)) cands.push_back(sh);
+      }
+  }
+  LaunchShape best{1, 0, 64};
   float best_ms = 1e30f;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -532,7 +540,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);
       (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block, sh.staged,
-                             shape_lds(hs, sh), s);
+                             sh.lanes, shape_lds(hs, sh), s);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) {
         *ok = false;
@@ -826,6 +834,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
 
   double construct_ms = 0.0;
   int64_t launches = 0;
+  LaunchShape used{0, 0, 0};
   if (m > 0) {
     bool any_ls = false;
     int32_t max_iter = 0, max_n = 0;
@@ -834,13 +843,14 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       max_iter = std::max(max_iter, h.p.iterations);
       max_n = std::max(max_n, h.lay.n);
     }
-    LaunchShape shape{1, 0};
+    LaunchShape shape{1, 0, 64};
     if (max_iter > 0) {
       bool ok = true;
       shape = tune_shape(hs, d_descs, s, c->scratch, &ok);
       if (!ok) return set_err(c, HAC_EDEVICE, "autotuner launch failed");
       CTX_HIP(launch_init(d_descs, m, s));  // undo the tuner's fallback counts
     }
+    used = shape;
     std::vector<BlockMap> map = build_block_map(hs, shape.ants_per_block);
     c->scratch.reset();
     CTX_HIP(c->scratch.reserve(map.size() * sizeof(BlockMap)));
@@ -849,7 +859,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     const size_t lds = shape_lds(hs, shape);
     const int32_t blocks = (int32_t)map.size();
     auto one_iteration = [&]() -> hipError_t {
-      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, lds, s);
+      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, shape.lanes, lds, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
         e = launch_local_search(d_descs, m, max_n, s);
@@ -866,7 +876,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       }
       for (int32_t it = 0; it < max_iter; ++it) {
         CTX_HIP(hipEventRecord(c->events[2 * it], s));
-        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, lds, s));
+        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, shape.lanes, lds, s));
         CTX_HIP(hipEventRecord(c->events[2 * it + 1], s));
         if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
@@ -944,6 +954,9 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   st.total_ms = ms_since(t0);
   st.construct_ms = construct_ms;
   st.construct_launches = launches;
+  st.ants_per_block = used.ants_per_block;
+  st.lds_staged = used.staged;
+  st.lanes_per_ant = used.lanes;
   for (int32_t y = 0; y < m; ++y) {
     st.ant_steps += (int64_t)hs[y].p.ants * (hs[y].lay.n - 1) * hs[y].p.iterations;
     st.fallback_steps += (int64_t)sts[y].fallbacks;

@@ -39,7 +39,7 @@ struct InstDesc {
   const int32_t* col;
   const float* val;
   int32_t* cand;              // [n][k]
-  const uint16_t* cand16;     // [n][k] (n <= 65535) for LDS staging, or null
+  uint2* cw;                  // [n][k] {candidate id, bits of tau * S}: one 8-byte load per slot
   const float* heur;          // [n][k]  S = eta^beta e^kappa
   float* tau;                 // [n][k]
   float* w;                   // [n][k]  tau * S
@@ -71,7 +71,7 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
-                            int32_t ants_per_block, int32_t staged, size_t lds_bytes,
+                            int32_t ants_per_block, int32_t staged, int32_t lanes, size_t lds_bytes,
                             hipStream_t s);
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                hipStream_t s);
@@ -79,6 +79,8 @@ hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s
 hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const* d_out_tours,
                          double* d_out_lens, hipStream_t s);
 
+// lanes per ant in the construction kernel (16, 32 or 64) for a candidate width
+int32_t construct_group_lanes(int32_t max_k);
 // LDS the construction kernel needs for one block
 size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t staged);
 int32_t max_lds_bytes();

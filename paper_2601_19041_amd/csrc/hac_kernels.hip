@@ -81,6 +81,42 @@ __device__ __forceinline__ bool key_less(double ka, int ia, double kb, int ib) {
   return ka < kb || (ka == kb && ia < ib);
 }
 
+// Pointers known to address global memory, so that accesses compile to
+// global_* instead of flat_* instructions (a flat access may alias LDS and
+// forces waits on every later LDS access).
+#define HAC_AS1 __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ HAC_AS1 T* as_global(T* p) {
+  return (HAC_AS1 T*)p;
+}
+
+// The distance view the hot kernels use.
+struct GDist {
+  const HAC_AS1 double* xy = nullptr;
+  const HAC_AS1 double* dist = nullptr;
+  int n = 0;
+  GDist() = default;
+  __device__ explicit GDist(const InstDesc& D)
+      : xy(D.xy ? as_global(D.xy) : nullptr), dist(D.dist ? as_global(D.dist) : nullptr), n(D.n) {}
+  __device__ __forceinline__ double key(int i, int j) const {
+    if (xy) {
+      const double dx = xy[2 * i] - xy[2 * j];
+      const double dy = xy[2 * i + 1] - xy[2 * j + 1];
+      return dx * dx + dy * dy;
+    }
+    return dist[(int64_t)i * n + j];
+  }
+  __device__ __forceinline__ double len(int i, int j) const {
+    if (xy) return sqrt(key(i, j));
+    return dist[(int64_t)i * n + j];
+  }
+};
+
+// lane mask of a > b for unsigned 64-bit values, straight from the compare
+__device__ __forceinline__ uint64_t lanes_ugt(uint64_t a, uint64_t b) {
+  return __builtin_amdgcn_uicmpl(a, b, 34 /* unsigned greater than */);
+}
+
 // Lexicographic (key, index) minimum over the wave, returned to all lanes.
 __device__ __forceinline__ void wave_argmin(double& key, int& idx) {
 #pragma unroll
@@ -157,35 +193,6 @@ __device__ double tour_length_wave(const InstDesc& D, const int32_t* tour) {
 // bitset (bits >= n set).  The geometric list holds the kg nearest nodes in
 // that order, so its first unvisited entry, if any, is the answer;
 // otherwise every node is scanned.
-__device__ int nearest_unvisited(const InstDesc& D, int i, const uint32_t* vis) {
-  const int lane = lane_id(), n = D.n, kg = D.kg;
-  int g = 0;
-  bool open = false;
-  if (lane < kg) {
-    g = D.geo[(int64_t)i * kg + lane];
-    open = !((vis[g >> 5] >> (g & 31)) & 1u);
-  }
-  uint64_t m = __ballot(open);
-  if (m) return rd_lane(g, __ffsll((unsigned long long)m) - 1);
-  double bk = __builtin_huge_val();
-  int bj = 0x7fffffff;
-  for (int b0 = 0; b0 < n; b0 += WAVE) {
-    uint32_t w0 = vis[b0 >> 5], w1 = vis[(b0 >> 5) + 1];
-    if ((w0 & w1) == 0xffffffffu) continue;
-    uint32_t word = lane < 32 ? w0 : w1;
-    int j = b0 + lane;
-    if (!((word >> (lane & 31)) & 1u)) {
-      double kj = order_key(D, i, j);
-      if (kj < bk) {
-        bk = kj;
-        bj = j;
-      }
-    }
-  }
-  wave_argmin(bk, bj);
-  return bj < n ? bj : n - 1;  // always a node index, even on a broken bitset
-}
-
 // ------------------------------------------------------------------------
 // Candidate lists (eq. 3) and geometric neighbour lists.
 // One wave per row.  The k nearest heatmap-supported nodes, or all of them
@@ -289,6 +296,17 @@ __global__ void __launch_bounds__(256) candidates_kernel(const InstDesc* insts, 
   if (lane < s) out[rank_s] = sup.id;
   if (lane < need) out[rank_f] = fill.id;
   if (lane < kg) D.geo[(int64_t)i * kg + lane] = geo.id;
+}
+
+// Nearest unvisited node to i by (key, index), for the preparation kernels.
+template <int CH>
+__device__ int scan_unvisited_g(const GDist& G, int i, const uint32_t* vis);
+__device__ __forceinline__ int geo_first_unvisited(const HAC_AS1 int32_t* geo, int kg, int i,
+                                                   const uint32_t* vis);
+__device__ int nearest_unvisited(const InstDesc& D, int i, const uint32_t* vis) {
+  const int jg = geo_first_unvisited(as_global(D.geo), D.kg, i, vis);
+  if (jg >= 0) return jg;
+  return scan_unvisited_g<8>(GDist(D), i, vis);
 }
 
 // ------------------------------------------------------------------------
@@ -495,138 +513,426 @@ __global__ void __launch_bounds__(256) init_kernel(const InstDesc* insts) {
   const float tm = s_tmax;
   const int64_t nk = (int64_t)D.n * D.k;
   for (int64_t x = threadIdx.x; x < nk; x += blockDim.x) {
+    const float w = tm * D.heur[x];
     D.tau[x] = tm;
-    D.w[x] = tm * D.heur[x];
+    D.w[x] = w;
+    D.cw[x] = make_uint2((uint32_t)D.cand[x], __float_as_uint(w));
   }
   for (int s = threadIdx.x; s < D.n; s += blockDim.x) D.t_gb[s] = D.nn_tour[s];
 }
 
+// Full scans for the nearest unvisited node.  Each lane takes nodes
+// j = b0 + 64c + lane; CH chunks are loaded before any is examined, so a
+// batch costs one memory round trip.  Every lane keeps its own best
+// (key, j) in increasing j, then the wave reduces.  Visited bits past n
+// are set, so j < n need not be tested against the bitset.
+template <int CH>
+__device__ int scan_unvisited_lds(const double2* xy, int n, int i, const uint32_t* vis) {
+  const int lane = lane_id();
+  const double2 pi = xy[i];
+  double bk = __builtin_huge_val();
+  int bj = 0x7fffffff;
+  for (int b0 = 0; b0 < n; b0 += CH * WAVE) {
+    bool open[CH];
+    double2 p[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int j = b0 + c * WAVE + lane;
+      const int jc = j < n ? j : n - 1;  // reads stay inside this ant's bitset
+      open[c] = j < n && !((vis[jc >> 5] >> (jc & 31)) & 1u);
+      p[c] = xy[jc];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const double dx = pi.x - p[c].x, dy = pi.y - p[c].y;
+      const double kj = dx * dx + dy * dy;
+      if (open[c] && kj < bk) {
+        bk = kj;
+        bj = b0 + c * WAVE + lane;
+      }
+    }
+  }
+  wave_argmin(bk, bj);
+  return bj < n ? bj : n - 1;
+}
+
+template <int CH>
+__device__ int scan_unvisited_g(const GDist& G, int i, const uint32_t* vis) {
+  const int lane = lane_id(), n = G.n;
+  double bk = __builtin_huge_val();
+  int bj = 0x7fffffff;
+  if (G.xy) {
+    const HAC_AS1 double* xy = G.xy;
+    const double xi = xy[2 * i], yi = xy[2 * i + 1];
+    for (int b0 = 0; b0 < n; b0 += CH * WAVE) {
+      bool open[CH];
+      double px[CH], py[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int j = b0 + c * WAVE + lane;
+        const int jc = j < n ? j : n - 1;
+        open[c] = j < n && !((vis[jc >> 5] >> (jc & 31)) & 1u);
+        px[c] = xy[2 * jc];
+        py[c] = xy[2 * jc + 1];
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const double dx = xi - px[c], dy = yi - py[c];
+        const double kj = dx * dx + dy * dy;
+        if (open[c] && kj < bk) {
+          bk = kj;
+          bj = b0 + c * WAVE + lane;
+        }
+      }
+    }
+  } else {
+    const HAC_AS1 double* row = G.dist + (int64_t)i * n;
+    for (int b0 = 0; b0 < n; b0 += CH * WAVE) {
+      bool open[CH];
+      double v[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int j = b0 + c * WAVE + lane;
+        const int jc = j < n ? j : n - 1;
+        open[c] = j < n && !((vis[jc >> 5] >> (jc & 31)) & 1u);
+        v[c] = row[jc];
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        if (open[c] && v[c] < bk) {
+          bk = v[c];
+          bj = b0 + c * WAVE + lane;
+        }
+    }
+  }
+  wave_argmin(bk, bj);
+  return bj < n ? bj : n - 1;
+}
+
+// The geometric list holds the kg nearest nodes in (key, index) order, so
+// its first unvisited entry, if any, is the answer; otherwise a full scan.
+__device__ __forceinline__ int geo_first_unvisited(const HAC_AS1 int32_t* geo, int kg, int i,
+                                                   const uint32_t* vis) {
+  const int lane = lane_id();
+  int g = 0;
+  bool open = false;
+  if (lane < kg) {
+    g = geo[(int64_t)i * kg + lane];
+    open = !((vis[g >> 5] >> (g & 31)) & 1u);
+  }
+  const uint64_t m = __builtin_amdgcn_ballot_w64(open);
+  return m ? rd_lane(g, __ffsll((unsigned long long)m) - 1) : -1;
+}
+
 // ------------------------------------------------------------------------
-// Ant construction (Alg. 2, eq. 4).  One wavefront per ant; lane u holds
-// candidate slot u of the current node.  Per step:
+// Ant construction (Alg. 2, eq. 4).
+//
+// Per step, for the ant at node i with candidate row C_i:
 //   open slots  = candidates whose visited bit is clear (LDS bitset)
 //   E           = largest biased exponent of the open weights
 //   q_u         = max(1, floor(w_u 2^(31-E)))  by integer shifts of the
 //                 FP32 mantissa (exact)
 //   r           = floor(U * sum q / 2^64) for the step's 64-bit uniform U
 //   choice      = first open slot whose inclusive prefix sum exceeds r
-// and when no slot is open the nearest unvisited node.  The Philox blocks
-// for 64 consecutive steps are computed at once, one per lane; the tour is
-// buffered 64 steps per register and its length is summed in step order.
-// STAGED copies the instance's candidate ids (16 bit) and weights to LDS.
+// and, when no slot is open, the nearest unvisited node.
+//
+// Lane groups.  A wave64 VALU instruction occupies a 16-lane SIMD for four
+// cycles, so a wave that spends 64 lanes on a 10- or 20-slot row wastes
+// most of the chip.  An ant therefore owns a group of G lanes (G = 16, 32
+// or 64, the smallest that holds k slots) and a wave carries 64/G ants
+// that step in lockstep through the same instance.  Reductions stay inside
+// the group: a butterfly max (quad_perm / row mirrors, plus a lane^16
+// swizzle for G >= 32), a row-shifted prefix scan, and row_newbcast
+// broadcasts.  The chosen node comes back with one ds_bpermute.  Groups
+// whose row is exhausted run the wave-wide nearest-unvisited scan one after
+// another.
+//
+// The step loop is unrolled by 16: at step s the lane (s mod 16) of every
+// 16-lane row holds that step's Philox output and buffers the tour entry,
+// so every broadcast lane index is a compile-time constant.  The tour is
+// written and its length accumulated (in step order) once per 16 steps.
+// STAGED copies the instance's {candidate, weight} table and coordinates
+// into LDS at the start of the launch.
 // ------------------------------------------------------------------------
-template <bool STAGED>
-__global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* insts, const BlockMap* map,
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_all(uint32_t x) {
+  // permutations that stay inside a row: every lane has a source
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t swz_xor16(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401f);  // lane ^ 16 inside 32 lanes
+}
+
+// every lane gets the maximum of its G-lane group
+template <int G>
+__device__ __forceinline__ uint32_t group_max_all(uint32_t v) {
+  v = max(v, dpp_all<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
+  v = max(v, dpp_all<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
+  v = max(v, dpp_all<0x141>(v));  // row_half_mirror: the other quad of the half row
+  v = max(v, dpp_all<0x140>(v));  // row_mirror: the other half of the row
+  if (G >= 32) v = max(v, swz_xor16(v));
+  if (G >= 64) v = max((uint32_t)__builtin_amdgcn_readlane((int)v, 0),
+                       (uint32_t)__builtin_amdgcn_readlane((int)v, 32));
+  return v;
+}
+
+// inclusive prefix sum inside each G-lane group
+template <int G>
+__device__ __forceinline__ uint64_t group_scan_u64(uint64_t v) {
+#define HAC_GSCAN_STEP(C, R)                                                       \
+  {                                                                               \
+    uint32_t lo_ = (uint32_t)v, hi_ = (uint32_t)(v >> 32);                        \
+    v += ((uint64_t)dpp_or0<C, R>(hi_) << 32) | (uint64_t)dpp_or0<C, R>(lo_);     \
+  }
+  HAC_GSCAN_STEP(0x111, 0xf)
+  HAC_GSCAN_STEP(0x112, 0xf)
+  HAC_GSCAN_STEP(0x114, 0xf)
+  HAC_GSCAN_STEP(0x118, 0xf)
+  if (G >= 32) HAC_GSCAN_STEP(0x142, 0xa)
+  if (G >= 64) HAC_GSCAN_STEP(0x143, 0xc)
+#undef HAC_GSCAN_STEP
+  return v;
+}
+
+// lane Q of each 16-lane row, to the whole row
+template <int Q>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
+  return dpp_all<0x150 + Q>(v);
+}
+template <int Q>
+__device__ __forceinline__ uint64_t row_bcast_u64(uint64_t v) {
+  return ((uint64_t)row_bcast<Q>((uint32_t)(v >> 32)) << 32) | row_bcast<Q>((uint32_t)v);
+}
+template <int Q>
+__device__ __forceinline__ double row_bcast_f64(double v) {
+  return __hiloint2double((int)row_bcast<Q>((uint32_t)__double2hiint(v)),
+                          (int)row_bcast<Q>((uint32_t)__double2loint(v)));
+}
+
+// the group's total: the inclusive scan value of its last lane
+template <int G>
+__device__ __forceinline__ uint64_t group_total_u64(uint64_t pre, int lane) {
+  if (G == 16) return row_bcast_u64<15>(pre);
+  if (G == 32) {
+    const uint64_t t = row_bcast_u64<15>(pre);  // odd rows now hold the total
+    const uint64_t o = ((uint64_t)swz_xor16((uint32_t)(t >> 32)) << 32) | swz_xor16((uint32_t)t);
+    return (lane & 16) ? t : o;
+  }
+  return rd_lane_u64(pre, 63);
+}
+
+// floor(a * b / 2^64) on the vector unit
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t t1 = __umulhi(a0, b0);
+  const uint64_t t2 = (uint64_t)a1 * b0 + t1;
+  const uint64_t t3 = (uint64_t)a0 * b1 + (uint32_t)t2;
+  return (uint64_t)a1 * b1 + (t2 >> 32) + (t3 >> 32);
+}
+
+template <bool STAGED, int G>
+struct AntGroups {
+  static constexpr int R = WAVE / G;  // ants per wave
+  // instance
+  int n, k, kg, t, lane, u, g, r16;
+  bool live;
+  const uint64_t* cw_lds;
+  const HAC_AS1 uint64_t* cw_g;
+  const double2* xy_lds;
+  GDist D;
+  const HAC_AS1 int32_t* geo;
+  uint32_t* vis_wave;  // bitsets of this wave's R ants, vis_words apart
+  uint32_t* vis_g;     // this lane's ant
+  int vis_words;
+  // per-ant state (uniform inside a group)
+  int cur;
+  uint32_t fallbacks;
+  int tb;        // lane (s mod 16) of every row holds T[s] of the block
+  uint64_t rnd;  // lane (s mod 16) of every row holds step s's uniform
+
+  __device__ __forceinline__ int nearest(int gg) const {
+    const int ii = rd_lane(cur, gg * G);
+    const uint32_t* vv = vis_wave + gg * vis_words;
+    const int jg = geo_first_unvisited(geo, kg, ii, vv);
+    if (jg >= 0) return jg;
+    return (STAGED && xy_lds) ? scan_unvisited_lds<4>(xy_lds, n, ii, vv)
+                              : scan_unvisited_g<8>(D, ii, vv);
+  }
+
+  template <int Q>
+  __device__ __forceinline__ void step() {
+    const int x = cur * k + (u < k ? u : 0);  // lanes past the row reread slot 0
+    const uint64_t e = STAGED ? cw_lds[x] : cw_g[x];  // {id, weight bits}
+    const int c = (int)(uint32_t)e;
+    const uint32_t wb = (uint32_t)(e >> 32);
+    const bool open = (u < k) & !((vis_g[c >> 5] >> (c & 31)) & 1u);
+    const uint64_t om = __builtin_amdgcn_ballot_w64(open);
+    const uint32_t be = open ? (wb >> 23) : 0u;
+    const uint32_t d = group_max_all<G>(be) - be;
+    const uint32_t m = ((wb & 0x7fffffu) | 0x800000u) << 8;
+    const uint32_t q = max(d < 32u ? (m >> d) : 0u, 1u);
+    const uint64_t pre = group_scan_u64<G>(open ? (uint64_t)q : 0ull);
+    const uint64_t tot = group_total_u64<G>(pre, lane);
+    const uint64_t r = mulhi64(row_bcast_u64<Q>(rnd), tot);
+    const uint64_t sm = om & lanes_ugt(pre, r);
+    int j;
+    uint64_t fb_lead;
+    if constexpr (G == 64) {
+      j = rd_lane(c, __ffsll((unsigned long long)sm) - 1);
+      fb_lead = om ? 0ull : 1ull;
+    } else {
+      const uint32_t gmask = G == 16 ? 0xffffu : 0xffffffffu;
+      const uint32_t field = (uint32_t)(sm >> (G * g)) & gmask;
+      // an exhausted group gets some lane of its own; the fallback below overwrites j
+      const int src = G * g + (int)__builtin_ctz(field | (1u << (G - 1)));
+      j = __builtin_amdgcn_ds_bpermute(src * 4, c);
+      const uint32_t ofield = (uint32_t)(om >> (G * g)) & gmask;
+      fb_lead = __builtin_amdgcn_ballot_w64(u == 0 && ofield == 0u);
+    }
+    while (fb_lead) {  // exhausted rows: nearest unvisited node, one group at a time
+      const int lead = __ffsll((unsigned long long)fb_lead) - 1;
+      fb_lead &= fb_lead - 1;
+      const int gg = lead / G;
+      const int jj = nearest(gg);
+      if (g == gg) {
+        j = jj;
+        fallbacks++;
+      }
+    }
+    if (u == 0) atomicOr(&vis_g[j >> 5], 1u << (j & 31));
+    if (r16 == Q) tb = j;
+    cur = j;
+  }
+};
+
+template <int Q, class A>
+__device__ __forceinline__ void unroll16(A& a, int s0, int n) {
+  if constexpr (Q < 16) {
+    const int s = s0 + Q;
+    if (s >= 1 && s < n) a.template step<Q>();
+    unroll16<Q + 1>(a, s0, n);
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void sum_row_in_order(double& len, double d) {
+  if constexpr (Q < 16) {
+    len += row_bcast_f64<Q>(d);
+    sum_row_in_order<Q + 1>(len, d);
+  }
+}
+
+template <bool STAGED, int G>
+__global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restrict__ insts,
+                                                         const BlockMap* __restrict__ map,
                                                          int ants_per_block) {
+  constexpr int R = WAVE / G;
   const BlockMap bm = map[blockIdx.x];
   if (bm.inst < 0) return;
-  const InstDesc& D = insts[bm.inst];
-  const int t = D.st->t;
-  if (t > D.iterations) return;
+  const InstDesc I = insts[bm.inst];  // by value: the fields stay in registers
+  const int t = I.st->t;
+  if (t > I.iterations) return;
   extern __shared__ uint32_t lds[];
-  const int n = D.n, k = D.k, lane = lane_id(), wave = threadIdx.x / WAVE;
+  const int n = I.n, k = I.k, lane = lane_id(), wave = threadIdx.x / WAVE;
   const int words2 = ((n + 63) >> 6) << 1;
   const int vis_words = ((words2 + 3) >> 2) << 2;
-  uint32_t* vis = lds + wave * vis_words;
-  const uint16_t* c16 = nullptr;
-  const float* wl = nullptr;
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const uint64_t* cw_lds = nullptr;
+  const double2* xy_lds = nullptr;
   if (STAGED) {
-    uint32_t* base = lds + ants_per_block * vis_words;
-    const int64_t nk = (int64_t)n * k;
-    const int c_vec = (int)((nk * 2 + 15) / 16);
-    const int w_vec = (int)((nk * 4 + 15) / 16);
-    uint4* dc = reinterpret_cast<uint4*>(base);
-    uint4* dw = reinterpret_cast<uint4*>(base + c_vec * 4);
-    const uint4* sc = reinterpret_cast<const uint4*>(D.cand16);
-    const uint4* sw = reinterpret_cast<const uint4*>(D.w);
-    for (int x = threadIdx.x; x < c_vec; x += blockDim.x) dc[x] = sc[x];
-    for (int x = threadIdx.x; x < w_vec; x += blockDim.x) dw[x] = sw[x];
-    c16 = reinterpret_cast<const uint16_t*>(dc);
-    wl = reinterpret_cast<const float*>(dw);
+    u32x4* dst = reinterpret_cast<u32x4*>(lds + ants_per_block * vis_words);
+    const HAC_AS1 u32x4* src = reinterpret_cast<const HAC_AS1 u32x4*>(as_global(I.cw));
+    const int vec = (n * k * 8 + 15) / 16;
+    for (int x = threadIdx.x; x < vec; x += blockDim.x) dst[x] = src[x];
+    cw_lds = reinterpret_cast<const uint64_t*>(dst);
+    if (I.xy) {
+      u32x4* dxy = dst + vec;
+      const HAC_AS1 u32x4* sxy = reinterpret_cast<const HAC_AS1 u32x4*>(as_global(I.xy));
+      for (int x = threadIdx.x; x < n; x += blockDim.x) dxy[x] = sxy[x];
+      xy_lds = reinterpret_cast<const double2*>(dxy);
+    }
     __syncthreads();
   }
-  const int ant = bm.ant0 + wave;
-  if (ant >= D.ants) return;
+  const int first_ant = bm.ant0 + wave * R;
+  if (first_ant >= I.ants) return;  // whole wave idle
 
-  for (int w = lane; w < vis_words; w += WAVE) {
-    int lo = w * 32;
-    uint32_t v = 0;
+  AntGroups<STAGED, G> A{};
+  A.n = n;
+  A.k = k;
+  A.kg = I.kg;
+  A.t = t;
+  A.lane = lane;
+  A.u = lane % G;
+  A.g = lane / G;
+  A.r16 = lane & 15;
+  const int my_ant = first_ant + A.g;
+  A.live = my_ant < I.ants;
+  const int ant = A.live ? my_ant : I.ants - 1;  // idle groups shadow a real ant, write nothing
+  A.cw_lds = cw_lds;
+  A.cw_g = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.cw));
+  A.xy_lds = xy_lds;
+  A.D = GDist(I);
+  A.geo = as_global(I.geo);
+  A.vis_words = vis_words;
+  A.vis_wave = lds + wave * R * vis_words;
+  A.vis_g = A.vis_wave + A.g * vis_words;
+
+  for (int w = lane; w < R * vis_words; w += WAVE) {
+    const int lo = (w % vis_words) * 32;
+    uint32_t v;
     if (lo + 32 <= n)
       v = 0;
     else if (lo >= n)
       v = 0xffffffffu;
     else
       v = ~((1u << (n - lo)) - 1u);
-    vis[w] = v;
+    A.vis_wave[w] = v;
   }
   __builtin_amdgcn_wave_barrier();
 
-  const uint32_t k0 = D.seed_lo, k1 = D.seed_hi;
-  // uniforms for steps 0..63, one per lane
-  uint64_t rnd = philox_u64((uint32_t)lane, (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
-  int cur = (int)__umul64hi(rd_lane_u64(rnd, 0), (uint64_t)n);
-  const int start = cur;
-  if (lane == 0) vis[cur >> 5] |= 1u << (cur & 31);
-  int tb = cur;        // lane (s & 63) holds T[s] of the current 64-step block
-  int carry = cur;     // last node of the previous block
+  const uint32_t k0 = I.seed_lo, k1 = I.seed_hi;
+  HAC_AS1 int32_t* my_tour = as_global(I.tours) + (int64_t)ant * n;
+  A.rnd = philox_u64((uint32_t)A.r16, (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
+  A.cur = (int)__umul64hi(row_bcast_u64<0>(A.rnd), (uint64_t)n);
+  const int start = A.cur;
+  if (A.u == 0) atomicOr(&A.vis_g[start >> 5], 1u << (start & 31));
+  A.tb = start;
+  A.fallbacks = 0;
+  int carry = start;  // T[s0 - 1]
   double len = 0.0;
-  uint32_t fallbacks = 0;
-  int32_t* my_tour = D.tours + (int64_t)ant * n;
-  const bool in_row = lane < k;
-
-  for (int s = 1; s < n; ++s) {
-    const int sl = s & 63;
-    if (sl == 0) rnd = philox_u64((uint32_t)(s + lane), (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
-    const int i = cur;
-    int c = 0;
-    uint32_t wb = 0;
-    if (in_row) {
-      const int64_t x = (int64_t)i * k + lane;
-      if (STAGED) {
-        c = c16[x];
-        wb = __float_as_uint(wl[x]);
+  for (int s0 = 0; s0 < n; s0 += 16) {
+    if (s0 > 0) A.rnd = philox_u64((uint32_t)(s0 + A.r16), (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
+    unroll16<0>(A, s0, n);
+    // write T[s0 .. s0+15] and add their incoming edges in step order
+    const int cnt = min(16, n - s0);
+    if (A.live && A.u < 16 && A.r16 < cnt) my_tour[s0 + A.r16] = A.tb;
+    int prev = (int)dpp_or0<0x111, 0xf>((uint32_t)A.tb);  // T[s - 1] from the lane below
+    if (A.r16 == 0) prev = carry;
+    double dl = 0.0;
+    if (A.r16 < cnt && s0 + A.r16 >= 1) {
+      if (STAGED && xy_lds) {
+        const double2 pa = xy_lds[prev], pb = xy_lds[A.tb];
+        const double dx = pa.x - pb.x, dy = pa.y - pb.y;
+        dl = sqrt(dx * dx + dy * dy);
       } else {
-        c = D.cand[x];
-        wb = __float_as_uint(D.w[x]);
+        dl = A.D.len(prev, A.tb);
       }
     }
-    const bool open = in_row && !((vis[c >> 5] >> (c & 31)) & 1u);
-    const uint64_t om = __ballot(open);
-    int j;
-    if (om) {
-      const uint32_t be = open ? (wb >> 23) : 0u;
-      const uint32_t be_max = wave_max_u32(be);
-      const int sh = (int)be - (int)be_max + 8;
-      const uint32_t m24 = (wb & 0x7fffffu) | 0x800000u;
-      uint32_t qv = sh >= 0 ? (m24 << sh) : (sh > -32 ? (m24 >> (-sh)) : 0u);
-      qv = qv < 1u ? 1u : qv;
-      const uint64_t pre = wave_scan_u64(open ? (uint64_t)qv : 0ull);
-      const uint64_t tot = rd_lane_u64(pre, 63);
-      const uint64_t r = __umul64hi(rd_lane_u64(rnd, sl), tot);
-      const uint64_t sm = __ballot(open && pre > r);
-      j = rd_lane(c, __ffsll((unsigned long long)sm) - 1);
-    } else {
-      j = nearest_unvisited(D, i, vis);
-      fallbacks++;
-    }
-    if (lane == 0) vis[j >> 5] |= 1u << (j & 31);
-    if (lane == sl) tb = j;
-    if (sl == 63 || s == n - 1) {
-      const int b0 = s & ~63;
-      if (lane <= sl) my_tour[b0 + lane] = tb;
-      int prev = __shfl_up(tb, 1);
-      if (lane == 0) prev = carry;
-      double d = 0.0;
-      if (lane <= sl && b0 + lane >= 1) d = edge_len(D, prev, tb);
-      for (int l = (b0 == 0 ? 1 : 0); l <= sl; ++l) len += rd_lane_d(d, l);
-      carry = rd_lane(tb, sl);
-    }
-    cur = j;
+    sum_row_in_order<0>(len, dl);  // adding 0.0 past the end leaves len unchanged
+    carry = A.cur;
   }
-  len += edge_len(D, carry, start);
-  if (lane == 0) {
-    D.lens[ant] = len;
-    if (fallbacks) atomicAdd(&D.st->fallbacks, (unsigned long long)fallbacks);
+  if (STAGED && xy_lds) {
+    const double2 pa = xy_lds[carry], pb = xy_lds[start];
+    const double dx = pa.x - pb.x, dy = pa.y - pb.y;
+    len += sqrt(dx * dx + dy * dy);
+  } else {
+    len += A.D.len(carry, start);
+  }
+  if (A.live && A.u == 0) {
+    I.lens[ant] = len;
+    if (A.fallbacks) atomicAdd(&I.st->fallbacks, (unsigned long long)A.fallbacks);
   }
 }
 
@@ -801,8 +1107,10 @@ __global__ void __launch_bounds__(1024) iter_end_kernel(const InstDesc* insts) {
     v = v + (on ? delta : 0.0f);
     v = fmaxf(tmin_f, v);
     v = fminf(tmax_f, v);
+    const float w = v * D.heur[x];
     D.tau[x] = v;
-    D.w[x] = v * D.heur[x];
+    D.w[x] = w;
+    D.cw[x].y = __float_as_uint(w);
   }
 
   // branching-factor restart
@@ -839,8 +1147,10 @@ __global__ void __launch_bounds__(1024) iter_end_kernel(const InstDesc* insts) {
     __syncthreads();
     if (s_restart) {
       for (int x = tid; x < nk; x += nthr) {
+        const float w = tmax_f * D.heur[x];
         D.tau[x] = tmax_f;
-        D.w[x] = tmax_f * D.heur[x];
+        D.w[x] = w;
+        D.cw[x].y = __float_as_uint(w);
       }
     }
   }
@@ -881,11 +1191,8 @@ int32_t max_lds_bytes() { return 160 * 1024; }
 size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t staged) {
   const size_t words2 = (size_t)(((n + 63) >> 6) << 1);
   const size_t vis_words = ((words2 + 3) >> 2) << 2;
-  size_t bytes = (size_t)ants_per_block * vis_words * 4;
-  if (staged) {
-    const size_t nk = (size_t)n * k;
-    bytes += ((nk * 2 + 15) / 16) * 16 + ((nk * 4 + 15) / 16) * 16;
-  }
+  size_t bytes = (size_t)ants_per_block * vis_words * 4;  // ants_per_block is a multiple of 64/G
+  if (staged) bytes += (((size_t)n * k * 8 + 15) / 16) * 16 + (size_t)16 * n;
   return bytes;
 }
 
@@ -916,15 +1223,27 @@ hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
+int32_t construct_group_lanes(int32_t max_k) { return max_k <= 16 ? 16 : (max_k <= 32 ? 32 : 64); }
+
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
-                            int32_t ants_per_block, int32_t staged, size_t lds_bytes,
+                            int32_t ants_per_block, int32_t staged, int32_t lanes, size_t lds_bytes,
                             hipStream_t s) {
-  if (staged)
-    hipLaunchKernelGGL(construct_kernel<true>, dim3(blocks), dim3(ants_per_block * WAVE), lds_bytes,
-                       s, d_insts, d_map, ants_per_block);
-  else
-    hipLaunchKernelGGL(construct_kernel<false>, dim3(blocks), dim3(ants_per_block * WAVE),
-                       lds_bytes, s, d_insts, d_map, ants_per_block);
+  const int G = lanes;
+  const int waves = (ants_per_block * G + WAVE - 1) / WAVE;
+  const dim3 grid(blocks), block(waves * WAVE);
+#define HAC_LAUNCH(ST, GL)                                                                 \
+  hipLaunchKernelGGL((construct_kernel<ST, GL>), grid, block, lds_bytes, s, d_insts, d_map, \
+                     ants_per_block)
+  if (staged) {
+    if (G == 16) HAC_LAUNCH(true, 16);
+    else if (G == 32) HAC_LAUNCH(true, 32);
+    else HAC_LAUNCH(true, 64);
+  } else {
+    if (G == 16) HAC_LAUNCH(false, 16);
+    else if (G == 32) HAC_LAUNCH(false, 32);
+    else HAC_LAUNCH(false, 64);
+  }
+#undef HAC_LAUNCH
   return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ class DeviceArena {
 // Sizes of the device arrays of one instance.
 struct Layout {
   int32_t n, k, kg, kls, ants, iterations;
-  bool coords, ls, staged16;
+  bool coords, ls;
   int64_t nnz;
   size_t bytes() const;
 };
@@ -57,10 +57,12 @@ struct HostInst {
   hac_csr dev_csr{};
 };
 
-// Chosen construction launch shape.
+// Chosen construction launch shape: ants per block (whole waves), LDS
+// staging of the candidate table, and lanes per ant (16, 32 or 64).
 struct LaunchShape {
   int32_t ants_per_block;
   int32_t staged;
+  int32_t lanes;
 };
 
 // One decode batch: everything from uploaded inputs to results.
@@ -72,7 +74,7 @@ struct Engine {
   // results of the last run
   double construct_ms = 0.0;
   int64_t construct_launches = 0;
-  LaunchShape shape{4, 0};
+  LaunchShape shape{4, 0, 64};
 };
 
 hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_params* p,
@@ -98,6 +100,8 @@ void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve);
 void fill_desc_scalars(HostInst& h);
 size_t align256(size_t bytes);
 size_t shape_lds(const std::vector<HostInst>& hs, LaunchShape sh);
+// largest candidate-list width of a batch (selects the reduction width)
+int32_t batch_max_k(const std::vector<HostInst>& hs);
 
 // Copies the host inputs of h into its slot (asynchronous on s).
 hipError_t upload_inputs(const HostInst& h, hipStream_t s);

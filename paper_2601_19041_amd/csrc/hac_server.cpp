@@ -182,7 +182,7 @@ void serve_loop(hac_server* S) {
   hipStream_t s = S->stream;
   std::vector<BlockMap> map;
   bool dirty = true;
-  LaunchShape shape{1, 0};
+  LaunchShape shape{1, 0, 64};
   InstDesc* d_descs = nullptr;
   int32_t** d_outs = nullptr;
   double* d_lens = nullptr;
@@ -339,7 +339,7 @@ void serve_loop(hac_server* S) {
     bool ok = true;
     for (int32_t r = 0; ok && r < rounds; ++r) {
       ok = hip_ok(S, launch_construct(d_descs, d_map, (int32_t)map.size(), shape.ants_per_block,
-                                      shape.staged, lds, s), "construct");
+                                      shape.staged, shape.lanes, lds, s), "construct");
       if (ok && any_ls) ok = hip_ok(S, launch_local_search(d_descs, m, max_n, s), "local search");
       if (ok) ok = hip_ok(S, launch_iter_end(d_descs, m, s), "iter end");
     }
