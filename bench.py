@@ -98,45 +98,30 @@ def traffic_from_profile(kernel_src_hash: str, launches_key: str):
         return None
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batch64", choices=["batch64"])
-    ap.add_argument("--iterations", type=int, default=500)
-    ap.add_argument("--plain-sample", type=int, default=16)
-    ap.add_argument("--cpu-sample", type=int, default=16)
-    ap.add_argument("--cpu-iterations", type=int, default=100)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the decoder runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def roofline(insts, cms, launches):
+    """Construction kernel: one launch = one iteration of every instance."""
+    bytes_per_launch = sum(x.ants * (x.n - 1) * construct_bytes_per_step(x.k, x.kind) for x in insts)
+    avg_launch_s = (cms / 1000.0) / max(launches, 1)
+    achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    src = open(os.path.join(ROOT, "paper_2601_19041_amd", "csrc", "hac_kernels.hip"), "rb").read()
+    return {"bound": "hbm", "kernel": "construct_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_from_profile(hashlib.sha256(src).hexdigest(), "batch64"),
+            "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
+            "algorithmic_bytes_per_launch": bytes_per_launch}
 
-    from paper_2601_19041_amd import workloads as wl
 
-    insts = wl.batch64(64, iterations=args.iterations)
-    count = len(insts)
-    # the CPU leg runs first, before this process initialises the GPU
-    cpu = None if args.no_cpu else cpu_baseline(insts, args.cpu_sample, args.cpu_iterations)
-
+def timed_batches(ctx, db, steps, warmup):
+    """Warmup, then `steps` timed hac_decode_batch_dev calls with per-launch
+    HIP-event timing of the construction kernel."""
     import torch
-    import paper_2601_19041_amd as hac
-
-    ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
-    ctx = hac.Context(0)
-    db = hac.DeviceBatch(insts)
-
-    # warmup (also runs the launch-shape autotuner once)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         ctx.decode_batch_dev(db)
     ctx.set_timing(True)
     torch.cuda.synchronize()
     times, cms, launches = [], 0.0, 0
     t_all = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         t0 = time.perf_counter()
         ctx.decode_batch_dev(db)
         times.append(time.perf_counter() - t0)
@@ -146,62 +131,202 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_all
     ctx.set_timing(False)
-    batched = db.results()
-    ms_per_step = 1000.0 * wall / args.steps
-    value = ant_steps * args.steps / wall
-    decodes_per_s = count * args.steps / wall
+    return wall, times, cms, launches
 
-    # roofline of the construction kernel: one launch = one iteration of
-    # every instance's ants
-    bytes_per_launch = sum(x.ants * (x.n - 1) * construct_bytes_per_step(x.k, x.kind) for x in insts)
-    avg_launch_s = (cms / 1000.0) / max(launches, 1)
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    src = open(os.path.join(ROOT, "paper_2601_19041_amd", "csrc", "hac_kernels.hip"), "rb").read()
-    traffic = traffic_from_profile(hashlib.sha256(src).hexdigest(), "batch64")
 
-    # plain path: the same instances, one decode per call
-    plain_lat = []
-    gap_equal = True
-    for x in range(min(args.plain_sample, count)):
+def plain_sample(ctx, insts, count, batched=None):
+    lat, equal = [], True
+    for x in range(min(count, len(insts))):
         t0 = time.perf_counter()
         tour, L = ctx.decode(insts[x])
-        plain_lat.append(time.perf_counter() - t0)
-        gap_equal &= bool(np.array_equal(tour, batched[x][0]) and L == batched[x][1])
-    assert gap_equal, "plain and batched tours differ"
-    plain_dps = len(plain_lat) / sum(plain_lat)
-    plain_steps = sum(insts[x].ants * (insts[x].n - 1) * insts[x].iterations for x in range(len(plain_lat)))
+        lat.append(time.perf_counter() - t0)
+        if batched is not None:
+            equal &= bool(np.array_equal(tour, batched[x][0]) and L == batched[x][1])
+    steps = sum(insts[x].ants * (insts[x].n - 1) * insts[x].iterations for x in range(len(lat)))
+    return lat, steps, equal
 
-    out = {
-        "metric": "ant-steps/s, batched decode of 64 TSP instances (n 500-1000)",
-        "value": value,
-        "unit": "ant-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "batch64: 64 TSP instances, n uniform on [500,1000], top-10 SoftDist "
-                               "heatmaps, k=10, 50 ants, 500 iterations, no local search",
-                   "instances": count, "iterations": args.iterations, "ants": 50, "k": 10,
-                   "inputs": "resident in HBM (hac_decode_batch_dev)"},
-        "decodes_per_s": decodes_per_s,
-        "plain": {"decodes_per_s": plain_dps, "ant_steps_per_s": plain_steps / sum(plain_lat),
-                  "sample": len(plain_lat)},
-        "batched_vs_plain": decodes_per_s / plain_dps,
-        "equal_gap": gap_equal,
+
+def base_line(args, metric, value, ms_per_step, config):
+    return {"metric": metric, "value": value, "unit": "ant-steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic", "config": config}
+
+
+def run_batched(args, hac, insts, cpu, name, desc, plain_count):
+    count = len(insts)
+    ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
+    ctx = hac.Context(0)
+    db = hac.DeviceBatch(insts)
+    wall, times, cms, launches = timed_batches(ctx, db, args.steps, args.warmup)
+    batched = db.results()
+    st = ctx.stats()
+    lat, psteps, equal = plain_sample(ctx, insts, plain_count, batched)
+    assert equal, "plain and batched tours differ"
+    plain_dps = len(lat) / sum(lat)
+    dps = count * args.steps / wall
+    out = base_line(args, f"ant-steps/s, batched decode ({name})", ant_steps * args.steps / wall,
+                    1000.0 * wall / args.steps,
+                    {"workload": desc, "instances": count, "iterations": insts[0].iterations,
+                     "ants": insts[0].ants, "k": insts[0].k, "inputs": "resident in HBM (hac_decode_batch_dev)",
+                     "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
+                                      "lanes_per_ant": st["lanes_per_ant"]}})
+    out.update({
+        "decodes_per_s": dps,
+        "plain": {"decodes_per_s": plain_dps, "ant_steps_per_s": psteps / sum(lat), "sample": len(lat)},
+        "batched_vs_plain": dps / plain_dps,
+        "equal_gap": equal,
         "latency_ms": {"batched_p50": 1000 * percentile(times, 0.5), "batched_p99": 1000 * percentile(times, 0.99),
-                       "plain_p50": 1000 * percentile(plain_lat, 0.5), "plain_p99": 1000 * percentile(plain_lat, 0.99)},
-        "roofline": {"bound": "hbm", "kernel": "construct_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
-    }
-    out["cpu_baseline"] = cpu
+                       "plain_p50": 1000 * percentile(lat, 0.5), "plain_p99": 1000 * percentile(lat, 0.99)},
+        "fallback_fraction": st["fallback_steps"] / max(1, st["ant_steps"]),
+        "roofline": roofline(insts, cms, launches),
+        "cpu_baseline": cpu,
+    })
     ctx.close()
+    return out
+
+
+def run_plain(args, hac, inst, cpu, name, desc):
+    ctx = hac.Context(0)
+    db = hac.DeviceBatch([inst])
+    wall, times, cms, launches = timed_batches(ctx, db, args.steps, args.warmup)
+    steps = inst.ants * (inst.n - 1) * inst.iterations
+    st = ctx.stats()
+    out = base_line(args, f"ant-steps/s, plain decode ({name})", steps * args.steps / wall,
+                    1000.0 * wall / args.steps,
+                    {"workload": desc, "instances": 1, "iterations": inst.iterations, "ants": inst.ants,
+                     "k": inst.k, "inputs": "resident in HBM",
+                     "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
+                                      "lanes_per_ant": st["lanes_per_ant"]}})
+    out.update({"decodes_per_s": args.steps / wall,
+                "latency_ms": {"p50": 1000 * percentile(times, 0.5), "p99": 1000 * percentile(times, 0.99)},
+                "fallback_fraction": st["fallback_steps"] / max(1, st["ant_steps"]),
+                "roofline": roofline([inst], cms, launches), "cpu_baseline": cpu})
+    ctx.close()
+    return out
+
+
+def run_serve(args, hac, wl, cpu):
+    """Poisson arrivals of the 40/40/10/10 mix; the rate is 0.7 x the
+    saturated throughput measured by a closed-loop calibration."""
+    kinds = ["tsp500", "tsp1000", "tsp10000", "atsp1000"]
+    count = args.requests
+    mix, _ = wl.serve_mix(count, 1.0, seed=1)
+    reqs = [wl.serve_request(k, r) for r, k in enumerate(mix)]
+    ctx = hac.Context(0)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    # calibration: the whole request set submitted at once (closed loop)
+    srv = hac.Server(ctx, budget=budget, max_slots=args.slots)
+    t0 = time.perf_counter()
+    tk = [srv.submit(r) for r in reqs]
+    for t in tk:
+        srv.wait(t)
+    sat = len(tk) / (time.perf_counter() - t0)
+    srv.close()
+    rate = 0.7 * sat
+    _, arrivals = wl.serve_mix(count, rate, seed=2)
+    srv = hac.Server(ctx, budget=budget, max_slots=args.slots)
+    t_start = time.perf_counter()
+    tickets = []
+    for r, at in zip(reqs, arrivals):
+        now = time.perf_counter() - t_start
+        if at > now:
+            time.sleep(at - now)
+        tickets.append(srv.submit(r))
+    lat = []
+    results = []
+    for t in tickets:
+        tour, L, l = srv.wait(t)
+        lat.append(l)
+        results.append((tour, L))
+    wall = time.perf_counter() - t_start
+    cnt = srv.counters()
+    srv.close()
+    ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in reqs)
+    # the plain path on the same mix: one request of each kind decoded alone
+    # (and checked against its served result), weighted by the mix fractions
+    frac = {"tsp500": 0.4, "tsp1000": 0.4, "tsp10000": 0.1, "atsp1000": 0.1}
+    per_kind, equal = {}, True
+    for kind in kinds:
+        idx = next((r for r, k in enumerate(mix) if k == kind), None)
+        if idx is None:
+            continue
+        t0 = time.perf_counter()
+        tour, L = ctx.decode(reqs[idx])
+        per_kind[kind] = time.perf_counter() - t0
+        equal &= bool(np.array_equal(tour, results[idx][0]) and L == results[idx][1])
+    assert equal, "served and plain tours differ"
+    ctx.close()
+    mean_plain_s = sum(frac[k] * t for k, t in per_kind.items()) / sum(frac[k] for k in per_kind)
+    plain_dps = 1.0 / mean_plain_s
+    plain_lat = list(per_kind.values())
+    out = base_line(args, "ant-steps/s, served decode (Poisson mix)", ant_steps / wall, 1000.0 * wall,
+                    {"workload": f"serve: {count} requests, 40/40/10/10 TSP500/TSP1000/TSP10000/ATSP1000, "
+                                 f"100 iterations each, Poisson arrivals at {rate:.2f}/s",
+                     "budget_gb": args.serve_budget_gb, "max_slots": args.slots})
+    out["steps"] = 1
+    out.update({"decodes_per_s": count / wall, "latency_ms": {"p50": 1000 * percentile(lat, 0.5),
+                                                             "p99": 1000 * percentile(lat, 0.99)},
+                "plain": {"decodes_per_s": plain_dps, "seconds_per_kind": per_kind,
+                          "note": "one request per kind decoded alone, weighted by the mix"},
+                "served_vs_plain": (count / wall) / plain_dps, "equal_gap": equal,
+                "saturated_decodes_per_s": sat, "arrival_rate_per_s": rate,
+                "server": cnt, "cpu_baseline": cpu})
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve"])
+    ap.add_argument("--iterations", type=int, default=None, help="override the workload's iteration count")
+    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-iterations", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the decoder runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2601_19041_amd import workloads as wl
+
+    it = args.iterations
+    if args.workload == "batch64":
+        insts = wl.batch64(64, iterations=it or 500)
+    elif args.workload == "tsp100":
+        insts = [wl.tsp100(iterations=it or 100)]
+    elif args.workload == "tsp500":
+        insts = [wl.tsp500(iterations=it or 1000)]
+    elif args.workload == "tsp10k":
+        insts = wl.tsp10k(8, iterations=it or 200)
+    else:
+        insts = [wl.serve_request("tsp500", 0)]
+    # the CPU leg runs first, before this process initialises the GPU
+    cpu = None if args.no_cpu else cpu_baseline(insts, args.cpu_sample, args.cpu_iterations)
+
+    import paper_2601_19041_amd as hac
+
+    if args.workload == "batch64":
+        out = run_batched(args, hac, insts, cpu, "64 TSP instances, n 500-1000",
+                          "batch64: 64 TSP instances, n uniform on [500,1000], top-10 SoftDist heatmaps, "
+                          "k=10, 50 ants, 500 iterations, no local search", args.plain_sample)
+    elif args.workload == "tsp10k":
+        out = run_batched(args, hac, insts, cpu, "8 TSP instances, n 10000, 2-opt",
+                          "tsp10k: 8 TSP instances, n=10000, top-20 heatmaps, k=20, 100 ants, 200 iterations, "
+                          "neighbour-list 2-opt (20) on each iteration best", min(args.plain_sample, 1))
+    elif args.workload == "serve":
+        out = run_serve(args, hac, wl, cpu)
+    else:
+        x = insts[0]
+        out = run_plain(args, hac, x, cpu, f"TSP n={x.n}",
+                        f"{args.workload}: one TSP instance, n={x.n}, k={x.k}, {x.ants} ants, "
+                        f"{x.iterations} iterations, no local search")
     print(json.dumps(out))
 
 

@@ -1,16 +1,20 @@
 // Continuous-batching request loop.
 //
-// A loop thread owns a device memory pool of `budget` bytes and up to
-// `max_slots` admitted instances.  Between rounds of iterations it admits
-// queued requests whose footprint fits a free block of the pool (first
-// fit, in arrival order), prepares them on the device, and then advances
-// every admitted instance together: each round launches the construction,
-// local-search and end-of-iteration kernels once per iteration over the
-// whole admitted set.  An instance whose iterations are done is retired:
-// its best tour is copied out, its pool block freed, its waiters woken.
-// Instances never leave the device between admission and retirement.
-// Every instance runs exactly the kernels and per-instance state of the
-// plain path, so a served result equals hac_decode's bit for bit.
+// The server owns a device memory pool of `budget` bytes and admits at most
+// `max_slots` instances at a time.  Requests are split into size classes
+// (lanes); each lane has its own loop thread and HIP stream, so a large
+// instance's long iterations do not pace the small ones: their kernels run
+// concurrently on the device.  Between rounds of iterations a lane admits
+// queued requests of its class whose footprint fits a free block of the
+// shared pool (first fit, in arrival order), prepares them on the device,
+// and then advances every instance it holds together: each round launches
+// the construction, local-search and end-of-iteration kernels once per
+// iteration over the lane's admitted set.  An instance whose iterations are
+// done is retired: its best tour is copied out, its pool block freed, its
+// waiters woken.  Instances never leave the device between admission and
+// retirement.  Every instance runs exactly the kernels and per-instance
+// state of the plain path, so a served result equals hac_decode's bit for
+// bit.
 
 #include <hip/hip_runtime.h>
 
@@ -96,6 +100,7 @@ enum ReqState { QUEUED, RUNNING, DONE, CANCELLED, FAILED };
 
 struct Request {
   uint64_t ticket = 0;
+  int lane = 0;
   std::vector<double> coords, dist;
   std::vector<int32_t> row_ptr, col;
   std::vector<float> val;
@@ -125,20 +130,32 @@ struct Slot {
 
 using namespace hac;
 
+// One size class of requests with its own loop thread and stream.
+struct Lane {
+  int id = 0;
+  hipStream_t stream = nullptr;
+  DeviceArena meta, mapa, scratch;  // descriptor arrays, block map, tuner scratch
+  std::vector<Slot> active;
+  std::thread loop;
+};
+
+// requests with at least this many nodes run in the large-instance lane
+static constexpr int32_t kLargeN = 4096;
+static constexpr int kLanes = 2;
+
 struct hac_server {
   hac_ctx* ctx = nullptr;
   int device = 0;
   uint64_t budget = 0;
   int32_t max_slots = 0;
-  hipStream_t stream = nullptr;
   Pool pool;
-  DeviceArena meta, mapa, scratch;  // descriptor arrays, block map, tuner scratch
+  Lane lanes[kLanes];
   std::mutex mu;
   std::condition_variable cv_done, cv_loop;
   std::deque<std::shared_ptr<Request>> queue;
   std::map<uint64_t, std::shared_ptr<Request>> reqs;
-  std::vector<Slot> active;
-  std::thread loop;
+  int32_t active_total = 0;
+  uint64_t gen = 0;  // bumped on every submission, release and cancel
   bool stop = false;
   uint64_t next_ticket = 1;
   int64_t admitted = 0, completed = 0;
@@ -160,15 +177,18 @@ void finish_request(hac_server* S, const std::shared_ptr<Request>& r, ReqState s
   S->completed += (st == DONE);
 }
 
-// Marks every admitted instance failed after a device error.
-void fail_active(hac_server* S, hac_status code) {
+// Marks every instance of a lane failed after a device error.
+void fail_active(hac_server* S, Lane& LN, hac_status code) {
   std::lock_guard<std::mutex> g(S->mu);
-  for (auto& s : S->active) {
+  for (auto& s : LN.active) {
     finish_request(S, s.req, FAILED, code);
     S->pool.release((size_t)s.off, s.req->bytes);
   }
-  S->active.clear();
+  S->active_total -= (int32_t)LN.active.size();
+  LN.active.clear();
+  S->gen++;
   S->cv_done.notify_all();
+  S->cv_loop.notify_all();
 }
 
 bool hip_ok(hac_server* S, hipError_t e, const char* what) {
@@ -177,9 +197,10 @@ bool hip_ok(hac_server* S, hipError_t e, const char* what) {
   return false;
 }
 
-void serve_loop(hac_server* S) {
+void serve_lane(hac_server* S, Lane* lane_ptr) {
+  Lane& LN = *lane_ptr;
   (void)hipSetDevice(S->device);
-  hipStream_t s = S->stream;
+  hipStream_t s = LN.stream;
   std::vector<BlockMap> map;
   bool dirty = true;
   LaunchShape shape{1, 0, 64};
@@ -194,30 +215,46 @@ void serve_loop(hac_server* S) {
     std::vector<Slot> fresh;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_loop.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
-      if (S->stop && S->active.empty()) break;
-      for (auto it = S->queue.begin(); it != S->queue.end();) {
-        auto& r = *it;
-        if (r->cancel) {
-          finish_request(S, r, CANCELLED, HAC_ECANCELLED);
+      bool quit = false;
+      for (;;) {
+        if (S->stop && LN.active.empty()) {
+          quit = true;
+          break;
+        }
+        for (auto it = S->queue.begin(); it != S->queue.end();) {
+          auto& r = *it;
+          if (r->lane != LN.id) {
+            ++it;
+            continue;
+          }
+          if (r->cancel) {
+            finish_request(S, r, CANCELLED, HAC_ECANCELLED);
+            it = S->queue.erase(it);
+            S->gen++;
+            S->cv_done.notify_all();
+            continue;
+          }
+          if (S->active_total + (int32_t)fresh.size() >= S->max_slots || S->stop) break;
+          int64_t off = S->pool.alloc(r->bytes);
+          if (off < 0) {
+            ++it;
+            continue;
+          }
+          Slot sl;
+          sl.req = r;
+          sl.off = off;
+          r->state = RUNNING;
+          fresh.push_back(std::move(sl));
+          S->admitted++;
           it = S->queue.erase(it);
-          S->cv_done.notify_all();
-          continue;
         }
-        if ((int32_t)(S->active.size() + fresh.size()) >= S->max_slots || S->stop) break;
-        int64_t off = S->pool.alloc(r->bytes);
-        if (off < 0) {
-          ++it;
-          continue;
-        }
-        Slot sl;
-        sl.req = r;
-        sl.off = off;
-        r->state = RUNNING;
-        fresh.push_back(std::move(sl));
-        S->admitted++;
-        it = S->queue.erase(it);
+        if (!fresh.empty() || !LN.active.empty()) break;
+        // nothing to run: sleep until a submission, release or stop
+        const uint64_t seen = S->gen;
+        S->cv_loop.wait(lk, [&] { return S->stop || S->gen != seen; });
       }
+      if (quit) break;
+      S->active_total += (int32_t)fresh.size();
     }
     // ---- preparation of the newly admitted instances ----
     if (!fresh.empty()) {
@@ -246,9 +283,9 @@ void serve_loop(hac_server* S) {
         fill_desc_scalars(h);
       }
       bool ok = true;
-      S->scratch.reset();
-      ok = hip_ok(S, S->scratch.reserve(align256(sizeof(InstDesc) * hs.size())), "scratch");
-      InstDesc* d_new = ok ? (InstDesc*)S->scratch.carve(sizeof(InstDesc) * hs.size()) : nullptr;
+      LN.scratch.reset();
+      ok = hip_ok(S, LN.scratch.reserve(align256(sizeof(InstDesc) * hs.size())), "scratch");
+      InstDesc* d_new = ok ? (InstDesc*)LN.scratch.carve(sizeof(InstDesc) * hs.size()) : nullptr;
       for (size_t x = 0; ok && x < hs.size(); ++x) ok = hip_ok(S, upload_inputs(hs[x], s), "upload");
       if (ok) {
         std::vector<InstDesc> dd(hs.size());
@@ -267,36 +304,41 @@ void serve_loop(hac_server* S) {
         if (!ok || ps != HAC_OK) {
           finish_request(S, fresh[x].req, FAILED, ok ? ps : HAC_EDEVICE);
           S->pool.release((size_t)fresh[x].off, fresh[x].req->bytes);
+          S->active_total -= 1;
+          S->gen++;
           continue;
         }
         fresh[x].h = hs[x];
         fresh[x].h.cand_h.clear();
-        S->active.push_back(std::move(fresh[x]));
+        LN.active.push_back(std::move(fresh[x]));
         dirty = true;
       }
-      S->peak_slots = std::max(S->peak_slots, (int32_t)S->active.size());
-      if (!ok || ps != HAC_OK) S->cv_done.notify_all();
+      S->peak_slots = std::max(S->peak_slots, S->active_total);
+      if (!ok || ps != HAC_OK) {
+        S->cv_done.notify_all();
+        S->cv_loop.notify_all();
+      }
     }
-    if (S->active.empty()) continue;
+    if (LN.active.empty()) continue;
 
     // ---- a round of iterations over the admitted set ----
-    const int32_t m = (int32_t)S->active.size();
+    const int32_t m = (int32_t)LN.active.size();
     std::vector<HostInst> hs;
     hs.reserve(m);
-    for (auto& sl : S->active) hs.push_back(sl.h);
+    for (auto& sl : LN.active) hs.push_back(sl.h);
     if (dirty) {
       // descriptors first: the tuner times real construction launches
-      bool ok = hip_ok(S, S->meta.reserve(align256(sizeof(InstDesc) * m) + align256(sizeof(int32_t*) * m) +
+      bool ok = hip_ok(S, LN.meta.reserve(align256(sizeof(InstDesc) * m) + align256(sizeof(int32_t*) * m) +
                                           align256(8 * (size_t)m)), "meta");
       if (ok) {
-        d_descs = (InstDesc*)S->meta.carve(sizeof(InstDesc) * m);
-        d_outs = (int32_t**)S->meta.carve(sizeof(int32_t*) * m);
-        d_lens = (double*)S->meta.carve(8 * (size_t)m);
+        d_descs = (InstDesc*)LN.meta.carve(sizeof(InstDesc) * m);
+        d_outs = (int32_t**)LN.meta.carve(sizeof(int32_t*) * m);
+        d_lens = (double*)LN.meta.carve(8 * (size_t)m);
         std::vector<InstDesc> dd(m);
         std::vector<int32_t*> outs(m);
         for (int32_t x = 0; x < m; ++x) {
-          dd[x] = S->active[x].h.d;
-          outs[x] = S->active[x].d_tour;
+          dd[x] = LN.active[x].h.d;
+          outs[x] = LN.active[x].d_tour;
         }
         ok = hip_ok(S, hipMemcpyAsync(d_descs, dd.data(), sizeof(InstDesc) * m, hipMemcpyHostToDevice, s), "descs") &&
              hip_ok(S, hipMemcpyAsync(d_outs, outs.data(), sizeof(int32_t*) * m, hipMemcpyHostToDevice, s), "outs");
@@ -304,34 +346,34 @@ void serve_loop(hac_server* S) {
       if (ok) {
         // construction only reads the search state, so timing it here
         // leaves every instance's trajectory unchanged
-        shape = tune_shape(hs, d_descs, s, S->scratch, &ok);
+        shape = tune_shape(hs, d_descs, s, LN.scratch, &ok);
         if (!ok) S->err = "autotuner launch failed";
       }
       if (ok) {
         map = build_block_map(hs, shape.ants_per_block);
-        ok = hip_ok(S, S->mapa.reserve(sizeof(BlockMap) * map.size()), "map");
+        ok = hip_ok(S, LN.mapa.reserve(sizeof(BlockMap) * map.size()), "map");
         if (ok) {
-          d_map = (BlockMap*)S->mapa.carve(sizeof(BlockMap) * map.size());
+          d_map = (BlockMap*)LN.mapa.carve(sizeof(BlockMap) * map.size());
           ok = hip_ok(S, hipMemcpyAsync(d_map, map.data(), sizeof(BlockMap) * map.size(), hipMemcpyHostToDevice, s), "map");
         }
       }
       if (!ok) {
-        fail_active(S, HAC_EDEVICE);
+        fail_active(S, LN, HAC_EDEVICE);
         continue;
       }
       dirty = false;
     }
     int32_t remaining = 1 << 30, max_n = 0;
     bool any_ls = false;
-    for (auto& sl : S->active) {
+    for (auto& sl : LN.active) {
       remaining = std::min(remaining, sl.h.p.iterations - sl.done_iters);
       max_n = std::max(max_n, sl.h.lay.n);
       any_ls |= sl.h.p.local_search != 0;
     }
-    bool queued;
+    bool queued = false;
     {
       std::lock_guard<std::mutex> g(S->mu);
-      queued = !S->queue.empty();
+      for (auto& r : S->queue) queued |= r->lane == LN.id;
     }
     // short rounds while requests wait, so they join soon
     const int32_t rounds = std::max(0, std::min(remaining, queued ? 2 : 8));
@@ -348,11 +390,11 @@ void serve_loop(hac_server* S) {
     if (ok) ok = hip_ok(S, hipMemcpyAsync(lens.data(), d_lens, 8 * (size_t)m, hipMemcpyDeviceToHost, s), "lens");
     std::vector<int32_t> finished;
     for (int32_t x = 0; x < m; ++x) {
-      S->active[x].done_iters += rounds;
-      if (S->active[x].done_iters >= S->active[x].h.p.iterations) finished.push_back(x);
+      LN.active[x].done_iters += rounds;
+      if (LN.active[x].done_iters >= LN.active[x].h.p.iterations) finished.push_back(x);
     }
     for (int32_t x : finished) {
-      Slot& sl = S->active[x];
+      Slot& sl = LN.active[x];
       sl.req->tour.resize(sl.h.lay.n);
       if (ok)
         ok = hip_ok(S, hipMemcpyAsync(sl.req->tour.data(), sl.d_tour, 4 * (size_t)sl.h.lay.n,
@@ -360,14 +402,14 @@ void serve_loop(hac_server* S) {
     }
     if (ok) ok = hip_ok(S, hipStreamSynchronize(s), "sync");
     if (!ok) {
-      fail_active(S, HAC_EDEVICE);
+      fail_active(S, LN, HAC_EDEVICE);
       continue;
     }
     // ---- retirement ----
     std::lock_guard<std::mutex> g(S->mu);
     std::vector<Slot> keep;
     for (int32_t x = 0; x < m; ++x) {
-      Slot& sl = S->active[x];
+      Slot& sl = LN.active[x];
       const bool fin = std::find(finished.begin(), finished.end(), x) != finished.end();
       if (fin || sl.req->cancel || S->stop) {
         if (fin && !sl.req->cancel) {
@@ -377,18 +419,27 @@ void serve_loop(hac_server* S) {
           finish_request(S, sl.req, CANCELLED, HAC_ECANCELLED);
         }
         S->pool.release((size_t)sl.off, sl.req->bytes);
+        S->active_total -= 1;
+        S->gen++;
         dirty = true;
       } else {
         keep.push_back(std::move(sl));
       }
     }
-    S->active.swap(keep);
+    LN.active.swap(keep);
     S->cv_done.notify_all();
+    S->cv_loop.notify_all();  // freed memory or slots may admit another lane's request
   }
-  // drain: cancel whatever is still queued
+  // drain: cancel whatever of this class is still queued
   std::lock_guard<std::mutex> g(S->mu);
-  for (auto& r : S->queue) finish_request(S, r, CANCELLED, HAC_ECANCELLED);
-  S->queue.clear();
+  for (auto it = S->queue.begin(); it != S->queue.end();) {
+    if ((*it)->lane == LN.id) {
+      finish_request(S, *it, CANCELLED, HAC_ECANCELLED);
+      it = S->queue.erase(it);
+    } else {
+      ++it;
+    }
+  }
   S->cv_done.notify_all();
 }
 
@@ -428,17 +479,21 @@ hac_status hac_server_create(hac_ctx* ctx, uint64_t budget_bytes, int32_t max_sl
   S->device = dev;
   S->budget = budget_bytes;
   S->max_slots = max_slots;
-  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
-    delete S;
-    return HAC_EDEVICE;
+  for (int l = 0; l < kLanes; ++l) {
+    S->lanes[l].id = l;
+    if (hipStreamCreateWithFlags(&S->lanes[l].stream, hipStreamNonBlocking) != hipSuccess) {
+      for (int q = 0; q < l; ++q) (void)hipStreamDestroy(S->lanes[q].stream);
+      delete S;
+      return HAC_EDEVICE;
+    }
   }
   hipError_t e = S->pool.init(budget_bytes);
   if (e != hipSuccess) {
-    (void)hipStreamDestroy(S->stream);
+    for (int l = 0; l < kLanes; ++l) (void)hipStreamDestroy(S->lanes[l].stream);
     delete S;
     return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HAC_ENOMEM : HAC_EDEVICE;
   }
-  S->loop = std::thread(serve_loop, S);
+  for (int l = 0; l < kLanes; ++l) S->lanes[l].loop = std::thread(serve_lane, S, &S->lanes[l]);
   *out = S;
   return HAC_OK;
 }
@@ -467,6 +522,7 @@ hac_status hac_server_submit(hac_server* S, const hac_instance* inst, const hac_
   r->csr.val = r->val.data();
   r->p = *p;
   r->seed = seed;
+  r->lane = n >= kLargeN ? 1 : 0;
   r->bytes = footprint_of(inst, heat, p);
   r->t_submit = Clock::now();
   if (r->bytes > S->budget) return HAC_ENOMEM;
@@ -482,6 +538,7 @@ hac_status hac_server_submit(hac_server* S, const hac_instance* inst, const hac_
   } else {
     S->queue.push_back(r);
   }
+  S->gen++;
   S->reqs[r->ticket] = r;
   *ticket = r->ticket;
   S->cv_loop.notify_all();
@@ -508,6 +565,7 @@ hac_status hac_server_cancel(hac_server* S, uint64_t ticket) {
   auto it = S->reqs.find(ticket);
   if (it == S->reqs.end()) return HAC_EINVAL;
   it->second->cancel = true;
+  S->gen++;
   S->cv_loop.notify_all();
   return HAC_OK;
 }
@@ -528,12 +586,17 @@ void hac_server_destroy(hac_server* S) {
   {
     std::lock_guard<std::mutex> g(S->mu);
     S->stop = true;
-    for (auto& sl : S->active) sl.req->cancel = true;
+    S->gen++;
+    for (auto& ln : S->lanes)
+      for (auto& sl : ln.active) sl.req->cancel = true;
     S->cv_loop.notify_all();
   }
-  if (S->loop.joinable()) S->loop.join();
-  (void)hipStreamSynchronize(S->stream);
-  (void)hipStreamDestroy(S->stream);
+  for (auto& ln : S->lanes)
+    if (ln.loop.joinable()) ln.loop.join();
+  for (auto& ln : S->lanes) {
+    (void)hipStreamSynchronize(ln.stream);
+    (void)hipStreamDestroy(ln.stream);
+  }
   delete S;
 }
 
