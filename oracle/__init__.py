@@ -77,14 +77,14 @@ def lib():
         vp = ctypes.c_void_p
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
         L.orc_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
-        L.orc_draw.restype = ctypes.c_uint64
+        L.orc_draw.restype = ctypes.c_uint32
         L.orc_candidates.argtypes = [P, vp]
         L.orc_candidates.restype = ctypes.c_int32
         L.orc_nearest_lists.argtypes = [P, ctypes.c_int32, vp]
         L.orc_nearest_lists.restype = ctypes.c_int32
         L.orc_evidence.argtypes = [P, vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
         L.orc_evidence.restype = ctypes.c_double
-        L.orc_select.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_uint64]
+        L.orc_select.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_uint32]
         L.orc_select.restype = ctypes.c_int32
         L.orc_nn_tour.argtypes = [P, vp]
         L.orc_nn_tour.restype = ctypes.c_double

@@ -63,18 +63,18 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 /* Each ant has its own stream (Section IV-C).  Reading: counter-based,
  * counter = (step s, ant a, iteration t, 0), key = the 64-bit seed; the
- * 64-bit uniform is the first two output words. */
-uint64_t orc_draw(uint64_t seed, uint32_t t, uint32_t a, uint32_t s) {
+ * uniform is the first 32-bit output word. */
+uint32_t orc_draw(uint64_t seed, uint32_t t, uint32_t a, uint32_t s) {
   uint32_t ctr[4] = {s, a, t, 0u};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t out[4];
   orc_philox4x32_10(ctr, key, out);
-  return (uint64_t)out[0] | ((uint64_t)out[1] << 32);
+  return out[0];
 }
 
-/* floor(x * y / 2^64) */
-static uint64_t mulhi64(uint64_t x, uint64_t y) {
-  return (uint64_t)(((unsigned __int128)x * (unsigned __int128)y) >> 64);
+/* floor(u * y / 2^32) for a 32-bit uniform u */
+static uint64_t scale32(uint32_t u, uint64_t y) {
+  return (uint64_t)(((unsigned __int128)u * (unsigned __int128)y) >> 32);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -334,14 +334,16 @@ double orc_evidence(const orc_problem* p, const int32_t* cand, int32_t k_eff, do
 
 /* ------------------------------------------------------------------------ */
 /* Eq. (4) as a roulette over the unvisited slots of one candidate row.       */
-/* Reading (the build's discretisation of eq. 4): with E the largest          */
-/* floor(log2 w) over the unvisited slots, each slot gets the integer weight  */
-/* q = max(1, floor(w 2^(31-E))); r = floor(u * sum(q) / 2^64) for the 64-bit */
-/* uniform u, and the choice is the first slot, in list order, whose          */
-/* inclusive prefix sum of q exceeds r.                                        */
+/* Reading (a fixed-point discretisation of eq. 4 at the resolution of the   */
+/* FP32 weights): with E the largest floor(log2 w) over the unvisited slots,  */
+/* each slot gets the integer weight q = max(1, floor(w 2^(23-E))), so the    */
+/* heaviest slot keeps its whole 24-bit significand; r = floor(u * sum(q) /   */
+/* 2^32) for the 32-bit uniform u, and the choice is the first slot, in list  */
+/* order, whose inclusive prefix sum of q exceeds r.  Each slot's probability */
+/* is within (k+1) 2^-23 + 2^-32 of eq. (4).                                   */
 /* ------------------------------------------------------------------------ */
 int32_t orc_select(int32_t k, const int32_t* cand_row, const float* w_row, const uint8_t* visited,
-                   uint64_t u) {
+                   uint32_t u) {
   int32_t emax = INT_MIN;
   for (int32_t s = 0; s < k; s++) {
     if (visited[cand_row[s]]) continue;
@@ -354,11 +356,11 @@ int32_t orc_select(int32_t k, const int32_t* cand_row, const float* w_row, const
   uint64_t q[256];
   for (int32_t s = 0; s < k; s++) {
     if (visited[cand_row[s]]) continue;
-    double scaled = floor(ldexp((double)w_row[s], 31 - emax));
+    double scaled = floor(ldexp((double)w_row[s], 23 - emax));
     q[s] = scaled < 1.0 ? 1u : (uint64_t)scaled;
     total += q[s];
   }
-  uint64_t r = mulhi64(u, total);
+  uint64_t r = scale32(u, total);
   uint64_t acc = 0;
   for (int32_t s = 0; s < k; s++) {
     if (visited[cand_row[s]]) continue;
@@ -405,7 +407,7 @@ static int64_t construct_ant(const orc_problem* p, int32_t k_eff, const int32_t*
   int32_t n = p->n;
   int64_t fallbacks = 0;
   memset(vis, 0, (size_t)n);
-  int32_t start = (int32_t)mulhi64(orc_draw(p->seed, t, a, 0), (uint64_t)n);
+  int32_t start = (int32_t)scale32(orc_draw(p->seed, t, a, 0), (uint64_t)n);
   tour[0] = start;
   vis[start] = 1;
   for (int32_t s = 1; s < n; s++) {

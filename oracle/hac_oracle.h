@@ -54,8 +54,8 @@ typedef struct {
 
 /* Philox4x32-10 block */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
-/* 64-bit uniform for (seed, iteration t, ant a, step s) */
-uint64_t orc_draw(uint64_t seed, uint32_t t, uint32_t a, uint32_t s);
+/* 32-bit uniform for (seed, iteration t, ant a, step s) */
+uint32_t orc_draw(uint64_t seed, uint32_t t, uint32_t a, uint32_t s);
 
 /* Candidate lists (eq. 3): writes n*k_eff ids, returns k_eff or <0 on error */
 int32_t orc_candidates(const orc_problem* p, int32_t* cand);
@@ -71,7 +71,7 @@ double orc_evidence(const orc_problem* p, const int32_t* cand, int32_t k_eff, do
 /* One roulette decision: chooses among the unvisited slots of a row.
  * Returns the chosen slot, or -1 if every slot is visited. */
 int32_t orc_select(int32_t k, const int32_t* cand_row, const float* w_row,
-                   const uint8_t* visited, uint64_t u);
+                   const uint8_t* visited, uint32_t u);
 
 /* Nearest-neighbour tour from node 0 (Alg. 1 preparation); returns length */
 double orc_nn_tour(const orc_problem* p, int32_t* tour);

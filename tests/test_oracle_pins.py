@@ -35,14 +35,14 @@ def test_philox_known_answers():
 
 
 def test_draw_layout_and_uniformity():
-    # the 64-bit draw is words 0 and 1 of the block at counter (s, a, t, 0)
+    # the 32-bit draw is word 0 of the block at counter (s, a, t, 0)
     seed = 0x0123456789ABCDEF
     out = oracle.philox([7, 3, 5, 0], [seed & 0xFFFFFFFF, seed >> 32])
-    assert oracle.draw(seed, 5, 3, 7) == int(out[0]) | (int(out[1]) << 32)
+    assert oracle.draw(seed, 5, 3, 7) == int(out[0])
     # chi-square on the top 6 bits of 40k draws
     bins = np.zeros(64)
     for s in range(40000):
-        bins[oracle.draw(11, 1 + s % 7, s % 13, s) >> 58] += 1
+        bins[oracle.draw(11, 1 + s % 7, s % 13, s) >> 26] += 1
     exp = 40000 / 64
     chi2 = ((bins - exp) ** 2 / exp).sum()
     # 63 dof: P(chi2 > 120) ~ 1e-5
@@ -309,7 +309,50 @@ def test_select_edge_cases():
     # extreme draws hit the first and the last open slot
     vis[:] = 0
     assert oracle.select(cand, w, vis, 0) == 0
-    assert oracle.select(cand, w, vis, 2 ** 64 - 1) == 2
+    assert oracle.select(cand, w, vis, 2 ** 32 - 1) == 2
+
+
+def _select_mass(cand, w, vis):
+    """Exact probability of each slot under the roulette: the chosen slot is
+    non-decreasing in the draw u, so the boundaries between slots are found
+    by bisection over u in [0, 2^32) and each slot's share of the draws is
+    counted exactly."""
+    k = len(cand)
+    first = []  # first draw that picks a slot > s
+    for s in range(k):
+        lo, hi = 0, 2 ** 32  # select(hi - 1) may still be <= s: hi = 2^32 means never
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if oracle.select(cand, w, vis, mid) > s:
+                hi = mid
+            else:
+                lo = mid + 1
+        first.append(lo)
+    mass, prev = [], 0
+    for s in range(k):
+        mass.append((first[s] - prev) / 2 ** 32)
+        prev = first[s]
+    return np.array(mass)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_select_probabilities_within_the_discretisation_bound(seed):
+    """Each slot's probability under the fixed-point roulette is within
+    (k+1) 2^-23 + 2^-32 of eq. (4), also for weights spread over many
+    binades (the light slots are floored to q = 1)."""
+    rng = np.random.default_rng(100 + seed)
+    k = int(rng.integers(2, 65))
+    w = np.exp(rng.uniform(-30.0, 0.0, size=k) if seed % 2 else rng.uniform(-2.0, 0.0, size=k))
+    w = w.astype(np.float32)
+    cand = np.arange(k, dtype=np.int32)
+    vis = (rng.random(k) < 0.3).astype(np.uint8)
+    vis[int(rng.integers(k))] = 0
+    mass = _select_mass(cand, w, vis)
+    p = np.where(vis == 0, w.astype(np.float64), 0.0)
+    p /= p.sum()
+    assert mass[vis == 1].sum() == 0
+    assert abs(mass.sum() - 1.0) < 1e-15
+    assert np.max(np.abs(mass - p)) <= (k + 1) * 2.0 ** -23 + 2.0 ** -32
 
 
 # --------------------------------------------------------------------------

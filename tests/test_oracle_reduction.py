@@ -33,9 +33,9 @@ def philox(ctr, key):
     return x0, x1, x2, x3
 
 
-def u64(seed, t, a, s):
+def u32(seed, t, a, s):
     o = philox((s, a, t, 0), (seed & M32, seed >> 32))
-    return o[0] | (o[1] << 32)
+    return o[0]
 
 
 def f32(x):
@@ -77,7 +77,7 @@ class TextbookMMAS:
     def ant(self, w, t, a):
         n = self.n
         vis = [False] * n
-        cur = (u64(self.seed, t, a, 0) * n) >> 64
+        cur = (u32(self.seed, t, a, 0) * n) >> 32
         tour = [cur]
         vis[cur] = True
         for s in range(1, n):
@@ -87,8 +87,8 @@ class TextbookMMAS:
                 j = self.nearest_free(i, vis)
             else:
                 E = max(math.frexp(w[i][q])[1] - 1 for q in open_)
-                qs = [max(1, math.floor(math.ldexp(w[i][q], 31 - E))) for q in open_]
-                r = (u64(self.seed, t, a, s) * sum(qs)) >> 64
+                qs = [max(1, math.floor(math.ldexp(w[i][q], 23 - E))) for q in open_]
+                r = (u32(self.seed, t, a, s) * sum(qs)) >> 32
                 acc = 0
                 for q, wq in zip(open_, qs):
                     acc += wq
