@@ -430,8 +430,8 @@ static void tune_cache_load() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char key[256];
-  int a, st, ln;
-  while (std::fscanf(f, "%255s %d %d %d", key, &a, &st, &ln) == 4) g_tune_cache[key] = LaunchShape{a, st, ln};
+  int a, st;
+  while (std::fscanf(f, "%255s %d %d", key, &a, &st) == 3) g_tune_cache[key] = LaunchShape{a, st, 0};
   std::fclose(f);
 }
 
@@ -441,8 +441,7 @@ static void tune_cache_store() {
   FILE* f = std::fopen(path, "w");
   if (!f) return;
   for (auto& kv : g_tune_cache)
-    std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged,
-                 kv.second.lanes);
+    std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged);
   std::fclose(f);
 }
 
@@ -485,18 +484,14 @@ static std::string shape_key(const std::vector<HostInst>& hs) {
 LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs, hipStream_t s,
                        DeviceArena& scratch, bool* ok) {
   *ok = true;
-  // lanes per ant: at least the candidate width, at most a whole wave
-  const int32_t gmin = construct_group_lanes(batch_max_k(hs));
+  const int32_t kmax = batch_max_k(hs);
   if (const char* force = std::getenv("HAC_SHAPE")) {
-    // "A,staged[,lanes]" pins the launch shape (used to show shape
-    // independence); A is rounded up to whole waves
-    LaunchShape sh{1, 0, gmin};
-    const int got = std::sscanf(force, "%d,%d,%d", &sh.ants_per_block, &sh.staged, &sh.lanes);
-    if (got >= 2 && sh.ants_per_block >= 1) {
-      if (got < 3 || (sh.lanes != 16 && sh.lanes != 32 && sh.lanes != 64) || sh.lanes < gmin) sh.lanes = gmin;
-      const int32_t per_wave = 64 / sh.lanes;
-      sh.ants_per_block = (sh.ants_per_block + per_wave - 1) / per_wave * per_wave;
-      if (sh.ants_per_block <= 16 * per_wave && shape_fits(hs, sh)) return sh;
+    // "A,staged" pins the launch shape (used to show shape independence);
+    // A is rounded up to whole waves of four ants
+    LaunchShape sh{1, 0, kmax};
+    if (std::sscanf(force, "%d,%d", &sh.ants_per_block, &sh.staged) == 2 && sh.ants_per_block >= 1) {
+      sh.ants_per_block = (sh.ants_per_block + 3) / 4 * 4;
+      if (sh.ants_per_block <= 64 && shape_fits(hs, sh)) return sh;
     }
   }
   const std::string key = shape_key(hs);
@@ -504,18 +499,18 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_cache_load();
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end() && shape_fits(hs, it->second)) return it->second;
+    if (it != g_tune_cache.end()) {
+      LaunchShape sh{it->second.ants_per_block, it->second.staged, kmax};
+      if (shape_fits(hs, sh)) return sh;
+    }
   }
   std::vector<LaunchShape> cands;
-  for (int lanes : {16, 32, 64}) {
-    if (lanes < gmin) continue;
-    for (int waves : {1, 2, 4, 8, 16})
-      for (int st : {0, 1}) {
-        LaunchShape sh{waves * (64 / lanes), st, lanes};
-        if (shape_fits(hs, sh)) cands.push_back(sh);
-      }
-  }
-  LaunchShape best{1, 0, 64};
+  for (int waves : {1, 2, 4, 8, 16})
+    for (int st : {0, 1}) {
+      LaunchShape sh{4 * waves, st, kmax};
+      if (shape_fits(hs, sh)) cands.push_back(sh);
+    }
+  LaunchShape best{4, 0, kmax};
   float best_ms = 1e30f;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -540,7 +535,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);
       (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block, sh.staged,
-                             sh.lanes, shape_lds(hs, sh), s);
+                             sh.kmax, shape_lds(hs, sh), s);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) {
         *ok = false;
@@ -843,7 +838,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       max_iter = std::max(max_iter, h.p.iterations);
       max_n = std::max(max_n, h.lay.n);
     }
-    LaunchShape shape{1, 0, 64};
+    LaunchShape shape{4, 0, 16};
     if (max_iter > 0) {
       bool ok = true;
       shape = tune_shape(hs, d_descs, s, c->scratch, &ok);
@@ -859,7 +854,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     const size_t lds = shape_lds(hs, shape);
     const int32_t blocks = (int32_t)map.size();
     auto one_iteration = [&]() -> hipError_t {
-      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, shape.lanes, lds, s);
+      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, shape.kmax, lds, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
         e = launch_local_search(d_descs, m, max_n, s);
@@ -876,7 +871,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       }
       for (int32_t it = 0; it < max_iter; ++it) {
         CTX_HIP(hipEventRecord(c->events[2 * it], s));
-        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, shape.lanes, lds, s));
+        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, shape.kmax, lds, s));
         CTX_HIP(hipEventRecord(c->events[2 * it + 1], s));
         if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
@@ -956,7 +951,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   st.construct_launches = launches;
   st.ants_per_block = used.ants_per_block;
   st.lds_staged = used.staged;
-  st.lanes_per_ant = used.lanes;
+  st.lanes_per_ant = used.ants_per_block > 0 ? 16 : 0;
   for (int32_t y = 0; y < m; ++y) {
     st.ant_steps += (int64_t)hs[y].p.ants * (hs[y].lay.n - 1) * hs[y].p.iterations;
     st.fallback_steps += (int64_t)sts[y].fallbacks;

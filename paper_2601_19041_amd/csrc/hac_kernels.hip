@@ -36,46 +36,50 @@ __device__ __forceinline__ double rd_lane_d(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ uint64_t rd_lane_u64(uint64_t v, int l) {
-  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
+// permutations that stay inside a 16-lane row: every lane has a source,
+// so bound_ctrl only spares the compiler an "old" operand
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_all(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
 }
 
-template <int CTRL, int ROWM>
-__device__ __forceinline__ uint32_t dpp_or0(uint32_t x) {
-  // lanes whose source is outside the row (or in a masked row) read 0
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWM, 0xf, false);
+template <int CTRL>
+__device__ __forceinline__ double dpp_all_f64(double v) {
+  return __hiloint2double((int)dpp_all<CTRL>((uint32_t)__double2hiint(v)),
+                          (int)dpp_all<CTRL>((uint32_t)__double2loint(v)));
 }
 
-// Inclusive prefix sum over the 64 lanes (Hillis-Steele inside each
-// 16-lane row, then row broadcasts).  Must run with all lanes active.
-__device__ __forceinline__ uint64_t wave_scan_u64(uint64_t v) {
-#define HAC_SCAN_STEP(C, R)                                                        \
-  {                                                                               \
-    uint32_t lo_ = (uint32_t)v, hi_ = (uint32_t)(v >> 32);                        \
-    v += ((uint64_t)dpp_or0<C, R>(hi_) << 32) | (uint64_t)dpp_or0<C, R>(lo_);     \
-  }
-  HAC_SCAN_STEP(0x111, 0xf)
-  HAC_SCAN_STEP(0x112, 0xf)
-  HAC_SCAN_STEP(0x114, 0xf)
-  HAC_SCAN_STEP(0x118, 0xf)
-  HAC_SCAN_STEP(0x142, 0xa)
-  HAC_SCAN_STEP(0x143, 0xc)
-#undef HAC_SCAN_STEP
+__device__ __forceinline__ uint32_t swz_xor16(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401f);  // lane ^ 16 inside 32 lanes
+}
+
+__device__ __forceinline__ double swz_xor16_f64(double v) {
+  return __hiloint2double((int)swz_xor16((uint32_t)__double2hiint(v)),
+                          (int)swz_xor16((uint32_t)__double2loint(v)));
+}
+
+// Butterfly inside each 16-lane row: lane ^ 1, lane ^ 2 (quad permutes),
+// then the mirrored quad of the half row and the mirrored half of the row.
+// Afterwards every lane holds the reduction over its row.
+template <class Op>
+__device__ __forceinline__ uint32_t row_reduce(uint32_t v, Op op) {
+  v = op(v, dpp_all<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = op(v, dpp_all<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = op(v, dpp_all<0x141>(v));  // row_half_mirror
+  v = op(v, dpp_all<0x140>(v));  // row_mirror
   return v;
 }
+struct OpMax {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; }
+};
+struct OpMin {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a < b ? a : b; }
+};
+struct OpOr {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a | b; }
+};
 
-// Maximum over the 64 lanes, returned to every lane.  All lanes active.
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-  v = max(v, dpp_or0<0x111, 0xf>(v));
-  v = max(v, dpp_or0<0x112, 0xf>(v));
-  v = max(v, dpp_or0<0x114, 0xf>(v));
-  v = max(v, dpp_or0<0x118, 0xf>(v));
-  v = max(v, dpp_or0<0x142, 0xa>(v));
-  v = max(v, dpp_or0<0x143, 0xc>(v));
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
+__device__ __forceinline__ double dmin(double a, double b) { return b < a ? b : a; }
 
 __device__ __forceinline__ bool key_less(double ka, int ia, double kb, int ib) {
   return ka < kb || (ka == kb && ia < ib);
@@ -118,27 +122,37 @@ __device__ __forceinline__ uint64_t lanes_ugt(uint64_t a, uint64_t b) {
 }
 
 // Lexicographic (key, index) minimum over the wave, returned to all lanes.
+// The smallest key comes from a DPP butterfly; a unique holder hands over
+// its index directly, ties take the smallest index among the holders.
+// Keys are never NaN.
 __device__ __forceinline__ void wave_argmin(double& key, int& idx) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    double ok = __shfl_xor(key, off);
-    int oi = __shfl_xor(idx, off);
-    if (key_less(ok, oi, key, idx)) {
-      key = ok;
-      idx = oi;
-    }
+  double m = key;
+  m = dmin(m, dpp_all_f64<0xB1>(m));
+  m = dmin(m, dpp_all_f64<0x4E>(m));
+  m = dmin(m, dpp_all_f64<0x141>(m));
+  m = dmin(m, dpp_all_f64<0x140>(m));
+  m = dmin(m, swz_xor16_f64(m));
+  const double M = dmin(rd_lane_d(m, 0), rd_lane_d(m, 32));
+  const uint64_t eq = __builtin_amdgcn_ballot_w64(key == M);
+  int j;
+  if ((eq & (eq - 1)) == 0) {
+    j = rd_lane(idx, (int)__builtin_ctzll(eq));
+  } else {
+    uint32_t v = row_reduce(key == M ? (uint32_t)idx : 0xffffffffu, OpMin());
+    v = min(v, swz_xor16(v));
+    j = (int)min((uint32_t)rd_lane((int)v, 0), (uint32_t)rd_lane((int)v, 32));
   }
-  key = rd_lane_d(key, 0);
-  idx = rd_lane(idx, 0);
+  key = M;
+  idx = j;
 }
 
 // ------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): two 32x32 multiplies
 // per round, key bumped by the golden-ratio Weyl constants.  Returns the
-// first two output words as one 64-bit uniform.
+// first output word, the step's 32-bit uniform.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t philox_u64(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ uint32_t philox_x0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
@@ -153,7 +167,7 @@ __device__ __forceinline__ uint64_t philox_u64(uint32_t c0, uint32_t c1, uint32_
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
-  return ((uint64_t)c1 << 32) | c0;
+  return c0;
 }
 
 // ------------------------------------------------------------------------
@@ -609,6 +623,94 @@ __device__ int scan_unvisited_g(const GDist& G, int i, const uint32_t* vis) {
   return bj < n ? bj : n - 1;
 }
 
+// Nearest unvisited node to i by (key, index) over an ant's list of nodes
+// that were unvisited at its previous scan; the scan compacts the list in
+// place to the nodes still unvisited.  The list starts as the implicit
+// range 0..n-1 (cnt < 0) and stays in increasing order (compaction keeps
+// order), so each lane meets its nodes in increasing index order and the
+// result is that of a scan over all nodes.  Only the nodes visited since
+// the previous scan are examined again.
+template <int CH>
+__device__ int scan_list(const GDist& G, const double2* xy_lds, int i, const uint32_t* vis,
+                         uint16_t* list, int& cnt) {
+  const int lane = lane_id(), n = G.n;
+  const bool all = cnt < 0;
+  const int m = all ? n : cnt;  // at least 1: an unvisited node exists
+  double xi = 0.0, yi = 0.0;
+  const HAC_AS1 double* row = nullptr;
+  if (xy_lds) {
+    xi = xy_lds[i].x;
+    yi = xy_lds[i].y;
+  } else if (G.xy) {
+    xi = G.xy[2 * i];
+    yi = G.xy[2 * i + 1];
+  } else {
+    row = G.dist + (int64_t)i * n;
+  }
+  double bk = __builtin_huge_val();
+  int bj = 0x7fffffff;
+  int out = 0;
+  for (int b0 = 0; b0 < m; b0 += CH * WAVE) {
+    int id[CH];
+    bool open[CH];
+    double ka[CH], kb[CH];
+    // every load is unconditional (indices clamped into the list), so the
+    // whole batch is one round trip per dependent level
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int x = min(b0 + c * WAVE + lane, m - 1);
+      id[c] = all ? x : (int)list[x];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int v = id[c];
+      open[c] = (b0 + c * WAVE + lane < m) & !((vis[v >> 5] >> (v & 31)) & 1u);
+      if (xy_lds) {
+        ka[c] = xy_lds[v].x;
+        kb[c] = xy_lds[v].y;
+      } else if (G.xy) {
+        ka[c] = G.xy[2 * v];
+        kb[c] = G.xy[2 * v + 1];
+      } else {
+        ka[c] = row[v];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      double kj;
+      if (row) {
+        kj = ka[c];
+      } else {
+        const double dx = xi - ka[c], dy = yi - kb[c];
+        kj = dx * dx + dy * dy;
+      }
+      if (open[c] && kj < bk) {
+        bk = kj;
+        bj = id[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {  // positions written never exceed positions read
+      const uint64_t mk = __builtin_amdgcn_ballot_w64(open[c]);
+      const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+      if (open[c]) list[out + below] = (uint16_t)id[c];
+      out += (int)__builtin_popcountll(mk);
+    }
+  }
+  cnt = out;
+  wave_argmin(bk, bj);
+  return bj < n ? bj : n - 1;
+}
+
+// one chunk when the list fits in a wave, batches of CH otherwise
+template <int CH>
+__device__ __forceinline__ int scan_list_any(const GDist& G, const double2* xy_lds, int i,
+                                             const uint32_t* vis, uint16_t* list, int& cnt) {
+  if (cnt >= 0 && cnt <= WAVE) return scan_list<1>(G, xy_lds, i, vis, list, cnt);
+  return scan_list<CH>(G, xy_lds, i, vis, list, cnt);
+}
+
 // The geometric list holds the kg nearest nodes in (key, index) order, so
 // its first unvisited entry, if any, is the answer; otherwise a full scan.
 __device__ __forceinline__ int geo_first_unvisited(const HAC_AS1 int32_t* geo, int kg, int i,
@@ -630,79 +732,42 @@ __device__ __forceinline__ int geo_first_unvisited(const HAC_AS1 int32_t* geo, i
 // Per step, for the ant at node i with candidate row C_i:
 //   open slots  = candidates whose visited bit is clear (LDS bitset)
 //   E           = largest biased exponent of the open weights
-//   q_u         = max(1, floor(w_u 2^(31-E)))  by integer shifts of the
-//                 FP32 mantissa (exact)
-//   r           = floor(U * sum q / 2^64) for the step's 64-bit uniform U
-//   choice      = first open slot whose inclusive prefix sum exceeds r
+//   q           = max(1, floor(w 2^(23-E))): the 24-bit FP32 significand
+//                 shifted right by E minus the slot's exponent (exact)
+//   r           = floor(U * sum q / 2^32) for the step's 32-bit uniform U
+//   choice      = the open slot whose exclusive prefix <= r < inclusive
+//                 prefix, i.e. the first one whose inclusive prefix exceeds r
 // and, when no slot is open, the nearest unvisited node.
 //
-// Lane groups.  A wave64 VALU instruction occupies a 16-lane SIMD for four
-// cycles, so a wave that spends 64 lanes on a 10- or 20-slot row wastes
-// most of the chip.  An ant therefore owns a group of G lanes (G = 16, 32
-// or 64, the smallest that holds k slots) and a wave carries 64/G ants
-// that step in lockstep through the same instance.  Reductions stay inside
-// the group: a butterfly max (quad_perm / row mirrors, plus a lane^16
-// swizzle for G >= 32), a row-shifted prefix scan, and row_newbcast
-// broadcasts.  The chosen node comes back with one ds_bpermute.  Groups
-// whose row is exhausted run the wave-wide nearest-unvisited scan one after
-// another.
+// Rows.  A wave64 VALU instruction occupies a 16-lane SIMD for four
+// cycles, so a wave spent on one 10- or 20-slot row would leave most of
+// the chip idle.  An ant therefore owns one 16-lane row of the wave (four
+// ants of one instance per wave) and each lane holds S consecutive slots
+// of the candidate row (S = 1, 2 or 4 for k <= 16, 32, 64).  Every
+// reduction is a DPP operation inside the row: a butterfly max of the
+// exponents, one prefix scan of the per-lane sums, a broadcast of the
+// row total, and a butterfly OR that hands the chosen id to all lanes
+// (exactly one slot of a live row passes the prefix test, so no search for
+// a first lane is needed).  The lane of the chosen slot marks the visited
+// bit with the bitset word it has just read.
 //
-// The step loop is unrolled by 16: at step s the lane (s mod 16) of every
-// 16-lane row holds that step's Philox output and buffers the tour entry,
-// so every broadcast lane index is a compile-time constant.  The tour is
-// written and its length accumulated (in step order) once per 16 steps.
-// STAGED copies the instance's {candidate, weight} table and coordinates
-// into LDS at the start of the launch.
+// Exhausted rows look up their geometric list (the kg <= 32 nearest nodes
+// in (distance, index) order, so the first unvisited entry is the answer)
+// inside their own row; rows whose list is exhausted as well run a
+// wave-wide scan of all nodes, one row after another.
+//
+// Lane u of a row holds the 32-bit Philox output of step s0 + u; the row
+// shifts them down one lane per step, so the current draw always sits in
+// lane 0.  Chosen nodes are buffered in lane (s mod 16) and written, with
+// their edge lengths added in step order, once per 16 steps.  STAGED
+// copies the instance's {candidate, weight} table and coordinates into
+// LDS at the start of the launch.
 // ------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_all(uint32_t x) {
-  // permutations that stay inside a row: every lane has a source
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
-}
 
-__device__ __forceinline__ uint32_t swz_xor16(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401f);  // lane ^ 16 inside 32 lanes
-}
-
-// every lane gets the maximum of its G-lane group
-template <int G>
-__device__ __forceinline__ uint32_t group_max_all(uint32_t v) {
-  v = max(v, dpp_all<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
-  v = max(v, dpp_all<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
-  v = max(v, dpp_all<0x141>(v));  // row_half_mirror: the other quad of the half row
-  v = max(v, dpp_all<0x140>(v));  // row_mirror: the other half of the row
-  if (G >= 32) v = max(v, swz_xor16(v));
-  if (G >= 64) v = max((uint32_t)__builtin_amdgcn_readlane((int)v, 0),
-                       (uint32_t)__builtin_amdgcn_readlane((int)v, 32));
-  return v;
-}
-
-// inclusive prefix sum inside each G-lane group
-template <int G>
-__device__ __forceinline__ uint64_t group_scan_u64(uint64_t v) {
-#define HAC_GSCAN_STEP(C, R)                                                       \
-  {                                                                               \
-    uint32_t lo_ = (uint32_t)v, hi_ = (uint32_t)(v >> 32);                        \
-    v += ((uint64_t)dpp_or0<C, R>(hi_) << 32) | (uint64_t)dpp_or0<C, R>(lo_);     \
-  }
-  HAC_GSCAN_STEP(0x111, 0xf)
-  HAC_GSCAN_STEP(0x112, 0xf)
-  HAC_GSCAN_STEP(0x114, 0xf)
-  HAC_GSCAN_STEP(0x118, 0xf)
-  if (G >= 32) HAC_GSCAN_STEP(0x142, 0xa)
-  if (G >= 64) HAC_GSCAN_STEP(0x143, 0xc)
-#undef HAC_GSCAN_STEP
-  return v;
-}
-
-// lane Q of each 16-lane row, to the whole row
+// lane Q of each 16-lane row, to the whole row (row_newbcast)
 template <int Q>
 __device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
   return dpp_all<0x150 + Q>(v);
-}
-template <int Q>
-__device__ __forceinline__ uint64_t row_bcast_u64(uint64_t v) {
-  return ((uint64_t)row_bcast<Q>((uint32_t)(v >> 32)) << 32) | row_bcast<Q>((uint32_t)v);
 }
 template <int Q>
 __device__ __forceinline__ double row_bcast_f64(double v) {
@@ -710,111 +775,141 @@ __device__ __forceinline__ double row_bcast_f64(double v) {
                           (int)row_bcast<Q>((uint32_t)__double2loint(v)));
 }
 
-// the group's total: the inclusive scan value of its last lane
-template <int G>
-__device__ __forceinline__ uint64_t group_total_u64(uint64_t pre, int lane) {
-  if (G == 16) return row_bcast_u64<15>(pre);
-  if (G == 32) {
-    const uint64_t t = row_bcast_u64<15>(pre);  // odd rows now hold the total
-    const uint64_t o = ((uint64_t)swz_xor16((uint32_t)(t >> 32)) << 32) | swz_xor16((uint32_t)t);
-    return (lane & 16) ? t : o;
-  }
-  return rd_lane_u64(pre, 63);
+// DPP shifts inside a row; lanes without a source read 0 (bound_ctrl)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_zero(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
 }
 
-// floor(a * b / 2^64) on the vector unit
-__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
-  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-  const uint64_t t1 = __umulhi(a0, b0);
-  const uint64_t t2 = (uint64_t)a1 * b0 + t1;
-  const uint64_t t3 = (uint64_t)a0 * b1 + (uint32_t)t2;
-  return (uint64_t)a1 * b1 + (t2 >> 32) + (t3 >> 32);
+// inclusive prefix sum inside each 16-lane row
+__device__ __forceinline__ uint32_t row_scan(uint32_t v) {
+  v += dpp_zero<0x111>(v);  // row_shr:1
+  v += dpp_zero<0x112>(v);  // row_shr:2
+  v += dpp_zero<0x114>(v);  // row_shr:4
+  v += dpp_zero<0x118>(v);  // row_shr:8
+  return v;
 }
 
-template <bool STAGED, int G>
-struct AntGroups {
-  static constexpr int R = WAVE / G;  // ants per wave
-  // instance
-  int n, k, kg, t, lane, u, g, r16;
-  bool live;
+template <bool STAGED, int S>
+struct AntRows {
+  int n, k, kg, u, g;
   const uint64_t* cw_lds;
   const HAC_AS1 uint64_t* cw_g;
   const double2* xy_lds;
   GDist D;
   const HAC_AS1 int32_t* geo;
-  uint32_t* vis_wave;  // bitsets of this wave's R ants, vis_words apart
-  uint32_t* vis_g;     // this lane's ant
+  uint32_t* vis_wave;  // bitsets of the wave's four rows, vis_words apart
+  uint32_t* vis_g;     // this row's bitset
   int vis_words;
-  // per-ant state (uniform inside a group)
-  int cur;
+  uint16_t* list_wave;  // unvisited lists of the wave's four rows, list_stride apart (or null)
+  int list_stride;
+  int lcnt;             // this row's list length (-1: all nodes)
+  bool live;
+  int cur;  // the row's current node (same in all its lanes)
   uint32_t fallbacks;
-  int tb;        // lane (s mod 16) of every row holds T[s] of the block
-  uint64_t rnd;  // lane (s mod 16) of every row holds step s's uniform
 
-  __device__ __forceinline__ int nearest(int gg) const {
-    const int ii = rd_lane(cur, gg * G);
-    const uint32_t* vv = vis_wave + gg * vis_words;
-    const int jg = geo_first_unvisited(geo, kg, ii, vv);
-    if (jg >= 0) return jg;
-    return (STAGED && xy_lds) ? scan_unvisited_lds<4>(xy_lds, n, ii, vv)
-                              : scan_unvisited_g<8>(D, ii, vv);
+  // one decision for every row of the wave; U is the row's uniform
+  __device__ __forceinline__ int step(uint32_t U) {
+    const uint32_t base = __umul24((uint32_t)cur, (uint32_t)k);
+    uint64_t e[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t x = base + (uint32_t)min(S * u + s, k - 1);
+      e[s] = STAGED ? cw_lds[x] : cw_g[x];
+    }
+    // the geometric list of the current node, needed only if the row is
+    // exhausted: loaded now so that its latency hides behind the step
+    const uint32_t go = __umul24((uint32_t)cur, (uint32_t)kg);
+    const int ga = geo[go + (uint32_t)min(2 * u, kg - 1)], gb = geo[go + (uint32_t)min(2 * u + 1, kg - 1)];
+    int c[S];
+    uint32_t wb[S], vw[S], bit[S];
+    bool open[S];
+    uint32_t emax = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      c[s] = (int)(uint32_t)e[s];
+      wb[s] = (uint32_t)(e[s] >> 32);
+      vw[s] = vis_g[c[s] >> 5];
+      bit[s] = 1u << (c[s] & 31);
+      open[s] = (S * u + s < k) & !(vw[s] & bit[s]);
+      emax = max(emax, open[s] ? (wb[s] >> 23) : 0u);
+    }
+    const uint32_t gm = row_reduce(emax, OpMax());  // 0: no open slot
+    uint32_t q[S], a[S], acc = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t d = min(gm - (wb[s] >> 23), 31u);
+      const uint32_t m = (wb[s] & 0x7fffffu) | 0x800000u;
+      q[s] = open[s] ? max(m >> d, 1u) : 0u;
+      acc += q[s];
+      a[s] = acc;
+    }
+    const uint32_t P = row_scan(acc);
+    const uint32_t tot = row_bcast<15>(P);
+    const uint32_t r = __umulhi(U, tot);
+    const uint32_t b0 = P - acc;  // exclusive prefix of this lane's first slot
+    uint32_t pick = 0, wv = 0;
+    int wi = 0;
+    bool hit = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t inc = b0 + a[s];
+      const bool h = (inc > r) & (inc - q[s] <= r);
+      pick = h ? (uint32_t)c[s] : pick;
+      wi = h ? (c[s] >> 5) : wi;
+      wv = h ? (vw[s] | bit[s]) : wv;
+      hit |= h;
+    }
+    int j = (int)row_reduce(pick, OpOr());
+    if (hit) vis_g[wi] = wv;  // only this row writes its bitset
+    const bool exhausted = gm == 0u;
+    if (__builtin_amdgcn_ballot_w64(exhausted)) j = fallback(exhausted, j, ga, gb);
+    return j;
   }
 
-  template <int Q>
-  __device__ __forceinline__ void step() {
-    const int x = cur * k + (u < k ? u : 0);  // lanes past the row reread slot 0
-    const uint64_t e = STAGED ? cw_lds[x] : cw_g[x];  // {id, weight bits}
-    const int c = (int)(uint32_t)e;
-    const uint32_t wb = (uint32_t)(e >> 32);
-    const bool open = (u < k) & !((vis_g[c >> 5] >> (c & 31)) & 1u);
-    const uint64_t om = __builtin_amdgcn_ballot_w64(open);
-    const uint32_t be = open ? (wb >> 23) : 0u;
-    const uint32_t d = group_max_all<G>(be) - be;
-    const uint32_t m = ((wb & 0x7fffffu) | 0x800000u) << 8;
-    const uint32_t q = max(d < 32u ? (m >> d) : 0u, 1u);
-    const uint64_t pre = group_scan_u64<G>(open ? (uint64_t)q : 0ull);
-    const uint64_t tot = group_total_u64<G>(pre, lane);
-    const uint64_t r = mulhi64(row_bcast_u64<Q>(rnd), tot);
-    const uint64_t sm = om & lanes_ugt(pre, r);
-    int j;
-    uint64_t fb_lead;
-    if constexpr (G == 64) {
-      j = rd_lane(c, __ffsll((unsigned long long)sm) - 1);
-      fb_lead = om ? 0ull : 1ull;
-    } else {
-      const uint32_t gmask = G == 16 ? 0xffffu : 0xffffffffu;
-      const uint32_t field = (uint32_t)(sm >> (G * g)) & gmask;
-      // an exhausted group gets some lane of its own; the fallback below overwrites j
-      const int src = G * g + (int)__builtin_ctz(field | (1u << (G - 1)));
-      j = __builtin_amdgcn_ds_bpermute(src * 4, c);
-      const uint32_t ofield = (uint32_t)(om >> (G * g)) & gmask;
-      fb_lead = __builtin_amdgcn_ballot_w64(u == 0 && ofield == 0u);
+  __device__ __forceinline__ int fallback(bool exhausted, int j, int id0, int id1) {
+    int jg = -1;
+    if (exhausted) {  // whole rows: the geometric list, two entries per lane
+      const uint32_t w0 = vis_g[id0 >> 5], w1 = vis_g[id1 >> 5];  // ids are valid in every lane
+      const bool o0 = (2 * u < kg) & !((w0 >> (id0 & 31)) & 1u);
+      const bool o1 = (2 * u + 1 < kg) & !((w1 >> (id1 & 31)) & 1u);
+      const uint64_t bm = __builtin_amdgcn_ballot_w64(o0 | o1);
+      const uint32_t field = (uint32_t)(bm >> (16 * g)) & 0xffffu;
+      if (field) {
+        const int f = (int)__builtin_ctz(field);
+        jg = (int)row_reduce(u == f ? (uint32_t)(o0 ? id0 : id1) : 0u, OpOr());
+      }
     }
-    while (fb_lead) {  // exhausted rows: nearest unvisited node, one group at a time
-      const int lead = __ffsll((unsigned long long)fb_lead) - 1;
-      fb_lead &= fb_lead - 1;
-      const int gg = lead / G;
-      const int jj = nearest(gg);
-      if (g == gg) {
-        j = jj;
+    // live rows still without a node: wave-wide scans, one row at a time
+    uint64_t miss = __builtin_amdgcn_ballot_w64(exhausted & (jg < 0) & (u == 0) & live);
+    while (miss) {
+      const int lead = (int)__builtin_ctzll(miss);
+      miss &= miss - 1;
+      const int gg = lead >> 4;
+      const int ii = rd_lane(cur, lead);
+      const uint32_t* vv = vis_wave + gg * vis_words;
+      int jj;
+      if (list_wave) {
+        int cnt = rd_lane(lcnt, lead);
+        jj = (STAGED && xy_lds) ? scan_list_any<4>(D, xy_lds, ii, vv, list_wave + gg * list_stride, cnt)
+                                : scan_list_any<8>(D, nullptr, ii, vv, list_wave + gg * list_stride, cnt);
+        if (g == gg) lcnt = cnt;
+      } else {
+        jj = (STAGED && xy_lds) ? scan_unvisited_lds<4>(xy_lds, n, ii, vv)
+                                : scan_unvisited_g<8>(D, ii, vv);
+      }
+      if (g == gg) jg = jj;
+    }
+    if (exhausted) {
+      j = jg < 0 ? 0 : jg;  // only idle rows can be left without a node
+      if (u == 0) {
+        atomicOr(&vis_g[j >> 5], 1u << (j & 31));
         fallbacks++;
       }
     }
-    if (u == 0) atomicOr(&vis_g[j >> 5], 1u << (j & 31));
-    if (r16 == Q) tb = j;
-    cur = j;
+    return j;
   }
 };
-
-template <int Q, class A>
-__device__ __forceinline__ void unroll16(A& a, int s0, int n) {
-  if constexpr (Q < 16) {
-    const int s = s0 + Q;
-    if (s >= 1 && s < n) a.template step<Q>();
-    unroll16<Q + 1>(a, s0, n);
-  }
-}
 
 template <int Q>
 __device__ __forceinline__ void sum_row_in_order(double& len, double d) {
@@ -824,11 +919,10 @@ __device__ __forceinline__ void sum_row_in_order(double& len, double d) {
   }
 }
 
-template <bool STAGED, int G>
+template <bool STAGED, int S>
 __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
-                                                         int ants_per_block) {
-  constexpr int R = WAVE / G;
+                                                         int ants_per_block, int lds_bytes) {
   const BlockMap bm = map[blockIdx.x];
   if (bm.inst < 0) return;
   const InstDesc I = insts[bm.inst];  // by value: the fields stay in registers
@@ -836,13 +930,17 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   if (t > I.iterations) return;
   extern __shared__ uint32_t lds[];
   const int n = I.n, k = I.k, lane = lane_id(), wave = threadIdx.x / WAVE;
-  const int words2 = ((n + 63) >> 6) << 1;
-  const int vis_words = ((words2 + 3) >> 2) << 2;
+  const ConstructLds L = construct_lds_layout(n, k, ants_per_block, STAGED, true);
+  const bool use_list = n <= 65535 && L.total <= (size_t)lds_bytes;
+  const int vis_words = (int)L.vis_words;
+  const int rows = (int)L.rows;  // bitsets (and lists) of every row of the block
+  const int list_off = rows * vis_words;
+  const int staged_off = use_list ? list_off + rows * (int)L.list_words : list_off;
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const uint64_t* cw_lds = nullptr;
   const double2* xy_lds = nullptr;
   if (STAGED) {
-    u32x4* dst = reinterpret_cast<u32x4*>(lds + ants_per_block * vis_words);
+    u32x4* dst = reinterpret_cast<u32x4*>(lds + staged_off);
     const HAC_AS1 u32x4* src = reinterpret_cast<const HAC_AS1 u32x4*>(as_global(I.cw));
     const int vec = (n * k * 8 + 15) / 16;
     for (int x = threadIdx.x; x < vec; x += blockDim.x) dst[x] = src[x];
@@ -855,31 +953,31 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
     }
     __syncthreads();
   }
-  const int first_ant = bm.ant0 + wave * R;
-  if (first_ant >= I.ants) return;  // whole wave idle
+  const int first_ant = bm.ant0 + wave * 4;
+  if (wave * 4 >= ants_per_block || first_ant >= I.ants) return;  // whole wave idle
 
-  AntGroups<STAGED, G> A{};
+  AntRows<STAGED, S> A{};
   A.n = n;
   A.k = k;
   A.kg = I.kg;
-  A.t = t;
-  A.lane = lane;
-  A.u = lane % G;
-  A.g = lane / G;
-  A.r16 = lane & 15;
-  const int my_ant = first_ant + A.g;
-  A.live = my_ant < I.ants;
-  const int ant = A.live ? my_ant : I.ants - 1;  // idle groups shadow a real ant, write nothing
+  A.u = lane & 15;
+  A.g = lane >> 4;
+  const int row = wave * 4 + A.g;
+  A.live = row < ants_per_block && bm.ant0 + row < I.ants;
+  const int ant = A.live ? bm.ant0 + row : first_ant;  // idle rows shadow the wave's first ant
   A.cw_lds = cw_lds;
   A.cw_g = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.cw));
   A.xy_lds = xy_lds;
   A.D = GDist(I);
   A.geo = as_global(I.geo);
   A.vis_words = vis_words;
-  A.vis_wave = lds + wave * R * vis_words;
+  A.vis_wave = lds + wave * 4 * vis_words;
   A.vis_g = A.vis_wave + A.g * vis_words;
+  A.list_stride = 2 * (int)L.list_words;
+  A.list_wave = use_list ? reinterpret_cast<uint16_t*>(lds + list_off) + wave * 4 * A.list_stride : nullptr;
+  A.lcnt = -1;
 
-  for (int w = lane; w < R * vis_words; w += WAVE) {
+  for (int w = lane; w < 4 * vis_words; w += WAVE) {
     const int lo = (w % vis_words) * 32;
     uint32_t v;
     if (lo + 32 <= n)
@@ -894,30 +992,40 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
 
   const uint32_t k0 = I.seed_lo, k1 = I.seed_hi;
   HAC_AS1 int32_t* my_tour = as_global(I.tours) + (int64_t)ant * n;
-  A.rnd = philox_u64((uint32_t)A.r16, (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
-  A.cur = (int)__umul64hi(row_bcast_u64<0>(A.rnd), (uint64_t)n);
-  const int start = A.cur;
-  if (A.u == 0) atomicOr(&A.vis_g[start >> 5], 1u << (start & 31));
-  A.tb = start;
+  uint32_t rnd = philox_x0((uint32_t)A.u, (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
+  const int start = (int)__umulhi(row_bcast<0>(rnd), (uint32_t)n);
+  rnd = dpp_zero<0x101>(rnd);  // row_shl:1, step 1's draw to lane 0
+  A.cur = start;
+  if (A.u == 0) A.vis_g[start >> 5] |= 1u << (start & 31);
   A.fallbacks = 0;
+  int tb = start;     // lane (s mod 16) holds T[s] of the current block of 16 steps
   int carry = start;  // T[s0 - 1]
   double len = 0.0;
+  int q0 = 1;
   for (int s0 = 0; s0 < n; s0 += 16) {
-    if (s0 > 0) A.rnd = philox_u64((uint32_t)(s0 + A.r16), (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
-    unroll16<0>(A, s0, n);
-    // write T[s0 .. s0+15] and add their incoming edges in step order
+    if (s0 > 0) {
+      rnd = philox_x0((uint32_t)(s0 + A.u), (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
+      q0 = 0;
+    }
     const int cnt = min(16, n - s0);
-    if (A.live && A.u < 16 && A.r16 < cnt) my_tour[s0 + A.r16] = A.tb;
-    int prev = (int)dpp_or0<0x111, 0xf>((uint32_t)A.tb);  // T[s - 1] from the lane below
-    if (A.r16 == 0) prev = carry;
+    for (int q = q0; q < cnt; ++q) {
+      const int j = A.step(row_bcast<0>(rnd));
+      rnd = dpp_zero<0x101>(rnd);
+      tb = A.u == q ? j : tb;
+      A.cur = j;
+    }
+    // write T[s0 .. s0+cnt-1] and add their incoming edges in step order
+    if (A.live && A.u < cnt) my_tour[s0 + A.u] = tb;
+    int prev = (int)dpp_zero<0x111>((uint32_t)tb);  // T[s - 1] from the lane below
+    if (A.u == 0) prev = carry;
     double dl = 0.0;
-    if (A.r16 < cnt && s0 + A.r16 >= 1) {
+    if (A.u < cnt && s0 + A.u >= 1) {
       if (STAGED && xy_lds) {
-        const double2 pa = xy_lds[prev], pb = xy_lds[A.tb];
+        const double2 pa = xy_lds[prev], pb = xy_lds[tb];
         const double dx = pa.x - pb.x, dy = pa.y - pb.y;
         dl = sqrt(dx * dx + dy * dy);
       } else {
-        dl = A.D.len(prev, A.tb);
+        dl = A.D.len(prev, tb);
       }
     }
     sum_row_in_order<0>(len, dl);  // adding 0.0 past the end leaves len unchanged
@@ -1189,11 +1297,10 @@ __global__ void __launch_bounds__(64) finish_kernel(const InstDesc* insts, int32
 int32_t max_lds_bytes() { return 160 * 1024; }
 
 size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t staged) {
-  const size_t words2 = (size_t)(((n + 63) >> 6) << 1);
-  const size_t vis_words = ((words2 + 3) >> 2) << 2;
-  size_t bytes = (size_t)ants_per_block * vis_words * 4;  // ants_per_block is a multiple of 64/G
-  if (staged) bytes += (((size_t)n * k * 8 + 15) / 16) * 16 + (size_t)16 * n;
-  return bytes;
+  // the unvisited lists are included whenever they fit
+  const ConstructLds with = construct_lds_layout(n, k, ants_per_block, staged != 0, true);
+  if (n <= 65535 && with.total <= (size_t)max_lds_bytes()) return with.total;
+  return construct_lds_layout(n, k, ants_per_block, staged != 0, false).total;
 }
 
 hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s) {
@@ -1223,25 +1330,25 @@ hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
-int32_t construct_group_lanes(int32_t max_k) { return max_k <= 16 ? 16 : (max_k <= 32 ? 32 : 64); }
+int32_t construct_group_lanes(int32_t max_k) { (void)max_k; return 16; }
 
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
-                            int32_t ants_per_block, int32_t staged, int32_t lanes, size_t lds_bytes,
+                            int32_t ants_per_block, int32_t staged, int32_t max_k, size_t lds_bytes,
                             hipStream_t s) {
-  const int G = lanes;
-  const int waves = (ants_per_block * G + WAVE - 1) / WAVE;
+  const int waves = (ants_per_block + 3) / 4;  // four ants (rows) per wave
   const dim3 grid(blocks), block(waves * WAVE);
-#define HAC_LAUNCH(ST, GL)                                                                 \
-  hipLaunchKernelGGL((construct_kernel<ST, GL>), grid, block, lds_bytes, s, d_insts, d_map, \
-                     ants_per_block)
+  const int S = max_k <= 16 ? 1 : (max_k <= 32 ? 2 : 4);
+#define HAC_LAUNCH(ST, SL)                                                                 \
+  hipLaunchKernelGGL((construct_kernel<ST, SL>), grid, block, lds_bytes, s, d_insts, d_map, \
+                     ants_per_block, (int)lds_bytes)
   if (staged) {
-    if (G == 16) HAC_LAUNCH(true, 16);
-    else if (G == 32) HAC_LAUNCH(true, 32);
-    else HAC_LAUNCH(true, 64);
+    if (S == 1) HAC_LAUNCH(true, 1);
+    else if (S == 2) HAC_LAUNCH(true, 2);
+    else HAC_LAUNCH(true, 4);
   } else {
-    if (G == 16) HAC_LAUNCH(false, 16);
-    else if (G == 32) HAC_LAUNCH(false, 32);
-    else HAC_LAUNCH(false, 64);
+    if (S == 1) HAC_LAUNCH(false, 1);
+    else if (S == 2) HAC_LAUNCH(false, 2);
+    else HAC_LAUNCH(false, 4);
   }
 #undef HAC_LAUNCH
   return hipGetLastError();

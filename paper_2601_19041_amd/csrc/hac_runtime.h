@@ -57,12 +57,13 @@ struct HostInst {
   hac_csr dev_csr{};
 };
 
-// Chosen construction launch shape: ants per block (whole waves), LDS
-// staging of the candidate table, and lanes per ant (16, 32 or 64).
+// Chosen construction launch shape: ants per block (four per wave), LDS
+// staging of the candidate table, and the widest candidate row of the
+// batch (which sets the slots each of an ant's 16 lanes holds).
 struct LaunchShape {
   int32_t ants_per_block;
   int32_t staged;
-  int32_t lanes;
+  int32_t kmax;
 };
 
 // One decode batch: everything from uploaded inputs to results.
@@ -74,7 +75,7 @@ struct Engine {
   // results of the last run
   double construct_ms = 0.0;
   int64_t construct_launches = 0;
-  LaunchShape shape{4, 0, 64};
+  LaunchShape shape{4, 0, 16};
 };
 
 hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_params* p,
