@@ -123,7 +123,7 @@ typedef struct hac_stats {
   double kappa, q90, r_hat, l_nn; /* of the first instance of the call     */
   int32_t ants_per_block;         /* construction launch shape used         */
   int32_t lds_staged;             /* 1: candidate table staged in LDS       */
-  int32_t lanes_per_ant;          /* 16, 32 or 64 lanes of a wave per ant   */
+  int32_t ants_per_wave;          /* 1-4 ants per wave, 16 lanes each       */
 } hac_stats;
 
 /* Fills the paper's settings (Section IV-C): m = 32, I = 5000, k = 20,

@@ -430,8 +430,9 @@ static void tune_cache_load() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char key[256];
-  int a, st;
-  while (std::fscanf(f, "%255s %d %d", key, &a, &st) == 3) g_tune_cache[key] = LaunchShape{a, st, 0};
+  int a, st, rpw;
+  while (std::fscanf(f, "%255s %d %d %d", key, &a, &st, &rpw) == 4)
+    g_tune_cache[key] = LaunchShape{a, st, 0, rpw};
   std::fclose(f);
 }
 
@@ -441,13 +442,16 @@ static void tune_cache_store() {
   FILE* f = std::fopen(path, "w");
   if (!f) return;
   for (auto& kv : g_tune_cache)
-    std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged);
+    std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged,
+                 kv.second.rows_per_wave);
   std::fclose(f);
 }
 
 static bool shape_fits(const std::vector<HostInst>& hs, LaunchShape sh) {
   for (auto& h : hs) {
-    if (construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.staged) > (size_t)max_lds_bytes())
+    if (sh.rows_per_wave < 1 || sh.rows_per_wave > 4 ||
+        construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.rows_per_wave, sh.staged) >
+            (size_t)max_lds_bytes())
       return false;
   }
   return true;
@@ -461,7 +465,8 @@ int32_t batch_max_k(const std::vector<HostInst>& hs) {
 
 size_t shape_lds(const std::vector<HostInst>& hs, LaunchShape sh) {
   size_t b = 0;
-  for (auto& h : hs) b = std::max(b, construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.staged));
+  for (auto& h : hs)
+    b = std::max(b, construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.rows_per_wave, sh.staged));
   return b;
 }
 
@@ -486,12 +491,13 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
   *ok = true;
   const int32_t kmax = batch_max_k(hs);
   if (const char* force = std::getenv("HAC_SHAPE")) {
-    // "A,staged" pins the launch shape (used to show shape independence);
-    // A is rounded up to whole waves of four ants
-    LaunchShape sh{1, 0, kmax};
-    if (std::sscanf(force, "%d,%d", &sh.ants_per_block, &sh.staged) == 2 && sh.ants_per_block >= 1) {
-      sh.ants_per_block = (sh.ants_per_block + 3) / 4 * 4;
-      if (sh.ants_per_block <= 64 && shape_fits(hs, sh)) return sh;
+    // "A,staged[,rows]" pins the launch shape (used to show shape
+    // independence): A ants per block, rows (1..4, default 4) ants per wave
+    LaunchShape sh{1, 0, kmax, 4};
+    const int got = std::sscanf(force, "%d,%d,%d", &sh.ants_per_block, &sh.staged, &sh.rows_per_wave);
+    if (got >= 2 && sh.ants_per_block >= 1) {
+      if (got < 3 || sh.rows_per_wave < 1 || sh.rows_per_wave > 4) sh.rows_per_wave = 4;
+      if (sh.ants_per_block <= 16 * sh.rows_per_wave && shape_fits(hs, sh)) return sh;
     }
   }
   const std::string key = shape_key(hs);
@@ -500,17 +506,18 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     tune_cache_load();
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      LaunchShape sh{it->second.ants_per_block, it->second.staged, kmax};
+      LaunchShape sh{it->second.ants_per_block, it->second.staged, kmax, it->second.rows_per_wave};
       if (shape_fits(hs, sh)) return sh;
     }
   }
   std::vector<LaunchShape> cands;
-  for (int waves : {1, 2, 4, 8, 16})
-    for (int st : {0, 1}) {
-      LaunchShape sh{4 * waves, st, kmax};
-      if (shape_fits(hs, sh)) cands.push_back(sh);
-    }
-  LaunchShape best{4, 0, kmax};
+  for (int rpw : {4, 1})
+    for (int waves : {1, 2, 4, 8, 16})
+      for (int st : {0, 1}) {
+        LaunchShape sh{rpw * waves, st, kmax, rpw};
+        if (shape_fits(hs, sh)) cands.push_back(sh);
+      }
+  LaunchShape best{4, 0, kmax, 4};
   float best_ms = 1e30f;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -534,8 +541,8 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     float ms_min = 1e30f;
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);
-      (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block, sh.staged,
-                             sh.kmax, shape_lds(hs, sh), s);
+      (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block,
+                             sh.rows_per_wave, sh.staged, sh.kmax, shape_lds(hs, sh), s);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) {
         *ok = false;
@@ -829,7 +836,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
 
   double construct_ms = 0.0;
   int64_t launches = 0;
-  LaunchShape used{0, 0, 0};
+  LaunchShape used{0, 0, 0, 0};
   if (m > 0) {
     bool any_ls = false;
     int32_t max_iter = 0, max_n = 0;
@@ -838,7 +845,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       max_iter = std::max(max_iter, h.p.iterations);
       max_n = std::max(max_n, h.lay.n);
     }
-    LaunchShape shape{4, 0, 16};
+    LaunchShape shape{4, 0, 16, 4};
     if (max_iter > 0) {
       bool ok = true;
       shape = tune_shape(hs, d_descs, s, c->scratch, &ok);
@@ -854,7 +861,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     const size_t lds = shape_lds(hs, shape);
     const int32_t blocks = (int32_t)map.size();
     auto one_iteration = [&]() -> hipError_t {
-      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, shape.kmax, lds, s);
+      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged, shape.kmax, lds, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
         e = launch_local_search(d_descs, m, max_n, s);
@@ -871,7 +878,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       }
       for (int32_t it = 0; it < max_iter; ++it) {
         CTX_HIP(hipEventRecord(c->events[2 * it], s));
-        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.staged, shape.kmax, lds, s));
+        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged, shape.kmax, lds, s));
         CTX_HIP(hipEventRecord(c->events[2 * it + 1], s));
         if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
@@ -951,7 +958,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   st.construct_launches = launches;
   st.ants_per_block = used.ants_per_block;
   st.lds_staged = used.staged;
-  st.lanes_per_ant = used.ants_per_block > 0 ? 16 : 0;
+  st.ants_per_wave = used.rows_per_wave;
   for (int32_t y = 0; y < m; ++y) {
     st.ant_steps += (int64_t)hs[y].p.ants * (hs[y].lay.n - 1) * hs[y].p.iterations;
     st.fallback_steps += (int64_t)sts[y].fallbacks;

@@ -71,8 +71,8 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
-                            int32_t ants_per_block, int32_t staged, int32_t max_k, size_t lds_bytes,
-                            hipStream_t s);
+                            int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
+                            int32_t max_k, size_t lds_bytes, hipStream_t s);
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                hipStream_t s);
 hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s);
@@ -82,16 +82,16 @@ hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const*
 // lanes per ant in the construction kernel (one 16-lane row)
 int32_t construct_group_lanes(int32_t max_k);
 // LDS layout of one construction block, in 32-bit words: the visited
-// bitsets of every row (four rows per wave), optionally each row's list of
-// unvisited nodes (uint16), and for STAGED launches the {candidate, weight}
-// table and the coordinates.
+// bitsets of every row (four rows per wave, of which rows_per_wave carry
+// ants), optionally each row's list of unvisited nodes (uint16), and for
+// STAGED launches the {candidate, weight} table and the coordinates.
 struct ConstructLds {
   size_t rows, vis_words, list_words, total;  // total in bytes
 };
 __host__ __device__ inline ConstructLds construct_lds_layout(int32_t n, int32_t k, int32_t ants_per_block,
-                                                             bool staged, bool lists) {
+                                                             int32_t rows_per_wave, bool staged, bool lists) {
   ConstructLds L;
-  L.rows = (size_t)((ants_per_block + 3) & ~3);
+  L.rows = (size_t)4 * (size_t)((ants_per_block + rows_per_wave - 1) / rows_per_wave);
   L.vis_words = (size_t)(((((n + 63) >> 6) << 1) + 3) & ~3);
   L.list_words = (size_t)(((n + 7) >> 3) << 2);  // n uint16 rounded up to 16 bytes
   size_t bytes = L.rows * L.vis_words * 4;
@@ -101,7 +101,8 @@ __host__ __device__ inline ConstructLds construct_lds_layout(int32_t n, int32_t 
   return L;
 }
 // LDS the construction kernel needs for one block (lists included when they fit)
-size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t staged);
+size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t rows_per_wave,
+                           int32_t staged);
 int32_t max_lds_bytes();
 
 }  // namespace hac

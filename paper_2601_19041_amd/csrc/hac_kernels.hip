@@ -922,7 +922,8 @@ __device__ __forceinline__ void sum_row_in_order(double& len, double d) {
 template <bool STAGED, int S>
 __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
-                                                         int ants_per_block, int lds_bytes) {
+                                                         int ants_per_block, int rows_per_wave,
+                                                         int lds_bytes) {
   const BlockMap bm = map[blockIdx.x];
   if (bm.inst < 0) return;
   const InstDesc I = insts[bm.inst];  // by value: the fields stay in registers
@@ -930,7 +931,8 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   if (t > I.iterations) return;
   extern __shared__ uint32_t lds[];
   const int n = I.n, k = I.k, lane = lane_id(), wave = threadIdx.x / WAVE;
-  const ConstructLds L = construct_lds_layout(n, k, ants_per_block, STAGED, true);
+  const int rpw = rows_per_wave;  // rows of a wave that carry ants (the others shadow row 0)
+  const ConstructLds L = construct_lds_layout(n, k, ants_per_block, rpw, STAGED, true);
   const bool use_list = n <= 65535 && L.total <= (size_t)lds_bytes;
   const int vis_words = (int)L.vis_words;
   const int rows = (int)L.rows;  // bitsets (and lists) of every row of the block
@@ -953,8 +955,8 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
     }
     __syncthreads();
   }
-  const int first_ant = bm.ant0 + wave * 4;
-  if (wave * 4 >= ants_per_block || first_ant >= I.ants) return;  // whole wave idle
+  const int first_ant = bm.ant0 + wave * rpw;
+  if (wave * rpw >= ants_per_block || first_ant >= I.ants) return;  // whole wave idle
 
   AntRows<STAGED, S> A{};
   A.n = n;
@@ -962,8 +964,8 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   A.kg = I.kg;
   A.u = lane & 15;
   A.g = lane >> 4;
-  const int row = wave * 4 + A.g;
-  A.live = row < ants_per_block && bm.ant0 + row < I.ants;
+  const int row = wave * rpw + A.g;
+  A.live = A.g < rpw && row < ants_per_block && bm.ant0 + row < I.ants;
   const int ant = A.live ? bm.ant0 + row : first_ant;  // idle rows shadow the wave's first ant
   A.cw_lds = cw_lds;
   A.cw_g = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.cw));
@@ -1296,11 +1298,12 @@ __global__ void __launch_bounds__(64) finish_kernel(const InstDesc* insts, int32
 // ------------------------------------------------------------------------
 int32_t max_lds_bytes() { return 160 * 1024; }
 
-size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t staged) {
+size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t rows_per_wave,
+                           int32_t staged) {
   // the unvisited lists are included whenever they fit
-  const ConstructLds with = construct_lds_layout(n, k, ants_per_block, staged != 0, true);
+  const ConstructLds with = construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, true);
   if (n <= 65535 && with.total <= (size_t)max_lds_bytes()) return with.total;
-  return construct_lds_layout(n, k, ants_per_block, staged != 0, false).total;
+  return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, false).total;
 }
 
 hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s) {
@@ -1333,14 +1336,15 @@ hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s) {
 int32_t construct_group_lanes(int32_t max_k) { (void)max_k; return 16; }
 
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
-                            int32_t ants_per_block, int32_t staged, int32_t max_k, size_t lds_bytes,
-                            hipStream_t s) {
-  const int waves = (ants_per_block + 3) / 4;  // four ants (rows) per wave
+                            int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
+                            int32_t max_k, size_t lds_bytes, hipStream_t s) {
+  if (rows_per_wave < 1 || rows_per_wave > 4) return hipErrorInvalidValue;
+  const int waves = (ants_per_block + rows_per_wave - 1) / rows_per_wave;
   const dim3 grid(blocks), block(waves * WAVE);
   const int S = max_k <= 16 ? 1 : (max_k <= 32 ? 2 : 4);
 #define HAC_LAUNCH(ST, SL)                                                                 \
   hipLaunchKernelGGL((construct_kernel<ST, SL>), grid, block, lds_bytes, s, d_insts, d_map, \
-                     ants_per_block, (int)lds_bytes)
+                     ants_per_block, rows_per_wave, (int)lds_bytes)
   if (staged) {
     if (S == 1) HAC_LAUNCH(true, 1);
     else if (S == 2) HAC_LAUNCH(true, 2);

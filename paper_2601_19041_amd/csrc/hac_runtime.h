@@ -57,13 +57,16 @@ struct HostInst {
   hac_csr dev_csr{};
 };
 
-// Chosen construction launch shape: ants per block (four per wave), LDS
-// staging of the candidate table, and the widest candidate row of the
-// batch (which sets the slots each of an ant's 16 lanes holds).
+// Chosen construction launch shape: ants per block, LDS staging of the
+// candidate table, the widest candidate row of the batch (which sets the
+// slots each of an ant's 16 lanes holds), and the ants per wave (one per
+// 16-lane row; fewer than four keeps the other rows' fallback scans out of
+// an ant's critical path).
 struct LaunchShape {
   int32_t ants_per_block;
   int32_t staged;
   int32_t kmax;
+  int32_t rows_per_wave;
 };
 
 // One decode batch: everything from uploaded inputs to results.
@@ -75,7 +78,7 @@ struct Engine {
   // results of the last run
   double construct_ms = 0.0;
   int64_t construct_launches = 0;
-  LaunchShape shape{4, 0, 16};
+  LaunchShape shape{4, 0, 16, 4};
 };
 
 hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_params* p,

@@ -120,12 +120,26 @@ def test_batch_equals_alone(ctx):
         assert np.array_equal(alone[0], got[x][0]) and alone[1] == got[x][1]
 
 
-@pytest.mark.parametrize("shape", ["1,0", "4,0", "16,0", "1,1", "8,1"])
+@pytest.mark.parametrize("shape", ["1,0", "4,0", "16,0", "1,1", "8,1", "4,0,1", "3,1,2", "8,1,1"])
 def test_launch_shape_independence(ctx, shape, monkeypatch):
+    """Ants per block, LDS staging and ants per wave change nothing."""
     inst = wl.tsp100(instance=4, seed=4, iterations=25)
     monkeypatch.setenv("HAC_SHAPE", shape)
     print(f"case shape {shape}", flush=True)
     _same(ctx.decode(inst), oracle.decode(inst), shape)
+
+
+@pytest.mark.parametrize("k,shape", [(24, "8,0"), (24, "5,1,1"), (40, "8,1"), (40, "2,0,2"), (64, "4,0")])
+def test_wide_candidate_rows(ctx, k, shape, monkeypatch):
+    """k > 16: each lane of an ant's row holds 2 or 4 slots; a batch with
+    rows of different widths uses the widest."""
+    insts = [wl.random_instance(150, seed=70 + k, k=k, ants=9, iterations=12),
+             wl.random_instance(90, seed=71 + k, k=7, ants=5, iterations=12)]
+    monkeypatch.setenv("HAC_SHAPE", shape)
+    print(f"case wide k={k} shape {shape}", flush=True)
+    got = ctx.decode_batch(insts)
+    for x, inst in enumerate(insts):
+        _same(got[x], oracle.decode(inst), f"k{k}/{x}")
 
 
 def test_invalid_inputs_leave_outputs(ctx):
