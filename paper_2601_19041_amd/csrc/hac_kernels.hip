@@ -367,126 +367,224 @@ __global__ void __launch_bounds__(64) nn_tour_kernel(const InstDesc* insts) {
 
 // ------------------------------------------------------------------------
 // First-improvement 2-opt over the geometric lists with a FIFO don't-look
-// queue (Section III-D).  One wave.  Candidate moves of node a are
-// evaluated in parallel (lanes 0..31: succ direction, 32..63: pred), and
-// the first improving one in (direction, list position) order is applied,
-// exactly as a sequential scan would find it.  tour/pos may live in LDS or
-// global memory; the queue and in-queue flags are touched by lane 0 only.
+// queue (Section III-D), one block of LS_WAVES waves per tour.
+//
+// Sequentially, node a leaves the queue head and its moves are scanned:
+// successor direction, then predecessor, each in list order and stopping at
+// the first neighbour c with d(a,c) >= d(a,b).  The first improving move is
+// applied, its end nodes are queued if absent, and a is examined again.  A
+// node without an improving move only leaves the queue.  The block
+// therefore evaluates the next LS_WAVES queue entries at once, one wave per
+// entry and all against the same tour (lanes 0..31 the successor moves,
+// 32..63 the predecessor moves).  The entries before the first one with an
+// improving move are consumed exactly as a sequential scan would consume
+// them; that move is applied and its node re-examined, and the speculative
+// results behind it are dropped.  The outcome is the sequential one.
 // ------------------------------------------------------------------------
-__device__ void reverse_path_wave(int n, int32_t* tour, int32_t* pos, int x, int y) {
+static constexpr int LS_WAVES = 16;
+
+struct LsMove {
+  int imp, a, b, c, e, dir;
+};
+
+// candidate moves of node a against the current tour (one wave)
+template <class IP>
+__device__ __forceinline__ LsMove ls_eval(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls,
+                                          int n, IP tour, IP pos, int a, double min_gain) {
   const int lane = lane_id();
+  const bool pred_dir = lane >= 32;
+  const int q = lane & 31;
+  const bool in_list = q < kls;
+  const int c = geo[(int64_t)a * kg + min(q, kls - 1)];
+  const int pa = pos[a];
+  const int b = pred_dir ? tour[pa == 0 ? n - 1 : pa - 1] : tour[pa + 1 == n ? 0 : pa + 1];
+  const double dab = G.len(a, b);
+  const double dac = G.len(a, c);
+  const double g1 = dab - dac;
+  // a direction stops at the first list entry that cannot gain
+  const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !(g1 > 0.0));
+  const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
+  const int lim_s = stop_s ? (int)__builtin_ctzll(stop_s) : 32;
+  const int lim_p = stop_p ? (int)__builtin_ctzll(stop_p) : 32;
+  const bool ok = in_list && q < (pred_dir ? lim_p : lim_s);
+  const int pc = pos[c];
+  const int e = pred_dir ? tour[pc == 0 ? n - 1 : pc - 1] : tour[pc + 1 == n ? 0 : pc + 1];
+  const double gain = (dab + G.len(c, e)) - (dac + G.len(b, e));
+  const bool imp = ok && e != a && c != b && gain > min_gain;
+  const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
+  LsMove m{0, a, 0, 0, 0, 0};
+  if (mi) {
+    const int l = (int)__builtin_ctzll(mi);
+    m.imp = 1;
+    m.b = rd_lane(b, l);
+    m.c = rd_lane(c, l);
+    m.e = rd_lane(e, l);
+    m.dir = l >= 32;
+  }
+  return m;
+}
+
+// reverse the tour path from x to y (or its complement when shorter); block-wide
+template <class IP>
+__device__ __forceinline__ void ls_reverse(int n, IP tour, IP pos, int x, int y) {
   int i = pos[x], j = pos[y];
   int len = ((j - i + n) % n) + 1;
   if (2 * len > n) {
-    int ni = (j + 1) % n, nj = (i - 1 + n) % n;
+    const int ni = (j + 1) % n, nj = (i - 1 + n) % n;
     i = ni;
     j = nj;
     len = n - len;
   }
+  __syncthreads();  // every thread has read pos[x], pos[y]
   const int half = len / 2;
-  for (int s = lane; s < half; s += WAVE) {
-    int pi = (i + s) % n;
-    int pj = (j - s + n) % n;
-    int ti = tour[pi], tj = tour[pj];
+  for (int s = threadIdx.x; s < half; s += blockDim.x) {
+    int pi = i + s;
+    if (pi >= n) pi -= n;
+    int pj = j - s;
+    if (pj < 0) pj += n;
+    const int ti = tour[pi], tj = tour[pj];
     tour[pi] = tj;
     tour[pj] = ti;
     pos[tj] = pi;
     pos[ti] = pj;
   }
-  __threadfence_block();
-  __builtin_amdgcn_wave_barrier();
+  __syncthreads();
 }
 
-__device__ void two_opt_wave(const InstDesc& D, int32_t* tour, int32_t* pos, int32_t* queue,
-                             int32_t* inq, double min_gain) {
-  const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id();
+template <class IP, class BP>
+__device__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain) {
+  __shared__ int sh_head, sh_count;
+  __shared__ LsMove sh_mv[LS_WAVES];
+  const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
   if (n < 5 || kls < 1) return;
-  for (int s = lane; s < n; s += WAVE) {
-    int v = tour[s];
+  const GDist G(D);
+  const HAC_AS1 int32_t* geo = as_global(D.geo);
+  for (int s = threadIdx.x; s < n; s += blockDim.x) {
+    const int v = tour[s];
     pos[v] = s;
     queue[s] = v;
     inq[v] = 1;
   }
-  __threadfence_block();
-  __builtin_amdgcn_wave_barrier();
-  int head = 0, count = n;
-  const bool pred_dir = lane >= 32;
-  const int q = lane & 31;
-  const bool in_list = q < kls;
-  while (count > 0) {
-    int a = 0;
-    if (lane == 0) {
-      a = queue[head];
-      inq[a] = 0;
+  if (threadIdx.x == 0) {
+    sh_head = 0;
+    sh_count = n;
+  }
+  __syncthreads();
+  for (;;) {
+    const int head = sh_head, count = sh_count;
+    if (count == 0) break;
+    const int nb = min(LS_WAVES, count);
+    if (wave < nb) {
+      int slot = head + wave;
+      if (slot >= n) slot -= n;
+      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, queue[slot], min_gain);
+      if (lane == 0) sh_mv[wave] = m;
     }
-    a = rd_lane(a, 0);
-    head = head + 1 == n ? 0 : head + 1;
-    count--;
-    for (;;) {
-      int pa = pos[a];
-      int b = pred_dir ? tour[pa == 0 ? n - 1 : pa - 1] : tour[pa + 1 == n ? 0 : pa + 1];
-      double dab = edge_len(D, a, b);
-      int c = in_list ? D.geo[(int64_t)a * kg + q] : a;
-      double dac = in_list ? edge_len(D, a, c) : 0.0;
-      double g1 = dab - dac;
-      // a direction stops at the first list entry that cannot gain
-      uint64_t stop = __ballot(in_list && !(g1 > 0.0));
-      uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
-      int lim_s = stop_s ? __ffsll((unsigned long long)stop_s) - 1 : 32;
-      int lim_p = stop_p ? __ffsll((unsigned long long)stop_p) - 1 : 32;
-      bool ok = in_list && q < (pred_dir ? lim_p : lim_s);
-      int e = 0;
-      bool imp = false;
-      if (ok) {
-        int pc = pos[c];
-        e = pred_dir ? tour[pc == 0 ? n - 1 : pc - 1] : tour[pc + 1 == n ? 0 : pc + 1];
-        if (e != a && c != b) {
-          double gain = (dab + edge_len(D, c, e)) - (dac + edge_len(D, b, e));
-          imp = gain > min_gain;
-        }
+    __syncthreads();
+    int f = -1;
+    for (int w = 0; w < nb; ++w)
+      if (sh_mv[w].imp) {
+        f = w;
+        break;
       }
-      uint64_t mi = __ballot(imp);
-      if (!mi) break;
-      int l = __ffsll((unsigned long long)mi) - 1;
-      int bb = rd_lane(b, l), cc = rd_lane(c, l), ee = rd_lane(e, l);
-      if (l < 32)
-        reverse_path_wave(n, tour, pos, bb, cc);
+    const int used = f < 0 ? nb : f + 1;  // entries consumed as a sequential scan would
+    LsMove m{};
+    if (f >= 0) m = sh_mv[f];
+    if ((int)threadIdx.x < used) {
+      int slot = head + threadIdx.x;
+      if (slot >= n) slot -= n;
+      inq[queue[slot]] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int h = head + used;
+      if (h >= n) h -= n;
+      sh_head = h;
+      sh_count = count - used;
+    }
+    if (f < 0) {
+      __syncthreads();
+      continue;
+    }
+    // apply the move, queue its end nodes, and examine its node again
+    for (;;) {
+      if (m.dir == 0)
+        ls_reverse(n, tour, pos, m.b, m.c);
       else
-        reverse_path_wave(n, tour, pos, cc, bb);
-      if (lane == 0) {
-        int ends[4] = {a, bb, cc, ee};
+        ls_reverse(n, tour, pos, m.c, m.b);
+      if (threadIdx.x == 0) {
+        int cnt = sh_count;
+        const int ends[4] = {m.a, m.b, m.c, m.e};
         for (int z = 0; z < 4; ++z) {
-          int x = ends[z];
+          const int x = ends[z];
           if (!inq[x]) {
-            int slot = head + count;
+            int slot = sh_head + cnt;
             if (slot >= n) slot -= n;
             queue[slot] = x;
-            count++;
+            cnt++;
             inq[x] = 1;
           }
         }
+        sh_count = cnt;
       }
-      count = rd_lane(count, 0);
+      __syncthreads();
+      if (wave == 0) {
+        const LsMove r = ls_eval(G, geo, kg, kls, n, tour, pos, m.a, min_gain);
+        if (lane == 0) sh_mv[0] = r;
+      }
+      __syncthreads();
+      m = sh_mv[0];
+      __syncthreads();
+      if (!m.imp) break;
     }
   }
 }
 
-// 2-opt of the NN tour (preparation, local search enabled).  One wave per
-// instance; working arrays in LDS when they fit.
-__global__ void __launch_bounds__(64) two_opt_nn_kernel(const InstDesc* insts, int use_lds) {
-  const InstDesc& D = insts[blockIdx.x];
-  if (!D.local_search) return;
+// Working arrays of the 2-opt: tour, pos and queue (int32) and the
+// in-queue flags (uint8), in LDS when 13n bytes fit, else in global memory
+// (the tour in place, the rest in the instance's work area).
+static __host__ __device__ inline size_t ls_lds_need(int n) {
+  return (((size_t)13 * n + 15) / 16) * 16;
+}
+
+template <bool IN_LDS>
+__device__ void two_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain) {
   extern __shared__ int32_t ls_lds[];
   const int n = D.n;
-  int32_t* pos = use_lds ? ls_lds : D.ls_work;
-  int32_t* queue = pos + n;
-  int32_t* inq = queue + n;
-  two_opt_wave(D, D.nn_tour, pos, queue, inq, D.st->min_gain);
+  if (IN_LDS) {
+    int32_t* tour = ls_lds;
+    int32_t* pos = tour + n;
+    int32_t* queue = pos + n;
+    uint8_t* inq = reinterpret_cast<uint8_t*>(queue + n);
+    for (int s = threadIdx.x; s < n; s += blockDim.x) tour[s] = tour_g[s];
+    __syncthreads();
+    two_opt_block(D, tour, pos, queue, inq, min_gain);
+    __syncthreads();
+    for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
+  } else {
+    HAC_AS1 int32_t* tour = as_global(tour_g);
+    HAC_AS1 int32_t* pos = as_global(D.ls_work);
+    HAC_AS1 int32_t* queue = pos + n;
+    HAC_AS1 uint8_t* inq = reinterpret_cast<HAC_AS1 uint8_t*>(queue + n);
+    two_opt_block(D, tour, pos, queue, inq, min_gain);
+  }
   __threadfence_block();
-  double len = tour_length_wave(D, D.nn_tour);
-  if (lane_id() == 0) {
-    D.st->l_gb = len;
-    D.st->l_ib = len;
+  __syncthreads();
+}
+
+// 2-opt of the NN tour (preparation, local search enabled).  One block per
+// instance.
+template <bool IN_LDS>
+__global__ void __launch_bounds__(LS_WAVES * WAVE) two_opt_nn_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.x];
+  if (!D.local_search) return;
+  two_opt_tour<IN_LDS>(D, D.nn_tour, D.st->min_gain);
+  if (threadIdx.x < WAVE) {
+    const double len = tour_length_wave(D, D.nn_tour);
+    if (threadIdx.x == 0) {
+      D.st->l_gb = len;
+      D.st->l_ib = len;
+    }
   }
 }
 
@@ -1065,27 +1163,31 @@ __device__ void iteration_best_wave(const InstDesc& D, int& ib, double& lib) {
   lib = bk;
 }
 
-__global__ void __launch_bounds__(64) local_search_kernel(const InstDesc* insts, int use_lds) {
+template <bool IN_LDS>
+__global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || D.st->t > D.iterations) return;
-  extern __shared__ int32_t ls_lds[];
-  const int n = D.n, lane = lane_id();
-  int ib;
-  double lib;
-  iteration_best_wave(D, ib, lib);
+  __shared__ int sh_ib;
+  const int n = D.n;
+  if (threadIdx.x < WAVE) {
+    int ib;
+    double lib;
+    iteration_best_wave(D, ib, lib);
+    if (threadIdx.x == 0) sh_ib = ib;
+  }
+  __syncthreads();
+  const int ib = sh_ib;
   const int32_t* src = D.tours + (int64_t)ib * n;
-  for (int s = lane; s < n; s += WAVE) D.t_ib[s] = src[s];
+  for (int s = threadIdx.x; s < n; s += blockDim.x) D.t_ib[s] = src[s];
   __threadfence_block();
-  __builtin_amdgcn_wave_barrier();
-  int32_t* pos = use_lds ? ls_lds : D.ls_work;
-  int32_t* queue = pos + n;
-  int32_t* inq = queue + n;
-  two_opt_wave(D, D.t_ib, pos, queue, inq, D.st->min_gain);
-  __threadfence_block();
-  double len = tour_length_wave(D, D.t_ib);
-  if (lane == 0) {
-    D.st->ib = ib;
-    D.st->l_ib = len;
+  __syncthreads();
+  two_opt_tour<IN_LDS>(D, D.t_ib, D.st->min_gain);
+  if (threadIdx.x < WAVE) {
+    const double len = tour_length_wave(D, D.t_ib);
+    if (threadIdx.x == 0) {
+      D.st->ib = ib;
+      D.st->l_ib = len;
+    }
   }
 }
 
@@ -1319,12 +1421,14 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
   return hipGetLastError();
 }
 
-static size_t ls_lds_bytes(int32_t max_n) { return (size_t)3 * max_n * 4; }
+static bool ls_in_lds(int32_t max_n) { return ls_lds_need(max_n) + 1024 <= (size_t)max_lds_bytes(); }
 
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s) {
-  const int use_lds = ls_lds_bytes(max_n) <= (size_t)max_lds_bytes();
-  hipLaunchKernelGGL(two_opt_nn_kernel, dim3(count), dim3(WAVE), use_lds ? ls_lds_bytes(max_n) : 0,
-                     s, d_insts, use_lds);
+  if (ls_in_lds(max_n))
+    hipLaunchKernelGGL(two_opt_nn_kernel<true>, dim3(count), dim3(LS_WAVES * WAVE), ls_lds_need(max_n),
+                       s, d_insts);
+  else
+    hipLaunchKernelGGL(two_opt_nn_kernel<false>, dim3(count), dim3(LS_WAVES * WAVE), 0, s, d_insts);
   return hipGetLastError();
 }
 
@@ -1360,9 +1464,11 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
 
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                hipStream_t s) {
-  const int use_lds = ls_lds_bytes(max_n) <= (size_t)max_lds_bytes();
-  hipLaunchKernelGGL(local_search_kernel, dim3(count), dim3(WAVE),
-                     use_lds ? ls_lds_bytes(max_n) : 0, s, d_insts, use_lds);
+  if (ls_in_lds(max_n))
+    hipLaunchKernelGGL(local_search_kernel<true>, dim3(count), dim3(LS_WAVES * WAVE),
+                       ls_lds_need(max_n), s, d_insts);
+  else
+    hipLaunchKernelGGL(local_search_kernel<false>, dim3(count), dim3(LS_WAVES * WAVE), 0, s, d_insts);
   return hipGetLastError();
 }
 

@@ -115,3 +115,13 @@ def test_serving_mix_kinds_first_iterations(ctx):
     got = ctx.decode_batch(insts)
     for x, inst in enumerate(insts):
         _check(got[x], inst)
+
+
+def test_two_opt_in_global_memory(ctx):
+    """n = 13000: the 2-opt working arrays no longer fit in LDS and the
+    block-level 2-opt runs on global memory; two iterations with 2-opt on
+    the iteration best against the oracle."""
+    inst = wl.tsp10k(count=1, iterations=2, n=13000)[0]
+    inst.ants = 6
+    print("case 2-opt global n=13000", flush=True)
+    _check(ctx.decode(inst), inst)
