@@ -98,6 +98,64 @@ def traffic_from_profile(kernel_src_hash: str, launches_key: str):
         return None
 
 
+def copy_calibration(mib: int):
+    """A plain device-to-device copy of known size (the runtime's copy
+    kernel), run under the same HBM counters as the construction kernel to
+    scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    nbytes = mib << 20
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}))
+
+
+def _pmc_rows(path, counter):
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                rows.append((r.get("Kernel_Name", ""), int(r.get("Grid_Size", 0)), float(r["Counter_Value"])))
+    return rows
+
+
+def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, key, command):
+    """Reduces the four rocprofv3 --pmc runs to HBM bytes per construction
+    launch and stores them, keyed by the kernel source hash, in
+    profiles/construct_traffic.json."""
+    def med(xs):
+        xs = sorted(xs)
+        return xs[len(xs) // 2]
+    def construct(rows):
+        # the batched launches: the construction dispatches with the largest grid
+        rows = [(g, v) for name, g, v in rows if "construct_kernel" in name]
+        top = max(g for g, _ in rows)
+        return med([v for g, v in rows if g == top])
+    def copy(rows):
+        vals = [v for name, g, v in rows if "copy" in name.lower()]
+        return max(vals)  # the large copy; small runtime copies read far less
+    f_kib, w_kib = construct(_pmc_rows(fetch_csv, "FETCH_SIZE")), construct(_pmc_rows(write_csv, "WRITE_SIZE"))
+    cf_kib, cw_kib = copy(_pmc_rows(copy_fetch_csv, "FETCH_SIZE")), copy(_pmc_rows(copy_write_csv, "WRITE_SIZE"))
+    sf, sw = copy_bytes / (cf_kib * 1024.0), copy_bytes / (cw_kib * 1024.0)
+    src = open(os.path.join(ROOT, "paper_2601_19041_amd", "csrc", "hac_kernels.hip"), "rb").read()
+    path = os.path.join(ROOT, "profiles", "construct_traffic.json")
+    d = json.load(open(path)) if os.path.exists(path) else {}
+    d[key] = {"kernel_source_sha256": hashlib.sha256(src).hexdigest(),
+              "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib,
+              "copy_bytes": copy_bytes, "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib,
+              "scale_fetch": sf, "scale_write": sw,
+              "hbm_bytes_per_launch": f_kib * 1024.0 * sf + w_kib * 1024.0 * sw,
+              "command": command}
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps(d[key]))
+
+
 def roofline(insts, cms, launches):
     """Construction kernel: one launch = one iteration of every instance."""
     bytes_per_launch = sum(x.ants * (x.n - 1) * construct_bytes_per_step(x.k, x.kind) for x in insts)
@@ -288,7 +346,20 @@ def main():
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=None,
+                    help="only run a device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    default=None, help="reduce rocprofv3 --pmc counter CSVs to profiles/construct_traffic.json")
+    ap.add_argument("--traffic-key", default="batch64")
+    ap.add_argument("--traffic-command", default="")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, float((args.copy_calibration or 512) << 20), args.traffic_key,
+                        args.traffic_command)
+        return
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the decoder runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
