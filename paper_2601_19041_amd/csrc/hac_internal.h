@@ -82,8 +82,9 @@ hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const*
 // lanes per ant in the construction kernel (one 16-lane row)
 int32_t construct_group_lanes(int32_t max_k);
 // LDS layout of one construction block, in 32-bit words: the visited
-// bitsets of every row (four rows per wave, of which rows_per_wave carry
-// ants), optionally each row's list of unvisited nodes (uint16), and for
+// bitsets of the rows that carry ants (rows_per_wave of each wave's four;
+// the other rows follow row 0 of their wave and read its bitset),
+// optionally each such row's list of unvisited nodes (uint16), and for
 // STAGED launches the {candidate, weight} table and the coordinates.
 struct ConstructLds {
   size_t rows, vis_words, list_words, total;  // total in bytes
@@ -91,7 +92,7 @@ struct ConstructLds {
 __host__ __device__ inline ConstructLds construct_lds_layout(int32_t n, int32_t k, int32_t ants_per_block,
                                                              int32_t rows_per_wave, bool staged, bool lists) {
   ConstructLds L;
-  L.rows = (size_t)4 * (size_t)((ants_per_block + rows_per_wave - 1) / rows_per_wave);
+  L.rows = (size_t)rows_per_wave * (size_t)((ants_per_block + rows_per_wave - 1) / rows_per_wave);
   L.vis_words = (size_t)(((((n + 63) >> 6) << 1) + 3) & ~3);
   L.list_words = (size_t)(((n + 7) >> 3) << 2);  // n uint16 rounded up to 16 bytes
   size_t bytes = L.rows * L.vis_words * 4;

@@ -896,10 +896,10 @@ struct AntRows {
   const double2* xy_lds;
   GDist D;
   const HAC_AS1 int32_t* geo;
-  uint32_t* vis_wave;  // bitsets of the wave's four rows, vis_words apart
-  uint32_t* vis_g;     // this row's bitset
+  uint32_t* vis_wave;  // bitsets of the wave's live rows, vis_words apart
+  uint32_t* vis_g;     // this row's bitset (row 0's for an idle row, which never writes)
   int vis_words;
-  uint16_t* list_wave;  // unvisited lists of the wave's four rows, list_stride apart (or null)
+  uint16_t* list_wave;  // unvisited lists of the wave's live rows, list_stride apart (or null)
   int list_stride;
   int lcnt;             // this row's list length (-1: all nodes)
   bool live;
@@ -959,7 +959,7 @@ struct AntRows {
       hit |= h;
     }
     int j = (int)row_reduce(pick, OpOr());
-    if (hit) vis_g[wi] = wv;  // only this row writes its bitset
+    if (hit && live) vis_g[wi] = wv;  // only this row writes its bitset
     const bool exhausted = gm == 0u;
     if (__builtin_amdgcn_ballot_w64(exhausted)) j = fallback(exhausted, j, ga, gb);
     return j;
@@ -1000,7 +1000,7 @@ struct AntRows {
     }
     if (exhausted) {
       j = jg < 0 ? 0 : jg;  // only idle rows can be left without a node
-      if (u == 0) {
+      if (u == 0 && live) {
         atomicOr(&vis_g[j >> 5], 1u << (j & 31));
         fallbacks++;
       }
@@ -1064,20 +1064,22 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   A.g = lane >> 4;
   const int row = wave * rpw + A.g;
   A.live = A.g < rpw && row < ants_per_block && bm.ant0 + row < I.ants;
-  const int ant = A.live ? bm.ant0 + row : first_ant;  // idle rows shadow the wave's first ant
+  // idle rows shadow the wave's first ant step for step, reading its bitset
+  // and writing nothing, so only live rows need LDS
+  const int ant = A.live ? bm.ant0 + row : first_ant;
   A.cw_lds = cw_lds;
   A.cw_g = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.cw));
   A.xy_lds = xy_lds;
   A.D = GDist(I);
   A.geo = as_global(I.geo);
   A.vis_words = vis_words;
-  A.vis_wave = lds + wave * 4 * vis_words;
-  A.vis_g = A.vis_wave + A.g * vis_words;
+  A.vis_wave = lds + wave * rpw * vis_words;
+  A.vis_g = A.vis_wave + (A.live ? A.g : 0) * vis_words;
   A.list_stride = 2 * (int)L.list_words;
-  A.list_wave = use_list ? reinterpret_cast<uint16_t*>(lds + list_off) + wave * 4 * A.list_stride : nullptr;
+  A.list_wave = use_list ? reinterpret_cast<uint16_t*>(lds + list_off) + wave * rpw * A.list_stride : nullptr;
   A.lcnt = -1;
 
-  for (int w = lane; w < 4 * vis_words; w += WAVE) {
+  for (int w = lane; w < rpw * vis_words; w += WAVE) {
     const int lo = (w % vis_words) * 32;
     uint32_t v;
     if (lo + 32 <= n)
@@ -1096,7 +1098,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   const int start = (int)__umulhi(row_bcast<0>(rnd), (uint32_t)n);
   rnd = dpp_zero<0x101>(rnd);  // row_shl:1, step 1's draw to lane 0
   A.cur = start;
-  if (A.u == 0) A.vis_g[start >> 5] |= 1u << (start & 31);
+  if (A.u == 0 && A.live) A.vis_g[start >> 5] |= 1u << (start & 31);
   A.fallbacks = 0;
   int tb = start;     // lane (s mod 16) holds T[s] of the current block of 16 steps
   int carry = start;  // T[s0 - 1]
