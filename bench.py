@@ -227,7 +227,7 @@ def run_batched(args, hac, insts, cpu, name, desc, plain_count):
                     {"workload": desc, "instances": count, "iterations": insts[0].iterations,
                      "ants": insts[0].ants, "k": insts[0].k, "inputs": "resident in HBM (hac_decode_batch_dev)",
                      "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
-                                      "ants_per_wave": st["ants_per_wave"]}})
+                                      "ants_per_wave": st["ants_per_wave"], "byte_marks": st["byte_marks"]}})
     out.update({
         "decodes_per_s": dps,
         "plain": {"decodes_per_s": plain_dps, "ant_steps_per_s": psteps / sum(lat), "sample": len(lat)},
@@ -254,7 +254,7 @@ def run_plain(args, hac, inst, cpu, name, desc):
                     {"workload": desc, "instances": 1, "iterations": inst.iterations, "ants": inst.ants,
                      "k": inst.k, "inputs": "resident in HBM",
                      "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
-                                      "ants_per_wave": st["ants_per_wave"]}})
+                                      "ants_per_wave": st["ants_per_wave"], "byte_marks": st["byte_marks"]}})
     out.update({"decodes_per_s": args.steps / wall,
                 "latency_ms": {"p50": 1000 * percentile(times, 0.5), "p99": 1000 * percentile(times, 0.99)},
                 "fallback_fraction": st["fallback_steps"] / max(1, st["ant_steps"]),

@@ -124,6 +124,7 @@ typedef struct hac_stats {
   int32_t ants_per_block;         /* construction launch shape used         */
   int32_t lds_staged;             /* 1: candidate table staged in LDS       */
   int32_t ants_per_wave;          /* 1-4 ants per wave, 16 lanes each       */
+  int32_t byte_marks;             /* 1: visited marks are bytes, 0: bits    */
 } hac_stats;
 
 /* Fills the paper's settings (Section IV-C): m = 32, I = 5000, k = 20,

@@ -68,7 +68,8 @@ class hac_stats(ctypes.Structure):
                 ("instances", ctypes.c_int32), ("kappa", ctypes.c_double), ("q90", ctypes.c_double),
                 ("r_hat", ctypes.c_double), ("l_nn", ctypes.c_double),
                 ("ants_per_block", ctypes.c_int32), ("lds_staged", ctypes.c_int32),
-                ("ants_per_wave", ctypes.c_int32)]
+                ("ants_per_wave", ctypes.c_int32),
+                ("byte_marks", ctypes.c_int32)]
 
 
 # every symbol include/hac.h declares

@@ -447,10 +447,18 @@ static void tune_cache_store() {
   std::fclose(f);
 }
 
+// byte marks when they fit every instance of the batch
+static LaunchShape with_marks(const std::vector<HostInst>& hs, LaunchShape sh) {
+  sh.bytes = 1;
+  for (auto& h : hs)
+    if (!construct_bytes_fit(h.lay.n, h.lay.k, sh.ants_per_block, sh.rows_per_wave, sh.staged)) sh.bytes = 0;
+  return sh;
+}
+
 static bool shape_fits(const std::vector<HostInst>& hs, LaunchShape sh) {
   for (auto& h : hs) {
     if (sh.rows_per_wave < 1 || sh.rows_per_wave > 4 ||
-        construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.rows_per_wave, sh.staged) >
+        construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.rows_per_wave, sh.staged, sh.bytes) >
             (size_t)max_lds_bytes())
       return false;
   }
@@ -466,7 +474,8 @@ int32_t batch_max_k(const std::vector<HostInst>& hs) {
 size_t shape_lds(const std::vector<HostInst>& hs, LaunchShape sh) {
   size_t b = 0;
   for (auto& h : hs)
-    b = std::max(b, construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.rows_per_wave, sh.staged));
+    b = std::max(b, construct_lds_bytes(h.lay.n, h.lay.k, sh.ants_per_block, sh.rows_per_wave, sh.staged,
+                                        sh.bytes));
   return b;
 }
 
@@ -493,10 +502,14 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
   if (const char* force = std::getenv("HAC_SHAPE")) {
     // "A,staged[,rows]" pins the launch shape (used to show shape
     // independence): A ants per block, rows (1..4, default 4) ants per wave
-    LaunchShape sh{1, 0, kmax, 4};
+    LaunchShape sh{1, 0, kmax, 4, 0};
     const int got = std::sscanf(force, "%d,%d,%d", &sh.ants_per_block, &sh.staged, &sh.rows_per_wave);
     if (got >= 2 && sh.ants_per_block >= 1) {
       if (got < 3 || sh.rows_per_wave < 1 || sh.rows_per_wave > 4) sh.rows_per_wave = 4;
+      sh = with_marks(hs, sh);
+      if (const char* bits = std::getenv("HAC_BIT_MARKS")) {
+        if (bits[0] == '1') sh.bytes = 0;  // pins bit marks (shows both give the same tours)
+      }
       if (sh.ants_per_block <= 16 * sh.rows_per_wave && shape_fits(hs, sh)) return sh;
     }
   }
@@ -506,18 +519,19 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     tune_cache_load();
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      LaunchShape sh{it->second.ants_per_block, it->second.staged, kmax, it->second.rows_per_wave};
+      LaunchShape sh = with_marks(hs, {it->second.ants_per_block, it->second.staged, kmax,
+                                       it->second.rows_per_wave, 0});
       if (shape_fits(hs, sh)) return sh;
     }
   }
   std::vector<LaunchShape> cands;
-  for (int rpw : {4, 1})
+  for (int rpw : {4, 2, 1})
     for (int waves : {1, 2, 4, 8, 16})
       for (int st : {0, 1}) {
-        LaunchShape sh{rpw * waves, st, kmax, rpw};
+        const LaunchShape sh = with_marks(hs, {rpw * waves, st, kmax, rpw, 0});
         if (shape_fits(hs, sh)) cands.push_back(sh);
       }
-  LaunchShape best{4, 0, kmax, 4};
+  LaunchShape best{4, 0, kmax, 4, 0};
   float best_ms = 1e30f;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -542,7 +556,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);
       (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block,
-                             sh.rows_per_wave, sh.staged, sh.kmax, shape_lds(hs, sh), s);
+                             sh.rows_per_wave, sh.staged, sh.bytes, sh.kmax, shape_lds(hs, sh), s);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) {
         *ok = false;
@@ -836,7 +850,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
 
   double construct_ms = 0.0;
   int64_t launches = 0;
-  LaunchShape used{0, 0, 0, 0};
+  LaunchShape used{0, 0, 0, 0, 0};
   if (m > 0) {
     bool any_ls = false;
     int32_t max_iter = 0, max_n = 0;
@@ -845,7 +859,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       max_iter = std::max(max_iter, h.p.iterations);
       max_n = std::max(max_n, h.lay.n);
     }
-    LaunchShape shape{4, 0, 16, 4};
+    LaunchShape shape{4, 0, 16, 4, 0};
     if (max_iter > 0) {
       bool ok = true;
       shape = tune_shape(hs, d_descs, s, c->scratch, &ok);
@@ -861,7 +875,8 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     const size_t lds = shape_lds(hs, shape);
     const int32_t blocks = (int32_t)map.size();
     auto one_iteration = [&]() -> hipError_t {
-      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged, shape.kmax, lds, s);
+      hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
+                                      shape.bytes, shape.kmax, lds, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
         e = launch_local_search(d_descs, m, max_n, s);
@@ -878,7 +893,8 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       }
       for (int32_t it = 0; it < max_iter; ++it) {
         CTX_HIP(hipEventRecord(c->events[2 * it], s));
-        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged, shape.kmax, lds, s));
+        CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
+                                      shape.bytes, shape.kmax, lds, s));
         CTX_HIP(hipEventRecord(c->events[2 * it + 1], s));
         if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
@@ -959,6 +975,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   st.ants_per_block = used.ants_per_block;
   st.lds_staged = used.staged;
   st.ants_per_wave = used.rows_per_wave;
+  st.byte_marks = used.bytes;
   for (int32_t y = 0; y < m; ++y) {
     st.ant_steps += (int64_t)hs[y].p.ants * (hs[y].lay.n - 1) * hs[y].p.iterations;
     st.fallback_steps += (int64_t)sts[y].fallbacks;

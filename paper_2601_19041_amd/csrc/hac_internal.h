@@ -72,7 +72,7 @@ hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
-                            int32_t max_k, size_t lds_bytes, hipStream_t s);
+                            int32_t bytes, int32_t max_k, size_t lds_bytes, hipStream_t s);
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                hipStream_t s);
 hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s);
@@ -90,20 +90,26 @@ struct ConstructLds {
   size_t rows, vis_words, list_words, total;  // total in bytes
 };
 __host__ __device__ inline ConstructLds construct_lds_layout(int32_t n, int32_t k, int32_t ants_per_block,
-                                                             int32_t rows_per_wave, bool staged, bool lists) {
+                                                             int32_t rows_per_wave, bool staged, bool lists,
+                                                             bool bytes) {
   ConstructLds L;
   L.rows = (size_t)rows_per_wave * (size_t)((ants_per_block + rows_per_wave - 1) / rows_per_wave);
-  L.vis_words = (size_t)(((((n + 63) >> 6) << 1) + 3) & ~3);
+  // visited marks per row: one byte per node (16-byte aligned), or one bit
+  L.vis_words = bytes ? (size_t)(((n + 15) >> 4) << 2) : (size_t)(((((n + 63) >> 6) << 1) + 3) & ~3);
   L.list_words = (size_t)(((n + 7) >> 3) << 2);  // n uint16 rounded up to 16 bytes
-  size_t bytes = L.rows * L.vis_words * 4;
-  if (lists) bytes += L.rows * L.list_words * 4;
-  if (staged) bytes += (((size_t)n * k * 8 + 15) / 16) * 16 + (size_t)16 * n;
-  L.total = bytes;
+  size_t total = L.rows * L.vis_words * 4;
+  if (lists) total += L.rows * L.list_words * 4;
+  if (staged) total += (((size_t)n * k * 8 + 15) / 16) * 16 + (size_t)16 * n;
+  L.total = total;
   return L;
 }
-// LDS the construction kernel needs for one block (lists included when they fit)
+// whether byte marks (with unvisited lists) fit a construction block
+bool construct_bytes_fit(int32_t n, int32_t k, int32_t ants_per_block, int32_t rows_per_wave,
+                         int32_t staged);
+// LDS the construction kernel needs for one block (with bit marks, the lists
+// are included when they fit)
 size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t rows_per_wave,
-                           int32_t staged);
+                           int32_t staged, int32_t bytes);
 int32_t max_lds_bytes();
 
 }  // namespace hac

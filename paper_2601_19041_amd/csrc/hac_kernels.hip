@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hac_internal.h"
 
 namespace hac {
@@ -77,6 +79,11 @@ struct OpMin {
 };
 struct OpOr {
   __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a | b; }
+};
+struct OpMinI {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const {
+    return (int32_t)a < (int32_t)b ? a : b;
+  }
 };
 
 __device__ __forceinline__ double dmin(double a, double b) { return b < a ? b : a; }
@@ -312,15 +319,27 @@ __global__ void __launch_bounds__(256) candidates_kernel(const InstDesc* insts, 
   if (lane < kg) D.geo[(int64_t)i * kg + lane] = geo.id;
 }
 
+// Visited tests over an ant's two representations: one bit per node, or
+// one byte per node (no shift or mask on the hot path, used when it fits).
+struct VisBits {
+  const uint32_t* p;
+  __device__ __forceinline__ bool operator()(int v) const { return (p[v >> 5] >> (v & 31)) & 1u; }
+};
+struct VisBytes {
+  const uint8_t* p;
+  __device__ __forceinline__ bool operator()(int v) const { return p[v] != 0; }
+};
+
 // Nearest unvisited node to i by (key, index), for the preparation kernels.
-template <int CH>
-__device__ int scan_unvisited_g(const GDist& G, int i, const uint32_t* vis);
+template <int CH, class V>
+__device__ int scan_unvisited_g(const GDist& G, int i, V visited);
+template <class V>
 __device__ __forceinline__ int geo_first_unvisited(const HAC_AS1 int32_t* geo, int kg, int i,
-                                                   const uint32_t* vis);
+                                                   V visited);
 __device__ int nearest_unvisited(const InstDesc& D, int i, const uint32_t* vis) {
-  const int jg = geo_first_unvisited(as_global(D.geo), D.kg, i, vis);
+  const int jg = geo_first_unvisited(as_global(D.geo), D.kg, i, VisBits{vis});
   if (jg >= 0) return jg;
-  return scan_unvisited_g<8>(GDist(D), i, vis);
+  return scan_unvisited_g<8>(GDist(D), i, VisBits{vis});
 }
 
 // ------------------------------------------------------------------------
@@ -638,8 +657,8 @@ __global__ void __launch_bounds__(256) init_kernel(const InstDesc* insts) {
 // batch costs one memory round trip.  Every lane keeps its own best
 // (key, j) in increasing j, then the wave reduces.  Visited bits past n
 // are set, so j < n need not be tested against the bitset.
-template <int CH>
-__device__ int scan_unvisited_lds(const double2* xy, int n, int i, const uint32_t* vis) {
+template <int CH, class V>
+__device__ int scan_unvisited_lds(const double2* xy, int n, int i, V visited) {
   const int lane = lane_id();
   const double2 pi = xy[i];
   double bk = __builtin_huge_val();
@@ -651,7 +670,7 @@ __device__ int scan_unvisited_lds(const double2* xy, int n, int i, const uint32_
     for (int c = 0; c < CH; ++c) {
       const int j = b0 + c * WAVE + lane;
       const int jc = j < n ? j : n - 1;  // reads stay inside this ant's bitset
-      open[c] = j < n && !((vis[jc >> 5] >> (jc & 31)) & 1u);
+      open[c] = j < n && !visited(jc);
       p[c] = xy[jc];
     }
 #pragma unroll
@@ -668,8 +687,8 @@ __device__ int scan_unvisited_lds(const double2* xy, int n, int i, const uint32_
   return bj < n ? bj : n - 1;
 }
 
-template <int CH>
-__device__ int scan_unvisited_g(const GDist& G, int i, const uint32_t* vis) {
+template <int CH, class V>
+__device__ int scan_unvisited_g(const GDist& G, int i, V visited) {
   const int lane = lane_id(), n = G.n;
   double bk = __builtin_huge_val();
   int bj = 0x7fffffff;
@@ -683,7 +702,7 @@ __device__ int scan_unvisited_g(const GDist& G, int i, const uint32_t* vis) {
       for (int c = 0; c < CH; ++c) {
         const int j = b0 + c * WAVE + lane;
         const int jc = j < n ? j : n - 1;
-        open[c] = j < n && !((vis[jc >> 5] >> (jc & 31)) & 1u);
+        open[c] = j < n && !visited(jc);
         px[c] = xy[2 * jc];
         py[c] = xy[2 * jc + 1];
       }
@@ -706,7 +725,7 @@ __device__ int scan_unvisited_g(const GDist& G, int i, const uint32_t* vis) {
       for (int c = 0; c < CH; ++c) {
         const int j = b0 + c * WAVE + lane;
         const int jc = j < n ? j : n - 1;
-        open[c] = j < n && !((vis[jc >> 5] >> (jc & 31)) & 1u);
+        open[c] = j < n && !visited(jc);
         v[c] = row[jc];
       }
 #pragma unroll
@@ -728,9 +747,9 @@ __device__ int scan_unvisited_g(const GDist& G, int i, const uint32_t* vis) {
 // order), so each lane meets its nodes in increasing index order and the
 // result is that of a scan over all nodes.  Only the nodes visited since
 // the previous scan are examined again.
-template <int CH>
-__device__ int scan_list(const GDist& G, const double2* xy_lds, int i, const uint32_t* vis,
-                         uint16_t* list, int& cnt) {
+template <int CH, class V>
+__device__ int scan_list(const GDist& G, const double2* xy_lds, int i, V visited, uint16_t* list,
+                         int& cnt) {
   const int lane = lane_id(), n = G.n;
   const bool all = cnt < 0;
   const int m = all ? n : cnt;  // at least 1: an unvisited node exists
@@ -762,7 +781,7 @@ __device__ int scan_list(const GDist& G, const double2* xy_lds, int i, const uin
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int v = id[c];
-      open[c] = (b0 + c * WAVE + lane < m) & !((vis[v >> 5] >> (v & 31)) & 1u);
+      open[c] = (b0 + c * WAVE + lane < m) & !visited(v);
       if (xy_lds) {
         ka[c] = xy_lds[v].x;
         kb[c] = xy_lds[v].y;
@@ -802,23 +821,24 @@ __device__ int scan_list(const GDist& G, const double2* xy_lds, int i, const uin
 }
 
 // one chunk when the list fits in a wave, batches of CH otherwise
-template <int CH>
-__device__ __forceinline__ int scan_list_any(const GDist& G, const double2* xy_lds, int i,
-                                             const uint32_t* vis, uint16_t* list, int& cnt) {
-  if (cnt >= 0 && cnt <= WAVE) return scan_list<1>(G, xy_lds, i, vis, list, cnt);
-  return scan_list<CH>(G, xy_lds, i, vis, list, cnt);
+template <int CH, class V>
+__device__ __forceinline__ int scan_list_any(const GDist& G, const double2* xy_lds, int i, V visited,
+                                             uint16_t* list, int& cnt) {
+  if (cnt >= 0 && cnt <= WAVE) return scan_list<1>(G, xy_lds, i, visited, list, cnt);
+  return scan_list<CH>(G, xy_lds, i, visited, list, cnt);
 }
 
 // The geometric list holds the kg nearest nodes in (key, index) order, so
 // its first unvisited entry, if any, is the answer; otherwise a full scan.
+template <class V>
 __device__ __forceinline__ int geo_first_unvisited(const HAC_AS1 int32_t* geo, int kg, int i,
-                                                   const uint32_t* vis) {
+                                                   V visited) {
   const int lane = lane_id();
   int g = 0;
   bool open = false;
   if (lane < kg) {
     g = geo[(int64_t)i * kg + lane];
-    open = !((vis[g >> 5] >> (g & 31)) & 1u);
+    open = !visited(g);
   }
   const uint64_t m = __builtin_amdgcn_ballot_w64(open);
   return m ? rd_lane(g, __ffsll((unsigned long long)m) - 1) : -1;
@@ -888,7 +908,7 @@ __device__ __forceinline__ uint32_t row_scan(uint32_t v) {
   return v;
 }
 
-template <bool STAGED, int S>
+template <bool STAGED, int S, bool BYTES>
 struct AntRows {
   int n, k, kg, u, g;
   const uint64_t* cw_lds;
@@ -896,23 +916,38 @@ struct AntRows {
   const double2* xy_lds;
   GDist D;
   const HAC_AS1 int32_t* geo;
-  uint32_t* vis_wave;  // bitsets of the wave's live rows, vis_words apart
-  uint32_t* vis_g;     // this row's bitset (row 0's for an idle row, which never writes)
-  int vis_words;
+  uint32_t* vis_wave;  // visited marks of the wave's live rows, vis_words apart
+  uint32_t* vis_g;     // this row's marks (row 0's for an idle row, which never writes)
+  int vis_words;       // BYTES: one byte per node, else one bit
+
+  __device__ __forceinline__ const uint8_t* vbytes(const uint32_t* w) const {
+    return reinterpret_cast<const uint8_t*>(w);
+  }
+  __device__ __forceinline__ bool visited(const uint32_t* w, int v) const {
+    if constexpr (BYTES) return vbytes(w)[v] != 0;
+    return (w[v >> 5] >> (v & 31)) & 1u;
+  }
+  // the row's own marks: only a live row's lane calls this
+  __device__ __forceinline__ void mark(int v) {
+    if constexpr (BYTES)
+      reinterpret_cast<uint8_t*>(vis_g)[v] = 1;
+    else
+      atomicOr(&vis_g[v >> 5], 1u << (v & 31));
+  }
   uint16_t* list_wave;  // unvisited lists of the wave's live rows, list_stride apart (or null)
   int list_stride;
   int lcnt;             // this row's list length (-1: all nodes)
   bool live;
-  int cur;  // the row's current node (same in all its lanes)
+  int cur;       // the row's current node (same in all its lanes)
+  uint32_t roff;  // cur * k: the first slot of cur's candidate row
   uint32_t fallbacks;
 
   // one decision for every row of the wave; U is the row's uniform
   __device__ __forceinline__ int step(uint32_t U) {
-    const uint32_t base = __umul24((uint32_t)cur, (uint32_t)k);
     uint64_t e[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const uint32_t x = base + (uint32_t)min(S * u + s, k - 1);
+      const uint32_t x = roff + (uint32_t)min(S * u + s, k - 1);
       e[s] = STAGED ? cw_lds[x] : cw_g[x];
     }
     // the geometric list of the current node, needed only if the row is
@@ -922,55 +957,80 @@ struct AntRows {
     int c[S];
     uint32_t wb[S], vw[S], bit[S];
     bool open[S];
-    uint32_t emax = 0;
+    // 150 - (biased exponent) of every open weight; the row minimum is the
+    // shift that brings the largest open weight to 24 integer bits
+    // (150 itself only when no slot is open: weights are normal numbers)
+    int tmin = 150;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       c[s] = (int)(uint32_t)e[s];
       wb[s] = (uint32_t)(e[s] >> 32);
-      vw[s] = vis_g[c[s] >> 5];
-      bit[s] = 1u << (c[s] & 31);
-      open[s] = (S * u + s < k) & !(vw[s] & bit[s]);
-      emax = max(emax, open[s] ? (wb[s] >> 23) : 0u);
+      if constexpr (BYTES) {
+        open[s] = (S * u + s < k) & (vbytes(vis_g)[c[s]] == 0);
+      } else {
+        vw[s] = vis_g[c[s] >> 5];
+        bit[s] = 1u << (c[s] & 31);
+        open[s] = (S * u + s < k) & !(vw[s] & bit[s]);
+      }
+      tmin = min(tmin, open[s] ? 150 - (int)(wb[s] >> 23) : 150);
     }
-    const uint32_t gm = row_reduce(emax, OpMax());  // 0: no open slot
+    const int sh = (int)row_reduce((uint32_t)tmin, OpMinI());
+    // q = floor(w 2^(23-E)) with E the largest floor(log2 w) of the open
+    // slots: scaling by a power of two is exact and the conversion truncates;
+    // open slots get at least 1, closed ones (weight taken as 0) exactly 0
     uint32_t q[S], a[S], acc = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const uint32_t d = min(gm - (wb[s] >> 23), 31u);
-      const uint32_t m = (wb[s] & 0x7fffffu) | 0x800000u;
-      q[s] = open[s] ? max(m >> d, 1u) : 0u;
+      const float wm = open[s] ? __uint_as_float(wb[s]) : 0.0f;
+      q[s] = max(__float2uint_rz(__builtin_ldexpf(wm, sh)), (uint32_t)open[s]);
       acc += q[s];
       a[s] = acc;
     }
     const uint32_t P = row_scan(acc);
     const uint32_t tot = row_bcast<15>(P);
+    uint32_t ex[S];  // exclusive prefix of each slot, ready before r
+#pragma unroll
+    for (int s = 0; s < S; ++s) ex[s] = P - acc + a[s] - q[s];
     const uint32_t r = __umulhi(U, tot);
-    const uint32_t b0 = P - acc;  // exclusive prefix of this lane's first slot
-    uint32_t pick = 0, wv = 0;
+    uint32_t pick = 0, pick_off = 0, wv = 0;
     int wi = 0;
     bool hit = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const uint32_t inc = b0 + a[s];
-      const bool h = (inc > r) & (inc - q[s] <= r);
+      // exclusive prefix <= r < inclusive prefix, i.e. r - exclusive < q
+      const bool h = r - ex[s] < q[s];
       pick = h ? (uint32_t)c[s] : pick;
-      wi = h ? (c[s] >> 5) : wi;
-      wv = h ? (vw[s] | bit[s]) : wv;
+      pick_off = h ? __umul24((uint32_t)c[s], (uint32_t)k) : pick_off;
+      if constexpr (!BYTES) {
+        wi = h ? (c[s] >> 5) : wi;
+        wv = h ? (vw[s] | bit[s]) : wv;
+      }
       hit |= h;
     }
     int j = (int)row_reduce(pick, OpOr());
-    if (hit && live) vis_g[wi] = wv;  // only this row writes its bitset
-    const bool exhausted = gm == 0u;
-    if (__builtin_amdgcn_ballot_w64(exhausted)) j = fallback(exhausted, j, ga, gb);
+    roff = row_reduce(pick_off, OpOr());  // the next row's offset, alongside j
+    // the lane of the chosen slot marks it (only this row writes its marks;
+    // a bitset word is rewritten with the value it has just read)
+    if (hit && live) {
+      if constexpr (BYTES)
+        reinterpret_cast<uint8_t*>(vis_g)[pick] = 1;
+      else
+        vis_g[wi] = wv;
+    }
+    const bool exhausted = sh == 150;
+    if (__builtin_amdgcn_ballot_w64(exhausted)) {
+      j = fallback(exhausted, j, ga, gb);
+      if (exhausted) roff = __umul24((uint32_t)j, (uint32_t)k);
+    }
     return j;
   }
 
   __device__ __forceinline__ int fallback(bool exhausted, int j, int id0, int id1) {
     int jg = -1;
     if (exhausted) {  // whole rows: the geometric list, two entries per lane
-      const uint32_t w0 = vis_g[id0 >> 5], w1 = vis_g[id1 >> 5];  // ids are valid in every lane
-      const bool o0 = (2 * u < kg) & !((w0 >> (id0 & 31)) & 1u);
-      const bool o1 = (2 * u + 1 < kg) & !((w1 >> (id1 & 31)) & 1u);
+      const bool v0 = visited(vis_g, id0), v1 = visited(vis_g, id1);  // ids are valid in every lane
+      const bool o0 = (2 * u < kg) & !v0;
+      const bool o1 = (2 * u + 1 < kg) & !v1;
       const uint64_t bm = __builtin_amdgcn_ballot_w64(o0 | o1);
       const uint32_t field = (uint32_t)(bm >> (16 * g)) & 0xffffu;
       if (field) {
@@ -985,7 +1045,13 @@ struct AntRows {
       miss &= miss - 1;
       const int gg = lead >> 4;
       const int ii = rd_lane(cur, lead);
-      const uint32_t* vv = vis_wave + gg * vis_words;
+      const uint32_t* vw_ = vis_wave + gg * vis_words;
+      using VisT = typename std::conditional<BYTES, VisBytes, VisBits>::type;
+      VisT vv;
+      if constexpr (BYTES)
+        vv = VisBytes{vbytes(vw_)};
+      else
+        vv = VisBits{vw_};
       int jj;
       if (list_wave) {
         int cnt = rd_lane(lcnt, lead);
@@ -1001,7 +1067,7 @@ struct AntRows {
     if (exhausted) {
       j = jg < 0 ? 0 : jg;  // only idle rows can be left without a node
       if (u == 0 && live) {
-        atomicOr(&vis_g[j >> 5], 1u << (j & 31));
+        mark(j);
         fallbacks++;
       }
     }
@@ -1017,7 +1083,7 @@ __device__ __forceinline__ void sum_row_in_order(double& len, double d) {
   }
 }
 
-template <bool STAGED, int S>
+template <bool STAGED, int S, bool BYTES>
 __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
                                                          int ants_per_block, int rows_per_wave,
@@ -1030,7 +1096,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   extern __shared__ uint32_t lds[];
   const int n = I.n, k = I.k, lane = lane_id(), wave = threadIdx.x / WAVE;
   const int rpw = rows_per_wave;  // rows of a wave that carry ants (the others shadow row 0)
-  const ConstructLds L = construct_lds_layout(n, k, ants_per_block, rpw, STAGED, true);
+  const ConstructLds L = construct_lds_layout(n, k, ants_per_block, rpw, STAGED, true, BYTES);
   const bool use_list = n <= 65535 && L.total <= (size_t)lds_bytes;
   const int vis_words = (int)L.vis_words;
   const int rows = (int)L.rows;  // bitsets (and lists) of every row of the block
@@ -1056,7 +1122,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   const int first_ant = bm.ant0 + wave * rpw;
   if (wave * rpw >= ants_per_block || first_ant >= I.ants) return;  // whole wave idle
 
-  AntRows<STAGED, S> A{};
+  AntRows<STAGED, S, BYTES> A{};
   A.n = n;
   A.k = k;
   A.kg = I.kg;
@@ -1080,14 +1146,14 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   A.lcnt = -1;
 
   for (int w = lane; w < rpw * vis_words; w += WAVE) {
-    const int lo = (w % vis_words) * 32;
-    uint32_t v;
-    if (lo + 32 <= n)
-      v = 0;
-    else if (lo >= n)
-      v = 0xffffffffu;
-    else
-      v = ~((1u << (n - lo)) - 1u);
+    uint32_t v = 0;  // bytes: all clear; bits: the bits past n are set
+    if (!BYTES) {
+      const int lo = (w % vis_words) * 32;
+      if (lo >= n)
+        v = 0xffffffffu;
+      else if (lo + 32 > n)
+        v = ~((1u << (n - lo)) - 1u);
+    }
     A.vis_wave[w] = v;
   }
   __builtin_amdgcn_wave_barrier();
@@ -1098,7 +1164,8 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   const int start = (int)__umulhi(row_bcast<0>(rnd), (uint32_t)n);
   rnd = dpp_zero<0x101>(rnd);  // row_shl:1, step 1's draw to lane 0
   A.cur = start;
-  if (A.u == 0 && A.live) A.vis_g[start >> 5] |= 1u << (start & 31);
+  A.roff = __umul24((uint32_t)start, (uint32_t)k);
+  if (A.u == 0 && A.live) A.mark(start);
   A.fallbacks = 0;
   int tb = start;     // lane (s mod 16) holds T[s] of the current block of 16 steps
   int carry = start;  // T[s0 - 1]
@@ -1402,12 +1469,21 @@ __global__ void __launch_bounds__(64) finish_kernel(const InstDesc* insts, int32
 // ------------------------------------------------------------------------
 int32_t max_lds_bytes() { return 160 * 1024; }
 
+bool construct_bytes_fit(int32_t n, int32_t k, int32_t ants_per_block, int32_t rows_per_wave,
+                         int32_t staged) {
+  // byte marks are used only together with the unvisited lists
+  return n <= 65535 &&
+         construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, true, true).total <=
+             (size_t)max_lds_bytes();
+}
+
 size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t rows_per_wave,
-                           int32_t staged) {
-  // the unvisited lists are included whenever they fit
-  const ConstructLds with = construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, true);
+                           int32_t staged, int32_t bytes) {
+  if (bytes) return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, true, true).total;
+  // bit marks: the unvisited lists are included whenever they fit
+  const ConstructLds with = construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, true, false);
   if (n <= 65535 && with.total <= (size_t)max_lds_bytes()) return with.total;
-  return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, false).total;
+  return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, false, false).total;
 }
 
 hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s) {
@@ -1443,23 +1519,26 @@ int32_t construct_group_lanes(int32_t max_k) { (void)max_k; return 16; }
 
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
-                            int32_t max_k, size_t lds_bytes, hipStream_t s) {
+                            int32_t bytes, int32_t max_k, size_t lds_bytes, hipStream_t s) {
   if (rows_per_wave < 1 || rows_per_wave > 4) return hipErrorInvalidValue;
   const int waves = (ants_per_block + rows_per_wave - 1) / rows_per_wave;
   const dim3 grid(blocks), block(waves * WAVE);
   const int S = max_k <= 16 ? 1 : (max_k <= 32 ? 2 : 4);
-#define HAC_LAUNCH(ST, SL)                                                                 \
-  hipLaunchKernelGGL((construct_kernel<ST, SL>), grid, block, lds_bytes, s, d_insts, d_map, \
+#define HAC_LAUNCH(ST, SL, BY)                                                                 \
+  hipLaunchKernelGGL((construct_kernel<ST, SL, BY>), grid, block, lds_bytes, s, d_insts, d_map, \
                      ants_per_block, rows_per_wave, (int)lds_bytes)
-  if (staged) {
-    if (S == 1) HAC_LAUNCH(true, 1);
-    else if (S == 2) HAC_LAUNCH(true, 2);
-    else HAC_LAUNCH(true, 4);
-  } else {
-    if (S == 1) HAC_LAUNCH(false, 1);
-    else if (S == 2) HAC_LAUNCH(false, 2);
-    else HAC_LAUNCH(false, 4);
+#define HAC_LAUNCH_S(ST, BY)             \
+  {                                      \
+    if (S == 1) HAC_LAUNCH(ST, 1, BY);   \
+    else if (S == 2) HAC_LAUNCH(ST, 2, BY); \
+    else HAC_LAUNCH(ST, 4, BY);          \
   }
+  if (staged) {
+    if (bytes) HAC_LAUNCH_S(true, true) else HAC_LAUNCH_S(true, false)
+  } else {
+    if (bytes) HAC_LAUNCH_S(false, true) else HAC_LAUNCH_S(false, false)
+  }
+#undef HAC_LAUNCH_S
 #undef HAC_LAUNCH
   return hipGetLastError();
 }

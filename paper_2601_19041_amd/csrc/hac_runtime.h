@@ -67,6 +67,7 @@ struct LaunchShape {
   int32_t staged;
   int32_t kmax;
   int32_t rows_per_wave;
+  int32_t bytes;  // visited marks: one byte per node (when they fit every instance) or one bit
 };
 
 // One decode batch: everything from uploaded inputs to results.
@@ -78,7 +79,7 @@ struct Engine {
   // results of the last run
   double construct_ms = 0.0;
   int64_t construct_launches = 0;
-  LaunchShape shape{4, 0, 16, 4};
+  LaunchShape shape{4, 0, 16, 4, 0};
 };
 
 hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_params* p,

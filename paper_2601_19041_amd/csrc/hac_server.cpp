@@ -203,7 +203,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
   hipStream_t s = LN.stream;
   std::vector<BlockMap> map;
   bool dirty = true;
-  LaunchShape shape{4, 0, 16, 4};
+  LaunchShape shape{4, 0, 16, 4, 0};
   InstDesc* d_descs = nullptr;
   int32_t** d_outs = nullptr;
   double* d_lens = nullptr;
@@ -381,7 +381,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
     bool ok = true;
     for (int32_t r = 0; ok && r < rounds; ++r) {
       ok = hip_ok(S, launch_construct(d_descs, d_map, (int32_t)map.size(), shape.ants_per_block,
-                                      shape.rows_per_wave, shape.staged, shape.kmax, lds, s), "construct");
+                                      shape.rows_per_wave, shape.staged, shape.bytes, shape.kmax, lds, s), "construct");
       if (ok && any_ls) ok = hip_ok(S, launch_local_search(d_descs, m, max_n, s), "local search");
       if (ok) ok = hip_ok(S, launch_iter_end(d_descs, m, s), "iter end");
     }

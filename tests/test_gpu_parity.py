@@ -129,6 +129,18 @@ def test_launch_shape_independence(ctx, shape, monkeypatch):
     _same(ctx.decode(inst), oracle.decode(inst), shape)
 
 
+@pytest.mark.parametrize("shape", ["4,0", "8,1", "3,0,1"])
+def test_bit_marks(ctx, shape, monkeypatch):
+    """Visited marks as bits instead of bytes (the form used when bytes do
+    not fit in LDS) give the same tours."""
+    inst = wl.tsp100(instance=5, seed=6, iterations=25)
+    monkeypatch.setenv("HAC_SHAPE", shape)
+    monkeypatch.setenv("HAC_BIT_MARKS", "1")
+    print(f"case bit marks {shape}", flush=True)
+    _same(ctx.decode(inst), oracle.decode(inst), shape)
+    assert ctx.stats()["byte_marks"] == 0
+
+
 @pytest.mark.parametrize("k,shape", [(24, "8,0"), (24, "5,1,1"), (40, "8,1"), (40, "2,0,2"), (64, "4,0")])
 def test_wide_candidate_rows(ctx, k, shape, monkeypatch):
     """k > 16: each lane of an ant's row holds 2 or 4 slots; a batch with
