@@ -98,15 +98,35 @@ def _pairwise(coords: np.ndarray, rows: np.ndarray) -> np.ndarray:
 
 
 def _topk_rows(dist_rows: np.ndarray, rows: np.ndarray, topk: int) -> np.ndarray:
-    """Indices of the `topk` nearest other nodes per row (stable on ties)."""
+    """Indices of the `topk` nearest other nodes per row, ordered by
+    (distance, index).  A partial selection finds them; rows where the
+    selection boundary is tied fall back to a full stable sort, so the
+    result is always that of the stable sort."""
     d = dist_rows.copy()
     d[np.arange(len(rows)), rows] = np.inf
-    idx = np.argsort(d, axis=1, kind="stable")[:, :topk]
+    n = d.shape[1]
+    if topk + 1 >= n:
+        return np.argsort(d, axis=1, kind="stable")[:, :topk]
+    part = np.argpartition(d, topk, axis=1)[:, : topk + 1]
+    pv = np.take_along_axis(d, part, axis=1)
+    order = np.lexsort((part, pv), axis=1)
+    part = np.take_along_axis(part, order, axis=1)
+    pv = np.take_along_axis(pv, order, axis=1)
+    idx = part[:, :topk].copy()
+    # the k-th and (k+1)-th smallest equal: other nodes may share that
+    # distance, and the lowest indices among them must win
+    tied = pv[:, topk - 1] == pv[:, topk]
+    if tied.any():
+        t = np.flatnonzero(tied)
+        idx[t] = np.argsort(d[t], axis=1, kind="stable")[:, :topk]
     return idx
 
 
-def _nn_tour_from_dist_fn(n: int, row_fn) -> np.ndarray:
-    """Greedy nearest-neighbour tour from node 0 (only used to plant edges)."""
+def _nn_tour_from_dist_fn(n: int, row_fn, near: Optional[np.ndarray] = None) -> np.ndarray:
+    """Greedy nearest-neighbour tour from node 0 (only used to plant edges).
+    `near[i]`, if given, lists i's nearest nodes in (distance, index) order:
+    its first unvisited entry is the nearest unvisited node, and only when
+    the list is exhausted is the whole row scanned."""
     visited = np.zeros(n, dtype=bool)
     tour = np.empty(n, dtype=np.int64)
     cur = 0
@@ -115,6 +135,11 @@ def _nn_tour_from_dist_fn(n: int, row_fn) -> np.ndarray:
         visited[cur] = True
         if s == n - 1:
             break
+        if near is not None:
+            free = near[cur][~visited[near[cur]]]
+            if free.size:
+                cur = int(free[0])
+                continue
         row = row_fn(cur).copy()
         row[visited] = np.inf
         cur = int(np.argmin(row))
@@ -149,10 +174,14 @@ def softdist_heatmap(
     if topk < 1:
         return empty_heatmap(n)
     rows_l, cols_l, vals_l = [], [], []
+    kn = min(n - 1, max(topk, 32))  # nearest lists for the planted NN tour
+    near = np.empty((n, kn), dtype=np.int64)
     for a in range(0, n, chunk):
         rows = np.arange(a, min(n, a + chunk))
         dr = _pairwise(coords, rows)
-        idx = _topk_rows(dr, rows, topk)
+        idxk = _topk_rows(dr, rows, kn)
+        near[rows] = idxk
+        idx = idxk[:, :topk]
         dsel = np.take_along_axis(dr, idx, axis=1)
         z = -dsel / temp
         z -= z.max(axis=1, keepdims=True)
@@ -165,7 +194,7 @@ def softdist_heatmap(
     c = np.concatenate(cols_l)
     v = np.concatenate(vals_l)
     # plant a nearest-neighbour tour in both directions
-    tour = _nn_tour_from_dist_fn(n, lambda i: _pairwise(coords, np.array([i]))[0])
+    tour = _nn_tour_from_dist_fn(n, lambda i: _pairwise(coords, np.array([i]))[0], near)
     nxt = np.roll(tour, -1)
     r = np.concatenate([r, tour, nxt])
     c = np.concatenate([c, nxt, tour])
