@@ -343,8 +343,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--cpu-iterations", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--requests", type=int, default=120)
-    ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--requests", type=int, default=240)
+    ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=None,
                     help="only run a device copy of MIB MiB (HBM counter calibration)")
