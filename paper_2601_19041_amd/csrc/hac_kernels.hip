@@ -489,14 +489,24 @@ __device__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP i
     sh_count = n;
   }
   __syncthreads();
+  // A node whose move was just applied is examined again before the queue
+  // moves on; that re-examination rides in wave 0 of the next batch, ahead
+  // of the queue entries, so results are taken in the sequential order.
+  int pend = -1;
   for (;;) {
     const int head = sh_head, count = sh_count;
-    if (count == 0) break;
-    const int nb = min(LS_WAVES, count);
+    const int re = pend >= 0 ? 1 : 0;
+    const int nq = min(LS_WAVES - re, count);  // queue entries in this batch
+    const int nb = nq + re;
+    if (nb == 0) break;
     if (wave < nb) {
-      int slot = head + wave;
-      if (slot >= n) slot -= n;
-      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, queue[slot], min_gain);
+      int node = pend;
+      if (wave >= re) {
+        int slot = head + wave - re;
+        if (slot >= n) slot -= n;
+        node = queue[slot];
+      }
+      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
       if (lane == 0) sh_mv[wave] = m;
     }
     __syncthreads();
@@ -506,7 +516,9 @@ __device__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP i
         f = w;
         break;
       }
-    const int used = f < 0 ? nb : f + 1;  // entries consumed as a sequential scan would
+    // queue entries consumed as a sequential scan would: all of them if no
+    // move improves, else those up to and including the improving one
+    const int used = f < 0 ? nq : max(0, f + 1 - re);
     LsMove m{};
     if (f >= 0) m = sh_mv[f];
     if ((int)threadIdx.x < used) {
@@ -522,40 +534,32 @@ __device__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP i
       sh_count = count - used;
     }
     if (f < 0) {
+      pend = -1;
       __syncthreads();
       continue;
     }
-    // apply the move, queue its end nodes, and examine its node again
-    for (;;) {
-      if (m.dir == 0)
-        ls_reverse(n, tour, pos, m.b, m.c);
-      else
-        ls_reverse(n, tour, pos, m.c, m.b);
-      if (threadIdx.x == 0) {
-        int cnt = sh_count;
-        const int ends[4] = {m.a, m.b, m.c, m.e};
-        for (int z = 0; z < 4; ++z) {
-          const int x = ends[z];
-          if (!inq[x]) {
-            int slot = sh_head + cnt;
-            if (slot >= n) slot -= n;
-            queue[slot] = x;
-            cnt++;
-            inq[x] = 1;
-          }
+    // apply the move and queue its end nodes; its node is examined next
+    if (m.dir == 0)
+      ls_reverse(n, tour, pos, m.b, m.c);
+    else
+      ls_reverse(n, tour, pos, m.c, m.b);
+    if (threadIdx.x == 0) {
+      int cnt = sh_count;
+      const int ends[4] = {m.a, m.b, m.c, m.e};
+      for (int z = 0; z < 4; ++z) {
+        const int x = ends[z];
+        if (!inq[x]) {
+          int slot = sh_head + cnt;
+          if (slot >= n) slot -= n;
+          queue[slot] = x;
+          cnt++;
+          inq[x] = 1;
         }
-        sh_count = cnt;
       }
-      __syncthreads();
-      if (wave == 0) {
-        const LsMove r = ls_eval(G, geo, kg, kls, n, tour, pos, m.a, min_gain);
-        if (lane == 0) sh_mv[0] = r;
-      }
-      __syncthreads();
-      m = sh_mv[0];
-      __syncthreads();
-      if (!m.imp) break;
+      sh_count = cnt;
     }
+    pend = m.a;
+    __syncthreads();
   }
 }
 
