@@ -543,20 +543,21 @@ __device__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP i
       ls_reverse(n, tour, pos, m.b, m.c);
     else
       ls_reverse(n, tour, pos, m.c, m.b);
-    if (threadIdx.x == 0) {
-      int cnt = sh_count;
-      const int ends[4] = {m.a, m.b, m.c, m.e};
-      for (int z = 0; z < 4; ++z) {
-        const int x = ends[z];
-        if (!inq[x]) {
-          int slot = sh_head + cnt;
-          if (slot >= n) slot -= n;
-          queue[slot] = x;
-          cnt++;
-          inq[x] = 1;
-        }
+    // the move's end nodes a, b, c, e (four distinct nodes) join the queue
+    // tail in that order if absent: lanes 0..3 of wave 0 take one each
+    if (threadIdx.x < 4) {
+      const int z = threadIdx.x;
+      const int x = z == 0 ? m.a : (z == 1 ? m.b : (z == 2 ? m.c : m.e));
+      const bool absent = !inq[x];
+      const uint32_t am = (uint32_t)__builtin_amdgcn_ballot_w64(absent) & 0xfu;
+      if (absent) {
+        int slot = sh_head + sh_count + __builtin_popcount(am & ((1u << z) - 1u));
+        if (slot >= n) slot -= n;
+        queue[slot] = x;
+        inq[x] = 1;
       }
-      sh_count = cnt;
+      __builtin_amdgcn_wave_barrier();
+      if (z == 0) sh_count += __builtin_popcount(am);
     }
     pend = m.a;
     __syncthreads();
