@@ -350,8 +350,12 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   // NN tour (+ 2-opt), then the range check on the first bounds
   HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
   bool any_ls = false;
-  for (auto& h : hs) any_ls |= h.p.local_search != 0;
-  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n, s));
+  int32_t all_coords = 1;
+  for (auto& h : hs) {
+    any_ls |= h.p.local_search != 0;
+    if (!h.lay.coords) all_coords = 0;
+  }
+  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n, all_coords, s));
   std::vector<State> sts(count);
   for (int x = 0; x < count; ++x)
     HAC_HIP(hipMemcpyAsync(&sts[x], hs[x].d.st, sizeof(State), hipMemcpyDeviceToHost, s));
@@ -853,11 +857,12 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   LaunchShape used{0, 0, 0, 0, 0};
   if (m > 0) {
     bool any_ls = false;
-    int32_t max_iter = 0, max_n = 0;
+    int32_t max_iter = 0, max_n = 0, all_coords = 1;
     for (auto& h : hs) {
       any_ls |= h.p.local_search != 0;
       max_iter = std::max(max_iter, h.p.iterations);
       max_n = std::max(max_n, h.lay.n);
+      if (!h.lay.coords) all_coords = 0;
     }
     LaunchShape shape{4, 0, 16, 4, 0};
     if (max_iter > 0) {
@@ -879,7 +884,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
                                       shape.bytes, shape.kmax, lds, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
-        e = launch_local_search(d_descs, m, max_n, s);
+        e = launch_local_search(d_descs, m, max_n, all_coords, s);
         if (e != hipSuccess) return e;
       }
       return launch_iter_end(d_descs, m, s);
@@ -896,7 +901,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
                                       shape.bytes, shape.kmax, lds, s));
         CTX_HIP(hipEventRecord(c->events[2 * it + 1], s));
-        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, s));
+        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
       }
       CTX_HIP(hipStreamSynchronize(s));

@@ -68,13 +68,16 @@ struct BlockMap {
 // ---- launchers (defined in hac_kernels.hip) ----
 hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s);
 hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
-hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
+// 2-opt launches: all_coords = 1 when every instance of the batch has
+// coordinates (the FP32-filtered LDS mode needs them)
+hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
+                             hipStream_t s);
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
                             int32_t bytes, int32_t max_k, size_t lds_bytes, hipStream_t s);
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
-                               hipStream_t s);
+                               int32_t all_coords, hipStream_t s);
 hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const* d_out_tours,
                          double* d_out_lens, hipStream_t s);

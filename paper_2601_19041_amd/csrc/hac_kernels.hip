@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "hac_internal.h"
@@ -406,10 +407,28 @@ struct LsMove {
   int imp, a, b, c, e, dir;
 };
 
+// FP32 copy of the coordinates in LDS, used to decide the 2-opt tests
+// without global loads.  M is the largest coordinate magnitude.  With u =
+// 2^-24, rounding the coordinates and computing a distance in FP32 is off
+// by at most 12 u M from the FP64 value, so
+//   d(a,b) - d(a,c)         is within E1 = 2^-19 M (>= 24 u M + rounding),
+//   (ab + ce) - (ac + be)   is within E2 = 2^-17 M (>= 48 u M + 17 u M).
+// A lane whose FP32 result lies inside the bound recomputes its test in
+// FP64 from global memory, so every decision is the FP64 one.
+struct LsFast {
+  const float2* xy;  // null: no FP32 copy
+  double e1, e2;
+  __device__ __forceinline__ float len(int i, int j) const {
+    const float dx = xy[i].x - xy[j].x, dy = xy[i].y - xy[j].y;
+    return __builtin_sqrtf(dx * dx + dy * dy);
+  }
+};
+
 // candidate moves of node a against the current tour (one wave)
 template <class IP>
 __device__ __forceinline__ LsMove ls_eval(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls,
-                                          int n, IP tour, IP pos, int a, double min_gain) {
+                                          int n, IP tour, IP pos, int a, double min_gain,
+                                          const LsFast& F) {
   const int lane = lane_id();
   const bool pred_dir = lane >= 32;
   const int q = lane & 31;
@@ -417,19 +436,50 @@ __device__ __forceinline__ LsMove ls_eval(const GDist& G, const HAC_AS1 int32_t*
   const int c = geo[(int64_t)a * kg + min(q, kls - 1)];
   const int pa = pos[a];
   const int b = pred_dir ? tour[pa == 0 ? n - 1 : pa - 1] : tour[pa + 1 == n ? 0 : pa + 1];
-  const double dab = G.len(a, b);
-  const double dac = G.len(a, c);
-  const double g1 = dab - dac;
+  bool g1pos;  // d(a,b) - d(a,c) > 0, as computed in FP64
+  double dab = 0.0, dac = 0.0;
+  bool have64 = false;
+  if (F.xy) {
+    // c == b gives exactly 0 (no gain); otherwise only list entries whose
+    // FP32 difference lies inside the bound are decided in FP64
+    const double g1f = (double)(F.len(a, b) - F.len(a, c));
+    g1pos = c != b && g1f > F.e1;
+    if (in_list && c != b && !(g1f > F.e1) && !(g1f < -F.e1)) {
+      dab = G.len(a, b);
+      dac = G.len(a, c);
+      have64 = true;
+      g1pos = dab - dac > 0.0;
+    }
+  } else {
+    dab = G.len(a, b);
+    dac = G.len(a, c);
+    have64 = true;
+    g1pos = dab - dac > 0.0;
+  }
   // a direction stops at the first list entry that cannot gain
-  const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !(g1 > 0.0));
+  const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !g1pos);
   const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
   const int lim_s = stop_s ? (int)__builtin_ctzll(stop_s) : 32;
   const int lim_p = stop_p ? (int)__builtin_ctzll(stop_p) : 32;
   const bool ok = in_list && q < (pred_dir ? lim_p : lim_s);
   const int pc = pos[c];
   const int e = pred_dir ? tour[pc == 0 ? n - 1 : pc - 1] : tour[pc + 1 == n ? 0 : pc + 1];
-  const double gain = (dab + G.len(c, e)) - (dac + G.len(b, e));
-  const bool imp = ok && e != a && c != b && gain > min_gain;
+  const bool cand = ok && e != a && c != b;  // a move that may be taken
+  bool imp;
+  if (F.xy) {
+    const double gf = (double)((F.len(a, b) + F.len(c, e)) - (F.len(a, c) + F.len(b, e)));
+    imp = gf > min_gain + F.e2;
+    if (cand && !(gf > min_gain + F.e2) && !(gf < min_gain - F.e2)) {
+      if (!have64) {
+        dab = G.len(a, b);
+        dac = G.len(a, c);
+      }
+      imp = (dab + G.len(c, e)) - (dac + G.len(b, e)) > min_gain;
+    }
+  } else {
+    imp = (dab + G.len(c, e)) - (dac + G.len(b, e)) > min_gain;
+  }
+  imp = imp && cand;
   const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
   LsMove m{0, a, 0, 0, 0, 0};
   if (mi) {
@@ -471,7 +521,8 @@ __device__ __forceinline__ void ls_reverse(int n, IP tour, IP pos, int x, int y)
 }
 
 template <class IP, class BP>
-__device__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain) {
+__device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain,
+                              const LsFast& F) {
   __shared__ int sh_head, sh_count;
   __shared__ LsMove sh_mv[LS_WAVES];
   const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
@@ -506,7 +557,7 @@ __device__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP i
         if (slot >= n) slot -= n;
         node = queue[slot];
       }
-      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
+      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, node, min_gain, F);
       if (lane == 0) sh_mv[wave] = m;
     }
     __syncthreads();
@@ -564,25 +615,56 @@ __device__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP i
   }
 }
 
-// Working arrays of the 2-opt: tour, pos and queue (int32) and the
-// in-queue flags (uint8), in LDS when 13n bytes fit, else in global memory
-// (the tour in place, the rest in the instance's work area).
-static __host__ __device__ inline size_t ls_lds_need(int n) {
-  return (((size_t)13 * n + 15) / 16) * 16;
+// Working arrays of the 2-opt, by mode:
+//   2: tour, pos and queue as uint16, in-queue flags as uint8 and an FP32
+//      copy of the coordinates, all in LDS (15 bytes per node, n < 65536,
+//      coordinate instances);
+//   1: tour, pos and queue as int32 and the flags in LDS (13 bytes per node);
+//   0: global memory (the tour in place, the rest in the work area).
+static __host__ __device__ inline size_t ls_lds_need(int n, int mode) {
+  if (mode == 2) return ((size_t)6 * n + 15) / 16 * 16 + ((size_t)n + 15) / 16 * 16 + (size_t)8 * n;
+  if (mode == 1) return (((size_t)13 * n + 15) / 16) * 16;
+  return 0;
 }
 
-template <bool IN_LDS>
-__device__ void two_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain) {
+template <int MODE>
+__device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain) {
   extern __shared__ int32_t ls_lds[];
   const int n = D.n;
-  if (IN_LDS) {
+  LsFast F{nullptr, 0.0, 0.0};
+  if constexpr (MODE == 2) {
+    uint16_t* tour = reinterpret_cast<uint16_t*>(ls_lds);
+    uint16_t* pos = tour + n;
+    uint16_t* queue = pos + n;
+    uint8_t* inq = reinterpret_cast<uint8_t*>(ls_lds) + ((size_t)6 * n + 15) / 16 * 16;
+    float2* xyf = reinterpret_cast<float2*>(reinterpret_cast<uint8_t*>(inq) + ((size_t)n + 15) / 16 * 16);
+    __shared__ double sh_m[LS_WAVES];
+    double mloc = 0.0;
+    const HAC_AS1 double* xy = as_global(D.xy);
+    for (int s = threadIdx.x; s < n; s += blockDim.x) {
+      tour[s] = (uint16_t)tour_g[s];
+      const double x = xy[2 * s], y = xy[2 * s + 1];
+      xyf[s] = make_float2((float)x, (float)y);
+      mloc = fmax(mloc, fmax(fabs(x), fabs(y)));
+    }
+    // largest coordinate magnitude (for the FP32 error bounds)
+    for (int off = 32; off >= 1; off >>= 1) mloc = fmax(mloc, __shfl_xor(mloc, off));
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh_m[threadIdx.x / WAVE] = mloc;
+    __syncthreads();
+    double M = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) M = fmax(M, sh_m[w]);
+    F = LsFast{xyf, M * 0x1p-19, M * 0x1p-17};
+    two_opt_block(D, tour, pos, queue, inq, min_gain, F);
+    __syncthreads();
+    for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
+  } else if constexpr (MODE == 1) {
     int32_t* tour = ls_lds;
     int32_t* pos = tour + n;
     int32_t* queue = pos + n;
     uint8_t* inq = reinterpret_cast<uint8_t*>(queue + n);
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour[s] = tour_g[s];
     __syncthreads();
-    two_opt_block(D, tour, pos, queue, inq, min_gain);
+    two_opt_block(D, tour, pos, queue, inq, min_gain, F);
     __syncthreads();
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
   } else {
@@ -590,7 +672,7 @@ __device__ void two_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain
     HAC_AS1 int32_t* pos = as_global(D.ls_work);
     HAC_AS1 int32_t* queue = pos + n;
     HAC_AS1 uint8_t* inq = reinterpret_cast<HAC_AS1 uint8_t*>(queue + n);
-    two_opt_block(D, tour, pos, queue, inq, min_gain);
+    two_opt_block(D, tour, pos, queue, inq, min_gain, F);
   }
   __threadfence_block();
   __syncthreads();
@@ -598,11 +680,11 @@ __device__ void two_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain
 
 // 2-opt of the NN tour (preparation, local search enabled).  One block per
 // instance.
-template <bool IN_LDS>
+template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) two_opt_nn_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search) return;
-  two_opt_tour<IN_LDS>(D, D.nn_tour, D.st->min_gain);
+  two_opt_tour<MODE>(D, D.nn_tour, D.st->min_gain);
   if (threadIdx.x < WAVE) {
     const double len = tour_length_wave(D, D.nn_tour);
     if (threadIdx.x == 0) {
@@ -1237,7 +1319,7 @@ __device__ void iteration_best_wave(const InstDesc& D, int& ib, double& lib) {
   lib = bk;
 }
 
-template <bool IN_LDS>
+template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || D.st->t > D.iterations) return;
@@ -1255,7 +1337,7 @@ __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const Ins
   for (int s = threadIdx.x; s < n; s += blockDim.x) D.t_ib[s] = src[s];
   __threadfence_block();
   __syncthreads();
-  two_opt_tour<IN_LDS>(D, D.t_ib, D.st->min_gain);
+  two_opt_tour<MODE>(D, D.t_ib, D.st->min_gain);
   if (threadIdx.x < WAVE) {
     const double len = tour_length_wave(D, D.t_ib);
     if (threadIdx.x == 0) {
@@ -1504,14 +1586,32 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
   return hipGetLastError();
 }
 
-static bool ls_in_lds(int32_t max_n) { return ls_lds_need(max_n) + 1024 <= (size_t)max_lds_bytes(); }
+// the 2-opt mode of a launch: 2 when every instance of the batch has
+// coordinates and fits, else 1 when the int32 arrays fit, else 0
+static int ls_mode(int32_t max_n, int32_t all_coords) {
+  const size_t cap = (size_t)max_lds_bytes() - 1024;  // static shared variables
+  if (const char* f = std::getenv("HAC_LS_MODE")) {
+    // pins a mode when it fits (used to show the modes give the same tours)
+    const int m = std::atoi(f);
+    if (m == 0 || (m == 1 && ls_lds_need(max_n, 1) <= cap) ||
+        (m == 2 && all_coords && max_n < 65536 && ls_lds_need(max_n, 2) <= cap))
+      return m;
+  }
+  if (all_coords && max_n < 65536 && ls_lds_need(max_n, 2) <= cap) return 2;
+  if (ls_lds_need(max_n, 1) <= cap) return 1;
+  return 0;
+}
 
-hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s) {
-  if (ls_in_lds(max_n))
-    hipLaunchKernelGGL(two_opt_nn_kernel<true>, dim3(count), dim3(LS_WAVES * WAVE), ls_lds_need(max_n),
-                       s, d_insts);
+hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
+                             hipStream_t s) {
+  const int mode = ls_mode(max_n, all_coords);
+  const dim3 grid(count), block(LS_WAVES * WAVE);
+  if (mode == 2)
+    hipLaunchKernelGGL(two_opt_nn_kernel<2>, grid, block, ls_lds_need(max_n, 2), s, d_insts);
+  else if (mode == 1)
+    hipLaunchKernelGGL(two_opt_nn_kernel<1>, grid, block, ls_lds_need(max_n, 1), s, d_insts);
   else
-    hipLaunchKernelGGL(two_opt_nn_kernel<false>, dim3(count), dim3(LS_WAVES * WAVE), 0, s, d_insts);
+    hipLaunchKernelGGL(two_opt_nn_kernel<0>, grid, block, 0, s, d_insts);
   return hipGetLastError();
 }
 
@@ -1549,12 +1649,15 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
 }
 
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
-                               hipStream_t s) {
-  if (ls_in_lds(max_n))
-    hipLaunchKernelGGL(local_search_kernel<true>, dim3(count), dim3(LS_WAVES * WAVE),
-                       ls_lds_need(max_n), s, d_insts);
+                               int32_t all_coords, hipStream_t s) {
+  const int mode = ls_mode(max_n, all_coords);
+  const dim3 grid(count), block(LS_WAVES * WAVE);
+  if (mode == 2)
+    hipLaunchKernelGGL(local_search_kernel<2>, grid, block, ls_lds_need(max_n, 2), s, d_insts);
+  else if (mode == 1)
+    hipLaunchKernelGGL(local_search_kernel<1>, grid, block, ls_lds_need(max_n, 1), s, d_insts);
   else
-    hipLaunchKernelGGL(local_search_kernel<false>, dim3(count), dim3(LS_WAVES * WAVE), 0, s, d_insts);
+    hipLaunchKernelGGL(local_search_kernel<0>, grid, block, 0, s, d_insts);
   return hipGetLastError();
 }
 

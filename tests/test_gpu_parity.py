@@ -70,11 +70,23 @@ def test_tsp100_seeds(ctx, seed):
     _same(ctx.decode(inst), oracle.decode(inst), f"seed{seed}")
 
 
-@pytest.mark.parametrize("name", ["atsp", "symmatrix", "ls", "empty", "grid_ties", "k_full",
-                                  "scope1", "ugb_restart"])
+@pytest.mark.parametrize("name", ["atsp", "symmatrix", "ls", "symmatrix_ls", "ls_grid", "ls_offset", "empty",
+                                  "grid_ties", "k_full", "scope1", "ugb_restart"])
 def test_small_variants(ctx, name):
     over = {}
-    if name == "atsp":
+    if name == "symmatrix_ls":
+        # 2-opt on a distance matrix: int32 working arrays, no FP32 filter
+        inst = wl.random_instance(120, seed=13, kind="matrix", symmetric=True, k=8, ants=10, iterations=20,
+                                  local_search=1, k_ls=10)
+    elif name == "ls_grid":
+        # lattice points: many equal distances, so the FP32 2-opt tests fall
+        # inside their error bound and are decided in FP64
+        inst = wl.random_instance(140, seed=14, grid=13, k=10, ants=10, iterations=20, local_search=1, k_ls=12)
+    elif name == "ls_offset":
+        # far from the origin: the FP32 error bounds scale with the largest coordinate
+        inst = wl.random_instance(150, seed=15, k=10, ants=10, iterations=20, local_search=1, k_ls=12)
+        inst.coords = inst.coords * 1e5 + 3e6
+    elif name == "atsp":
         inst = wl.random_instance(60, seed=5, kind="matrix", symmetric=False, k=8, ants=12, iterations=30)
     elif name == "symmatrix":
         inst = wl.random_instance(60, seed=6, kind="matrix", symmetric=True, k=8, ants=12, iterations=30)
@@ -165,3 +177,14 @@ def test_invalid_inputs_leave_outputs(ctx):
     assert ctx.decode_status(inst, alpha=2.0) == hac.HAC_EUNSUPPORTED
     assert ctx.decode_status(inst, k=65) == hac.HAC_EUNSUPPORTED
     assert ctx.decode_status(inst) == hac.HAC_OK
+
+
+@pytest.mark.parametrize("mode", ["0", "1", "2"])
+def test_two_opt_modes(ctx, mode, monkeypatch):
+    """The 2-opt working-array modes (global memory; int32 arrays in LDS;
+    uint16 arrays with FP32 coordinates in LDS and FP64 rechecks inside the
+    error bound) give the same tours."""
+    inst = wl.random_instance(600, seed=21, k=10, ants=8, iterations=6, local_search=1, k_ls=16)
+    monkeypatch.setenv("HAC_LS_MODE", mode)
+    print(f"case 2-opt mode {mode}", flush=True)
+    _same(ctx.decode(inst), oracle.decode(inst), f"ls mode {mode}")
