@@ -409,10 +409,11 @@ struct LsMove {
 
 // FP32 copy of the coordinates in LDS, used to decide the 2-opt tests
 // without global loads.  M is the largest coordinate magnitude.  With u =
-// 2^-24, rounding the coordinates and computing a distance in FP32 is off
-// by at most 12 u M from the FP64 value, so
-//   d(a,b) - d(a,c)         is within E1 = 2^-19 M (>= 24 u M + rounding),
-//   (ab + ce) - (ac + be)   is within E2 = 2^-17 M (>= 48 u M + 17 u M).
+// 2^-24, rounding the coordinates and computing a distance in FP32 (a
+// square root within a few ulp) is off by at most 17 u M from the FP64
+// value, so
+//   d(a,b) - d(a,c)         is within E1 = 2^-18 M (>= 34 u M + rounding),
+//   (ab + ce) - (ac + be)   is within E2 = 2^-17 M (>= 68 u M + 17 u M).
 // A lane whose FP32 result lies inside the bound recomputes its test in
 // FP64 from global memory, so every decision is the FP64 one.
 struct LsFast {
@@ -653,7 +654,7 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
     __syncthreads();
     double M = 0.0;
     for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) M = fmax(M, sh_m[w]);
-    F = LsFast{xyf, M * 0x1p-19, M * 0x1p-17};
+    F = LsFast{xyf, M * 0x1p-18, M * 0x1p-17};
     two_opt_block(D, tour, pos, queue, inq, min_gain, F);
     __syncthreads();
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
