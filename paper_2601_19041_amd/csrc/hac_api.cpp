@@ -145,6 +145,7 @@ Layout make_layout(const hac_instance* inst, const hac_csr* csr, const hac_param
   L.coords = inst->kind == HAC_COORDS_EUC2D;
   L.ls = p->local_search != 0;
   L.nnz = csr->nnz;
+  L.gside = (L.coords && L.n >= kGridMinN) ? grid_side(L.n) : 0;
   return L;
 }
 
@@ -158,6 +159,11 @@ size_t Layout::bytes() const {
   b += align256(4 * nn * (size_t)ants) + align256(8 * (size_t)ants);
   b += 6 * align256(4 * nn);
   b += ls ? align256(12 * nn) : 0;
+  if (gside > 0) {
+    const size_t cells = (size_t)gside * gside;
+    b += align256(4 * (cells + 1)) + align256(4 * cells) + align256(4 * nn) + align256(16 * nn) +
+         align256(sizeof(GridPar));
+  }
   b += align256(sizeof(State));
   b += 3 * align256(8 * (size_t)std::max(iterations, 1));
   return b;
@@ -187,6 +193,19 @@ void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve) {
   d.succ = (int32_t*)carve(4 * nn);
   d.pred = (int32_t*)carve(4 * nn);
   d.ls_work = L.ls ? (int32_t*)carve(12 * nn) : nullptr;
+  d.gside = L.gside;
+  if (L.gside > 0) {
+    const size_t cells = (size_t)L.gside * L.gside;
+    d.g_start = (int32_t*)carve(4 * (cells + 1));
+    d.g_cur = (int32_t*)carve(4 * cells);
+    d.g_ids = (int32_t*)carve(4 * nn);
+    d.g_xy = (double*)carve(16 * nn);
+    d.g_par = (GridPar*)carve(sizeof(GridPar));
+  } else {
+    d.g_start = d.g_cur = d.g_ids = nullptr;
+    d.g_xy = nullptr;
+    d.g_par = nullptr;
+  }
   d.st = (State*)carve(sizeof(State));
   const size_t it = 8 * (size_t)std::max(L.iterations, 1);
   d.tr_lib = (double*)carve(it);
@@ -347,7 +366,8 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
     const size_t nk = (size_t)h.lay.n * h.lay.k;
     HAC_HIP(hipMemcpyAsync((void*)h.d.heur, heur[x].data(), 4 * nk, hipMemcpyHostToDevice, s));
   }
-  // NN tour (+ 2-opt), then the range check on the first bounds
+  // coordinate grids, NN tour (+ 2-opt), then the range check on the first bounds
+  HAC_HIP(launch_grid(d_descs, count, s));
   HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
   bool any_ls = false;
   int32_t all_coords = 1;

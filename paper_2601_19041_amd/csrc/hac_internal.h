@@ -22,6 +22,22 @@ struct State {
   unsigned long long fallbacks;  // nearest-unvisited steps so far
 };
 
+// Uniform grid over the coordinates of a coordinate instance with
+// n >= kGridMinN, for exact nearest-unvisited searches by rings of cells.
+// A node's cell is min(side - 1, floor((x - x0) * ix)) per axis; wmin is a
+// lower bound on the cell widths 1/ix, 1/iy (shrunk by 1e-9 relative).
+struct GridPar {
+  int32_t gx, gy;
+  double x0, y0, ix, iy, wmin;
+};
+static constexpr int32_t kGridMinN = 2048;
+// cells per side: about two nodes per cell
+__host__ __device__ inline int32_t grid_side(int32_t n) {
+  int32_t g = 1;
+  while ((int64_t)(g + 1) * (g + 1) * 2 <= (int64_t)n) ++g;
+  return g;
+}
+
 // Everything a kernel needs to know about one instance.  Pointers are
 // device pointers into the instance's slot.
 struct InstDesc {
@@ -53,6 +69,12 @@ struct InstDesc {
   int32_t* succ;              // [n]
   int32_t* pred;              // [n]
   int32_t* ls_work;           // [3n] pos, queue, in-queue for 2-opt
+  int32_t gside;              // grid cells per side (0: no grid)
+  int32_t* g_start;           // [side^2 + 1] first slot of each cell
+  int32_t* g_cur;             // [side^2] build cursors
+  int32_t* g_ids;             // [n] node ids, grouped by cell
+  double* g_xy;               // [n][2] their coordinates, same order
+  GridPar* g_par;             // filled by the grid build
   State* st;
   double* tr_lib;             // [iterations] or null
   double* tr_lgb;             // [iterations] or null
@@ -73,6 +95,8 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
                              hipStream_t s);
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
+// builds the coordinate grid of every instance that has one
+hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
                             int32_t bytes, int32_t max_k, size_t lds_bytes, hipStream_t s);

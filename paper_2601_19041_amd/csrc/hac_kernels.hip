@@ -331,15 +331,128 @@ struct VisBytes {
   __device__ __forceinline__ bool operator()(int v) const { return p[v] != 0; }
 };
 
+// ------------------------------------------------------------------------
+// Exact nearest-unvisited search over a uniform grid (coordinate instances
+// with n >= kGridMinN).  Rings of cells around i's cell are examined
+// wave-wide, one cell per lane at a time; after rings 0..R every node not
+// yet examined lies at least R * wmin away, so the search stops once the
+// best (key, index) found has key < (R wmin)^2.  The key is the one every
+// scan uses (squared FP64 distance), so the result is that of a full scan.
+// ------------------------------------------------------------------------
+struct GridView {
+  const HAC_AS1 int32_t* start = nullptr;
+  const HAC_AS1 int32_t* ids = nullptr;
+  const HAC_AS1 double* xy = nullptr;
+  GridPar par{};
+  __device__ __forceinline__ int cellx(double x) const {
+    const int c = (int)((x - par.x0) * par.ix);
+    return c < 0 ? 0 : (c >= par.gx ? par.gx - 1 : c);
+  }
+  __device__ __forceinline__ int celly(double y) const {
+    const int c = (int)((y - par.y0) * par.iy);
+    return c < 0 ? 0 : (c >= par.gy ? par.gy - 1 : c);
+  }
+};
+
+__device__ __forceinline__ int ring_cells(int r) { return r == 0 ? 1 : 8 * r; }
+
+// cell offset of entry t of ring r (r >= 1): top row, bottom row, left and
+// right columns
+__device__ __forceinline__ void ring_cell(int r, int t, int& dx, int& dy) {
+  if (r == 0) {
+    dx = dy = 0;
+  } else if (t < 2 * r + 1) {
+    dx = t - r;
+    dy = -r;
+  } else if (t < 4 * r + 2) {
+    dx = t - (2 * r + 1) - r;
+    dy = r;
+  } else if (t < 6 * r + 1) {
+    dx = -r;
+    dy = t - (4 * r + 2) - (r - 1);
+  } else {
+    dx = r;
+    dy = t - (6 * r + 1) - (r - 1);
+  }
+}
+
+template <class V>
+__device__ int grid_nearest(const GridView& g, int n, double xi, double yi, V visited) {
+  const int lane = lane_id();
+  const int cxi = g.cellx(xi), cyi = g.celly(yi);
+  const int rmax = max(max(cxi, g.par.gx - 1 - cxi), max(cyi, g.par.gy - 1 - cyi));
+  double bk = __builtin_huge_val();
+  int bj = 0x7fffffff;
+  for (int r0 = 0;;) {
+    // this pass: rings r0..r1, at most two cells per lane unless one ring is larger
+    int r1 = r0, cells = ring_cells(r0);
+    while (r1 < rmax && cells + ring_cells(r1 + 1) <= 2 * WAVE) {
+      ++r1;
+      cells += ring_cells(r1);
+    }
+    for (int t = lane; t < cells; t += WAVE) {
+      int r = r0, tt = t;
+      while (tt >= ring_cells(r)) {
+        tt -= ring_cells(r);
+        ++r;
+      }
+      int dx, dy;
+      ring_cell(r, tt, dx, dy);
+      const int cx = cxi + dx, cy = cyi + dy;
+      if (cx < 0 || cy < 0 || cx >= g.par.gx || cy >= g.par.gy) continue;
+      const int c = cy * g.par.gx + cx;
+      const int s = g.start[c], e = g.start[c + 1];
+      for (int p0 = s; p0 < e; p0 += 4) {
+        int id[4];
+        double px[4], py[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int p = min(p0 + u, e - 1);
+          id[u] = g.ids[p];
+          px[u] = g.xy[2 * p];
+          py[u] = g.xy[2 * p + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (p0 + u < e && !visited(id[u])) {
+            const double ddx = xi - px[u], ddy = yi - py[u];
+            const double kj = ddx * ddx + ddy * ddy;
+            if (key_less(kj, id[u], bk, bj)) {
+              bk = kj;
+              bj = id[u];
+            }
+          }
+        }
+      }
+    }
+    wave_argmin(bk, bj);
+    const double bound = (double)r1 * g.par.wmin;
+    if (bk < bound * bound || r1 >= rmax) return bj < n ? bj : n - 1;
+    r0 = r1 + 1;
+  }
+}
+
+__device__ __forceinline__ GridView grid_view(const InstDesc& D) {
+  GridView g;
+  if (D.gside > 0) {
+    g.start = as_global((const int32_t*)D.g_start);
+    g.ids = as_global((const int32_t*)D.g_ids);
+    g.xy = as_global((const double*)D.g_xy);
+    g.par = *D.g_par;
+  }
+  return g;
+}
+
 // Nearest unvisited node to i by (key, index), for the preparation kernels.
 template <int CH, class V>
 __device__ int scan_unvisited_g(const GDist& G, int i, V visited);
 template <class V>
 __device__ __forceinline__ int geo_first_unvisited(const HAC_AS1 int32_t* geo, int kg, int i,
                                                    V visited);
-__device__ int nearest_unvisited(const InstDesc& D, int i, const uint32_t* vis) {
+__device__ int nearest_unvisited(const InstDesc& D, const GridView& g, int i, const uint32_t* vis) {
   const int jg = geo_first_unvisited(as_global(D.geo), D.kg, i, VisBits{vis});
   if (jg >= 0) return jg;
+  if (D.gside > 0) return grid_nearest(g, D.n, D.xy[2 * i], D.xy[2 * i + 1], VisBits{vis});
   return scan_unvisited_g<8>(GDist(D), i, VisBits{vis});
 }
 
@@ -367,8 +480,9 @@ __global__ void __launch_bounds__(64) nn_tour_kernel(const InstDesc* insts) {
     vis[0] |= 1u;
   }
   __syncthreads();
+  const GridView g = grid_view(D);
   for (int s = 1; s < n; ++s) {
-    int j = nearest_unvisited(D, cur, vis);
+    int j = nearest_unvisited(D, g, cur, vis);
     if (lane == 0) {
       tour[s] = j;
       vis[j >> 5] |= 1u << (j & 31);
@@ -996,6 +1110,11 @@ __device__ __forceinline__ uint32_t row_scan(uint32_t v) {
   return v;
 }
 
+// With a grid and an unvisited list both available, the list is scanned
+// once at most this many nodes are left: the nearest unvisited node is then
+// far away in cells, while the compacted list is short.
+constexpr int kListScanMax = 1024;
+
 template <bool STAGED, int S, bool BYTES>
 struct AntRows {
   int n, k, kg, u, g;
@@ -1022,9 +1141,11 @@ struct AntRows {
     else
       atomicOr(&vis_g[v >> 5], 1u << (v & 31));
   }
+  GridView grid;        // coordinate grid (grid.start null: none)
   uint16_t* list_wave;  // unvisited lists of the wave's live rows, list_stride apart (or null)
   int list_stride;
   int lcnt;             // this row's list length (-1: all nodes)
+  int left;             // unvisited nodes before this step's choice (same in every row of the wave)
   bool live;
   int cur;       // the row's current node (same in all its lanes)
   uint32_t roff;  // cur * k: the first slot of cur's candidate row
@@ -1110,6 +1231,7 @@ struct AntRows {
       j = fallback(exhausted, j, ga, gb);
       if (exhausted) roff = __umul24((uint32_t)j, (uint32_t)k);
     }
+    --left;
     return j;
   }
 
@@ -1141,7 +1263,11 @@ struct AntRows {
       else
         vv = VisBits{vw_};
       int jj;
-      if (list_wave) {
+      if (grid.start && (!list_wave || left > kListScanMax)) {
+        const double xi = xy_lds ? xy_lds[ii].x : D.xy[2 * ii];
+        const double yi = xy_lds ? xy_lds[ii].y : D.xy[2 * ii + 1];
+        jj = grid_nearest(grid, n, xi, yi, vv);
+      } else if (list_wave) {
         int cnt = rd_lane(lcnt, lead);
         jj = (STAGED && xy_lds) ? scan_list_any<4>(D, xy_lds, ii, vv, list_wave + gg * list_stride, cnt)
                                 : scan_list_any<8>(D, nullptr, ii, vv, list_wave + gg * list_stride, cnt);
@@ -1225,6 +1351,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   A.cw_g = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.cw));
   A.xy_lds = xy_lds;
   A.D = GDist(I);
+  A.grid = grid_view(I);
   A.geo = as_global(I.geo);
   A.vis_words = vis_words;
   A.vis_wave = lds + wave * rpw * vis_words;
@@ -1255,6 +1382,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   A.roff = __umul24((uint32_t)start, (uint32_t)k);
   if (A.u == 0 && A.live) A.mark(start);
   A.fallbacks = 0;
+  A.left = n - 1;
   int tb = start;     // lane (s mod 16) holds T[s] of the current block of 16 steps
   int carry = start;  // T[s0 - 1]
   double len = 0.0;
@@ -1613,6 +1741,106 @@ hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max
     hipLaunchKernelGGL(two_opt_nn_kernel<1>, grid, block, ls_lds_need(max_n, 1), s, d_insts);
   else
     hipLaunchKernelGGL(two_opt_nn_kernel<0>, grid, block, 0, s, d_insts);
+  return hipGetLastError();
+}
+
+// One block per instance with a grid: bounding box, cell widths, counting
+// sort of the nodes by cell (order inside a cell is irrelevant to the
+// search), and the coordinates copied in cell order.
+__global__ void __launch_bounds__(1024) grid_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.x];
+  if (D.gside <= 0) return;
+  __shared__ double sh[4][32];
+  __shared__ GridPar sp;
+  __shared__ int s_tot[1024];
+  const int n = D.n, G = D.gside, cells = G * G, tid = threadIdx.x, nt = blockDim.x;
+  const HAC_AS1 double* xy = as_global(D.xy);
+  double lx = __builtin_huge_val(), ly = lx, hx = -lx, hy = -lx;
+  for (int j = tid; j < n; j += nt) {
+    const double x = xy[2 * j], y = xy[2 * j + 1];
+    lx = fmin(lx, x);
+    ly = fmin(ly, y);
+    hx = fmax(hx, x);
+    hy = fmax(hy, y);
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    lx = fmin(lx, __shfl_xor(lx, off));
+    ly = fmin(ly, __shfl_xor(ly, off));
+    hx = fmax(hx, __shfl_xor(hx, off));
+    hy = fmax(hy, __shfl_xor(hy, off));
+  }
+  if ((tid & (WAVE - 1)) == 0) {
+    sh[0][tid / WAVE] = lx;
+    sh[1][tid / WAVE] = ly;
+    sh[2][tid / WAVE] = hx;
+    sh[3][tid / WAVE] = hy;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < nt / WAVE; ++w) {
+      lx = fmin(lx, sh[0][w]);
+      ly = fmin(ly, sh[1][w]);
+      hx = fmax(hx, sh[2][w]);
+      hy = fmax(hy, sh[3][w]);
+    }
+    lx = fmin(lx, sh[0][0]);
+    ly = fmin(ly, sh[1][0]);
+    hx = fmax(hx, sh[2][0]);
+    hy = fmax(hy, sh[3][0]);
+    GridPar P;
+    P.gx = P.gy = G;
+    P.x0 = lx;
+    P.y0 = ly;
+    P.ix = hx > lx ? (double)G / (hx - lx) : 0.0;
+    P.iy = hy > ly ? (double)G / (hy - ly) : 0.0;
+    const double im = fmax(P.ix, P.iy);
+    P.wmin = im > 0.0 ? (1.0 / im) * (1.0 - 1e-9) : 0.0;
+    sp = P;
+    *D.g_par = P;
+  }
+  for (int c = tid; c < cells; c += nt) D.g_cur[c] = 0;
+  __syncthreads();
+  GridView g;
+  g.par = sp;
+  for (int j = tid; j < n; j += nt) {
+    const int c = g.celly(xy[2 * j + 1]) * G + g.cellx(xy[2 * j]);
+    atomicAdd(&D.g_cur[c], 1);
+  }
+  __syncthreads();
+  // exclusive prefix of the counts: each thread a contiguous chunk of cells
+  const int chunk = (cells + nt - 1) / nt;
+  const int c0 = min(cells, tid * chunk), c1 = min(cells, c0 + chunk);
+  int local = 0;
+  for (int c = c0; c < c1; ++c) local += D.g_cur[c];
+  s_tot[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const int v = tid >= off ? s_tot[tid - off] : 0;
+    __syncthreads();
+    s_tot[tid] += v;
+    __syncthreads();
+  }
+  int run = s_tot[tid] - local;
+  for (int c = c0; c < c1; ++c) {
+    const int k = D.g_cur[c];
+    D.g_start[c] = run;
+    D.g_cur[c] = run;
+    run += k;
+  }
+  if (tid == 0) D.g_start[cells] = n;
+  __syncthreads();
+  for (int j = tid; j < n; j += nt) {
+    const double x = xy[2 * j], y = xy[2 * j + 1];
+    const int c = g.celly(y) * G + g.cellx(x);
+    const int p = atomicAdd(&D.g_cur[c], 1);
+    D.g_ids[p] = j;
+    D.g_xy[2 * p] = x;
+    D.g_xy[2 * p + 1] = y;
+  }
+}
+
+hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s) {
+  hipLaunchKernelGGL(grid_kernel, dim3(count), dim3(1024), 0, s, d_insts);
   return hipGetLastError();
 }
 

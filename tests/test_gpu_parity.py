@@ -179,6 +179,39 @@ def test_invalid_inputs_leave_outputs(ctx):
     assert ctx.decode_status(inst) == hac.HAC_OK
 
 
+def _grid_case(name):
+    """Coordinate instances large enough for the uniform-grid search."""
+    rng = np.random.default_rng(40)
+    if name == "clusters":
+        # tight clusters: the geometric lists run out whenever an ant leaves
+        # one, so most fallbacks reach the grid search
+        centres = rng.random((40, 2))
+        xy = (centres[:, None, :] + 0.004 * rng.random((40, 60, 2))).reshape(-1, 2)
+    elif name == "lattice":
+        # distinct lattice points: equal keys across cells and rings
+        cells = rng.permutation(50 * 50)[:2100]
+        xy = np.stack([cells % 50, cells // 50], 1).astype(np.float64) / 50
+    else:
+        # every x equal: a bounding box of zero width
+        xy = np.stack([np.full(2048, 0.5), rng.permutation(2048) / 2048.0], 1)
+    xy = np.ascontiguousarray(xy)
+    hm = wl.softdist_heatmap(xy, 6)
+    return wl.Instance(len(xy), "coords", True, xy, None, hm, ants=8, iterations=3, k=6, seed=41,
+                       name=f"grid-{name}")
+
+
+@pytest.mark.parametrize("name", ["clusters", "lattice", "line"])
+def test_grid_search(ctx, name):
+    """n >= 2048 coordinates: nearest-unvisited searches go through the
+    uniform grid and must return the (key, index) minimum of a full scan."""
+    inst = _grid_case(name)
+    print(f"case grid {name} n={inst.n}", flush=True)
+    _same(ctx.decode(inst), oracle.decode(inst), name)
+    info = _state_parity(ctx, inst)
+    assert info["fallback_steps"] > 0
+    assert ctx.stats()["fallback_steps"] == info["fallback_steps"]
+
+
 @pytest.mark.parametrize("mode", ["0", "1", "2"])
 def test_two_opt_modes(ctx, mode, monkeypatch):
     """The 2-opt working-array modes (global memory; int32 arrays in LDS;
