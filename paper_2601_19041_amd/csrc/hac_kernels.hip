@@ -81,6 +81,9 @@ struct OpMin {
 struct OpOr {
   __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a | b; }
 };
+struct OpAdd {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; }
+};
 struct OpMinI {
   __device__ uint32_t operator()(uint32_t a, uint32_t b) const {
     return (int32_t)a < (int32_t)b ? a : b;
@@ -1118,8 +1121,12 @@ constexpr int kListScanMax = 1024;
 template <bool STAGED, int S, bool BYTES>
 struct AntRows {
   int n, k, kg, u, g;
-  const uint64_t* cw_lds;
-  const HAC_AS1 uint64_t* cw_g;
+  const HAC_AS1 char* cw_g;       // the candidate table in global memory
+  uint32_t k8;                    // bytes per table row
+  uint32_t lane_off[S];           // byte offset of slot min(S u + s, k - 1) (staged: its LDS address)
+  int t_base[S];                  // 150, or 150 + 1024 for a slot at or past k (never open)
+  uint32_t vmask[S];              // all ones for a slot below k, else 0
+  uint32_t ra[S];                 // where this lane's slots of the current row are
   const double2* xy_lds;
   GDist D;
   const HAC_AS1 int32_t* geo;
@@ -1148,58 +1155,73 @@ struct AntRows {
   int left;             // unvisited nodes before this step's choice (same in every row of the wave)
   bool live;
   int cur;       // the row's current node (same in all its lanes)
-  uint32_t roff;  // cur * k: the first slot of cur's candidate row
   uint32_t fallbacks;
+
+  __device__ __forceinline__ uint64_t entry(uint32_t a) const {
+    if constexpr (STAGED)
+      return *reinterpret_cast<const __attribute__((address_space(3))) uint64_t*>((uintptr_t)a);
+    else
+      return *reinterpret_cast<const HAC_AS1 uint64_t*>(cw_g + a);
+  }
+  // the current node's row, from its byte offset in the table
+  __device__ __forceinline__ void set_row(uint32_t rb) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) ra[s] = rb + lane_off[s];
+  }
 
   // one decision for every row of the wave; U is the row's uniform
   __device__ __forceinline__ int step(uint32_t U) {
     uint64_t e[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const uint32_t x = roff + (uint32_t)min(S * u + s, k - 1);
-      e[s] = STAGED ? cw_lds[x] : cw_g[x];
-    }
+    for (int s = 0; s < S; ++s) e[s] = entry(ra[s]);
+    __builtin_amdgcn_sched_barrier(0);  // the table read goes first: it heads the step's chain
     // the geometric list of the current node, needed only if the row is
     // exhausted: loaded now so that its latency hides behind the step
     const uint32_t go = __umul24((uint32_t)cur, (uint32_t)kg);
     const int ga = geo[go + (uint32_t)min(2 * u, kg - 1)], gb = geo[go + (uint32_t)min(2 * u + 1, kg - 1)];
     int c[S];
-    uint32_t wb[S], vw[S], bit[S];
-    bool open[S];
-    // 150 - (biased exponent) of every open weight; the row minimum is the
-    // shift that brings the largest open weight to 24 integer bits
-    // (150 itself only when no slot is open: weights are normal numbers)
-    int tmin = 150;
+    uint32_t wb[S], mk[S], vw[S], bit[S];
+    // t = 150 - (biased exponent), plus 512 once the slot's node is visited
+    // and 1024 for a slot past k.  The row minimum is the shift that brings
+    // the largest open weight to 24 integer bits, and it is at least 256
+    // exactly when no slot is open (open slots give at most 149).
+    int tmin = 0x7fffffff;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       c[s] = (int)(uint32_t)e[s];
       wb[s] = (uint32_t)(e[s] >> 32);
       if constexpr (BYTES) {
-        open[s] = (S * u + s < k) & (vbytes(vis_g)[c[s]] == 0);
+        mk[s] = vbytes(vis_g)[c[s]];
       } else {
         vw[s] = vis_g[c[s] >> 5];
         bit[s] = 1u << (c[s] & 31);
-        open[s] = (S * u + s < k) & !(vw[s] & bit[s]);
+        mk[s] = (vw[s] >> (c[s] & 31)) & 1u;
       }
-      tmin = min(tmin, open[s] ? 150 - (int)(wb[s] >> 23) : 150);
+      const int t = (int)(mk[s] << 9) + (t_base[s] - (int)(wb[s] >> 23));
+      tmin = min(tmin, t);
     }
     const int sh = (int)row_reduce((uint32_t)tmin, OpMinI());
     // q = floor(w 2^(23-E)) with E the largest floor(log2 w) of the open
     // slots: scaling by a power of two is exact and the conversion truncates;
-    // open slots get at least 1, closed ones (weight taken as 0) exactly 0
+    // open slots get at least 1, closed ones (weight masked to 0) exactly 0
     uint32_t q[S], a[S], acc = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const float wm = open[s] ? __uint_as_float(wb[s]) : 0.0f;
-      q[s] = max(__float2uint_rz(__builtin_ldexpf(wm, sh)), (uint32_t)open[s]);
+      const uint32_t wm = wb[s] & (mk[s] - 1u) & vmask[s];
+      const uint32_t op = (mk[s] ^ 1u) & vmask[s] & 1u;
+      q[s] = max(__float2uint_rz(__builtin_ldexpf(__uint_as_float(wm), sh)), op);
       acc += q[s];
       a[s] = acc;
     }
+    // inclusive prefix and row total, side by side
     const uint32_t P = row_scan(acc);
-    const uint32_t tot = row_bcast<15>(P);
+    const uint32_t tot = row_reduce(acc, OpAdd());
     uint32_t ex[S];  // exclusive prefix of each slot, ready before r
 #pragma unroll
-    for (int s = 0; s < S; ++s) ex[s] = P - acc + a[s] - q[s];
+    for (int s = 0; s < S; ++s) {
+      ex[s] = P - acc + a[s] - q[s];
+      asm volatile("" : "+v"(ex[s]));  // kept as computed: one subtraction after r
+    }
     const uint32_t r = __umulhi(U, tot);
     uint32_t pick = 0, pick_off = 0, wv = 0;
     int wi = 0;
@@ -1209,7 +1231,7 @@ struct AntRows {
       // exclusive prefix <= r < inclusive prefix, i.e. r - exclusive < q
       const bool h = r - ex[s] < q[s];
       pick = h ? (uint32_t)c[s] : pick;
-      pick_off = h ? __umul24((uint32_t)c[s], (uint32_t)k) : pick_off;
+      pick_off = h ? __umul24((uint32_t)c[s], k8) : pick_off;
       if constexpr (!BYTES) {
         wi = h ? (c[s] >> 5) : wi;
         wv = h ? (vw[s] | bit[s]) : wv;
@@ -1217,7 +1239,19 @@ struct AntRows {
       hit |= h;
     }
     int j = (int)row_reduce(pick, OpOr());
-    roff = row_reduce(pick_off, OpOr());  // the next row's offset, alongside j
+    // the next row's byte offset, alongside j.  At most one lane of a row
+    // holds a nonzero offset, so after three levels one half of the row holds
+    // it and the other zero, and the last level may add instead of or: for one
+    // slot per lane it then adds the lane's own slot offset in the same step.
+    uint32_t ro = pick_off;
+    ro |= dpp_all<0xB1>(ro);
+    ro |= dpp_all<0x4E>(ro);
+    ro |= dpp_all<0x141>(ro);
+    if constexpr (S == 1) {
+      ra[0] = ro + dpp_all<0x140>(ro) + lane_off[0];
+    } else {
+      set_row(ro + dpp_all<0x140>(ro));
+    }
     // the lane of the chosen slot marks it (only this row writes its marks;
     // a bitset word is rewritten with the value it has just read)
     if (hit && live) {
@@ -1226,10 +1260,10 @@ struct AntRows {
       else
         vis_g[wi] = wv;
     }
-    const bool exhausted = sh == 150;
+    const bool exhausted = sh >= 256;
     if (__builtin_amdgcn_ballot_w64(exhausted)) {
       j = fallback(exhausted, j, ga, gb);
-      if (exhausted) roff = __umul24((uint32_t)j, (uint32_t)k);
+      if (exhausted) set_row(__umul24((uint32_t)j, k8));
     }
     --left;
     return j;
@@ -1317,14 +1351,12 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   const int list_off = rows * vis_words;
   const int staged_off = use_list ? list_off + rows * (int)L.list_words : list_off;
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  const uint64_t* cw_lds = nullptr;
   const double2* xy_lds = nullptr;
   if (STAGED) {
     u32x4* dst = reinterpret_cast<u32x4*>(lds + staged_off);
     const HAC_AS1 u32x4* src = reinterpret_cast<const HAC_AS1 u32x4*>(as_global(I.cw));
     const int vec = (n * k * 8 + 15) / 16;
     for (int x = threadIdx.x; x < vec; x += blockDim.x) dst[x] = src[x];
-    cw_lds = reinterpret_cast<const uint64_t*>(dst);
     if (I.xy) {
       u32x4* dxy = dst + vec;
       const HAC_AS1 u32x4* sxy = reinterpret_cast<const HAC_AS1 u32x4*>(as_global(I.xy));
@@ -1347,8 +1379,21 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   // idle rows shadow the wave's first ant step for step, reading its bitset
   // and writing nothing, so only live rows need LDS
   const int ant = A.live ? bm.ant0 + row : first_ant;
-  A.cw_lds = cw_lds;
-  A.cw_g = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.cw));
+  A.cw_g = reinterpret_cast<const HAC_AS1 char*>(as_global(I.cw));
+  A.k8 = 8u * (uint32_t)k;
+  // LDS address of the staged table
+  const uint32_t table_at =
+      (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t*)(lds + staged_off);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int slot = S * A.u + s;
+    A.lane_off[s] = 8u * (uint32_t)min(slot, k - 1) + (STAGED ? table_at : 0u);
+    A.t_base[s] = slot < k ? 150 : 150 + 1024;
+    A.vmask[s] = slot < k ? 0xffffffffu : 0u;
+    // opaque to the optimiser, so that the masking stays plain ALU work off
+    // the step's dependency chain instead of selects on it
+    asm volatile("" : "+v"(A.t_base[s]), "+v"(A.vmask[s]));
+  }
   A.xy_lds = xy_lds;
   A.D = GDist(I);
   A.grid = grid_view(I);
@@ -1379,7 +1424,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   const int start = (int)__umulhi(row_bcast<0>(rnd), (uint32_t)n);
   rnd = dpp_zero<0x101>(rnd);  // row_shl:1, step 1's draw to lane 0
   A.cur = start;
-  A.roff = __umul24((uint32_t)start, (uint32_t)k);
+  A.set_row(__umul24((uint32_t)start, A.k8));
   if (A.u == 0 && A.live) A.mark(start);
   A.fallbacks = 0;
   A.left = n - 1;
