@@ -341,7 +341,7 @@ def main():
     ap.add_argument("--iterations", type=int, default=None, help="override the workload's iteration count")
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=16)
-    ap.add_argument("--cpu-iterations", type=int, default=100)
+    ap.add_argument("--cpu-iterations", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--requests", type=int, default=240)
     ap.add_argument("--slots", type=int, default=64)
