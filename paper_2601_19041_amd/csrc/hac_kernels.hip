@@ -679,12 +679,10 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
       if (lane == 0) sh_mv[wave] = m;
     }
     __syncthreads();
-    int f = -1;
-    for (int w = 0; w < nb; ++w)
-      if (sh_mv[w].imp) {
-        f = w;
-        break;
-      }
+    // the first improving result in batch order: every lane reads one entry
+    // at once, instead of a chain of dependent reads
+    const uint64_t fm = __builtin_amdgcn_ballot_w64(lane < nb && sh_mv[min(lane, LS_WAVES - 1)].imp);
+    const int f = fm ? (int)__builtin_ctzll(fm) : -1;
     // queue entries consumed as a sequential scan would: all of them if no
     // move improves, else those up to and including the improving one
     const int used = f < 0 ? nq : max(0, f + 1 - re);
@@ -1760,10 +1758,27 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
   return hipGetLastError();
 }
 
+// largest static LDS of the 2-opt kernels (their __shared__ variables),
+// read from the compiled kernels once
+static size_t ls_static_lds() {
+  static size_t v = [] {
+    size_t m = 0;
+    const void* ks[] = {(const void*)two_opt_nn_kernel<2>, (const void*)two_opt_nn_kernel<1>,
+                        (const void*)local_search_kernel<2>, (const void*)local_search_kernel<1>};
+    for (const void* k : ks) {
+      hipFuncAttributes a{};
+      // on failure keep a generous reserve rather than overcommit LDS
+      m = std::max(m, hipFuncGetAttributes(&a, k) == hipSuccess ? (size_t)a.sharedSizeBytes : (size_t)8192);
+    }
+    return m;
+  }();
+  return v;
+}
+
 // the 2-opt mode of a launch: 2 when every instance of the batch has
 // coordinates and fits, else 1 when the int32 arrays fit, else 0
 static int ls_mode(int32_t max_n, int32_t all_coords) {
-  const size_t cap = (size_t)max_lds_bytes() - 1024;  // static shared variables
+  const size_t cap = (size_t)max_lds_bytes() - ls_static_lds();
   if (const char* f = std::getenv("HAC_LS_MODE")) {
     // pins a mode when it fits (used to show the modes give the same tours)
     const int m = std::atoi(f);
