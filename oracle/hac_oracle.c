@@ -539,6 +539,7 @@ static int valid_problem(const orc_problem* p) {
   if (p->n < 1 || p->ants < 1 || p->k < 1 || p->iterations < 0) return 0;
   if (!(p->rho > 0.0 && p->rho < 1.0) || !(p->p_best > 0.0 && p->p_best < 1.0)) return 0;
   if (p->alpha != 1.0) return 0;
+  if (p->local_search < 0 || p->local_search > 2) return 0;
   if (p->kind == ORC_MATRIX && !p->symmetric && p->local_search) return 0;
   if (p->row_ptr[0] != 0) return 0;
   for (int32_t i = 0; i < p->n; i++) {
@@ -648,6 +649,10 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
     for (int32_t a = 0; a < p->ants; a++) {
       int32_t* ta = tours + (int64_t)a * n;
       fallbacks += construct_ant(p, k_eff, cand, w, (uint32_t)t, (uint32_t)a, vis, ta);
+      /* Alg. 1 applies the local search to every constructed tour
+         (local_search = 2); the iteration best is then taken among the
+         improved tours */
+      if (p->local_search == 2) orc_two_opt(p, nl, k_ls, min_gain, ta);
       lens[a] = orc_tour_length(p, ta);
     }
     /* iteration best: the first ant with the smallest length */
@@ -656,7 +661,7 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
       if (lens[a] < lens[ib]) ib = a;
     memcpy(t_ib, tours + (int64_t)ib * n, 4 * (size_t)n);
     double l_ib = lens[ib];
-    if (p->local_search) {
+    if (p->local_search == 1) {
       orc_two_opt(p, nl, k_ls, min_gain, t_ib);
       l_ib = orc_tour_length(p, t_ib);
     }

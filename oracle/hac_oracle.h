@@ -27,7 +27,8 @@ typedef struct {
   const int32_t* row_ptr;
   const int32_t* col;
   const float* val;
-  /* MMAS / HeatACO parameters (Section IV-C) */
+  /* MMAS / HeatACO parameters (Section IV-C).  local_search: 0 none, 1 2-opt
+     on the iteration best, 2 2-opt on every ant's tour (Alg. 1) */
   int32_t ants, iterations, k, k_ls, local_search;
   double alpha, beta, rho, p_best, c_cap, theta_h, eps, xi_bf, lambda_bf, clip;
   int32_t degree_target, bf_period, restart_stall, ugb_max, baseline_scope;
@@ -47,7 +48,8 @@ typedef struct {
   float* heur;         /* [n*k_eff] folded eta^beta * e^kappa                */
   float* tau;          /* [n*k_eff] pheromone after the last iteration       */
   float* weight;       /* [n*k_eff] choice weights after the last iteration  */
-  int32_t* ant_tours;  /* [ants*n] tours of the last iteration, as built     */
+  int32_t* ant_tours;  /* [ants*n] tours of the last iteration (after the    */
+                       /* local search when local_search = 2)               */
   double* ant_len;     /* [ants] their lengths                               */
   int32_t* nn_tour;    /* [n] the (optionally 2-opted) NN tour               */
 } orc_trace;

@@ -43,8 +43,12 @@ def f32(x):
 
 
 class TextbookMMAS:
-    def __init__(self, inst, ugb_max=25, bf_period=100, restart_stall=250, xi=0.05, lam=1 + 1e-5):
+    """ls: 0 no local search, 1 2-opt on the iteration best, 2 on every ant."""
+
+    def __init__(self, inst, ugb_max=25, bf_period=100, restart_stall=250, xi=0.05, lam=1 + 1e-5, ls=0,
+                 k_ls=20):
         self.inst = inst
+        self.ls = ls
         self.n = n = inst.n
         self.xy = inst.coords
         self.k = min(inst.k, n - 1)
@@ -58,6 +62,73 @@ class TextbookMMAS:
         self.nn = [sorted((j for j in range(n) if j != i), key=lambda j: (self.key[i][j], j))[: self.k]
                    for i in range(n)]
         self.heur = [[f32((1.0 / self.d[i][j]) * (1.0 / self.d[i][j])) for j in self.nn[i]] for i in range(n)]
+        kl = min(k_ls, n - 1)
+        self.near = [sorted((j for j in range(n) if j != i), key=lambda j: (self.key[i][j], j))[:kl]
+                     for i in range(n)]
+
+    def two_opt(self, tour, min_gain):
+        """Neighbour-list 2-opt with a don't-look queue (Section III-D), as the
+        decoder reads it: the queue starts in tour order; for the popped node a,
+        its successor side is tried before its predecessor side; a side stops at
+        the first listed c no closer than the tour neighbour b; the first move
+        with gain above min_gain is applied, its four end nodes are queued if
+        absent and a is examined again.  A move reverses the tour positions of
+        the path between the two inner nodes, or of the rest of the cycle when
+        that path holds more than half the nodes."""
+        n, d = self.n, self.d
+        tour = list(tour)
+        if n < 5 or not self.near[0]:
+            return tour
+        pos = {v: q for q, v in enumerate(tour)}
+
+        def nxt(v):
+            return tour[(pos[v] + 1) % n]
+
+        def prv(v):
+            return tour[(pos[v] - 1) % n]
+
+        def flip(x, y):
+            lo, hi = pos[x], pos[y]
+            span = (hi - lo) % n + 1
+            if 2 * span > n:
+                lo, hi, span = (hi + 1) % n, (lo - 1) % n, n - span
+            idx = [(lo + q) % n for q in range(span)]
+            vals = [tour[q] for q in idx][::-1]
+            for q, v in zip(idx, vals):
+                tour[q] = v
+                pos[v] = q
+
+        from collections import deque
+        queue = deque(tour)
+        queued = set(tour)
+        while queue:
+            a = queue.popleft()
+            queued.discard(a)
+            moved = True
+            while moved:
+                moved = False
+                for side in (nxt, prv):
+                    b = side(a)
+                    for c in self.near[a]:
+                        if d[a][b] - d[a][c] <= 0.0:
+                            break
+                        e = side(c)
+                        if e == a or c == b:
+                            continue
+                        if (d[a][b] + d[c][e]) - (d[a][c] + d[b][e]) > min_gain:
+                            if side is nxt:
+                                flip(b, c)
+                            else:
+                                flip(c, b)
+                            for v in (a, b, c, e):
+                                if v not in queued:
+                                    queue.append(v)
+                                    queued.add(v)
+                            moved = True
+                            break
+                    if moved:
+                        break
+        return tour
 
     def length(self, t):
         s = 0.0
@@ -67,6 +138,8 @@ class TextbookMMAS:
 
     def bounds(self, L):
         tmax = 1.0 / (self.rho * L)
+        if self.ls:
+            return f32(tmax), f32(tmax / (2.0 * self.n))
         px = math.pow(0.05, 1.0 / self.n)
         tmin = tmax * (1.0 - px) / (((self.k - 1) / 2.0) * px)
         return f32(tmax), f32(tmin)
@@ -108,6 +181,9 @@ class TextbookMMAS:
             j = self.nearest_free(nn_t[-1], vis)
             nn_t.append(j)
             vis[j] = True
+        gain = 1e-9 * self.length(nn_t) / n
+        if self.ls:
+            nn_t = self.two_opt(nn_t, gain)
         gb, Lgb = nn_t, self.length(nn_t)
         tmax, tmin = self.bounds(Lgb)
         tau = [[tmax] * self.k for _ in range(n)]
@@ -116,9 +192,14 @@ class TextbookMMAS:
         self.elite_log = []
         for t in range(1, self.I + 1):
             tours = [self.ant(w, t, a) for a in range(self.m)]
+            if self.ls == 2:
+                tours = [self.two_opt(x, gain) for x in tours]
             lens = [self.length(x) for x in tours]
             ib = min(range(self.m), key=lambda a: (lens[a], a))
             Tib, Lib = tours[ib], lens[ib]
+            if self.ls == 1:
+                Tib = self.two_opt(Tib, gain)
+                Lib = self.length(Tib)
             if rb is None or Lib < Lrb:
                 rb, Lrb, stall = Tib, Lib, 0
             else:
@@ -190,3 +271,28 @@ def test_elite_schedule_and_restart_forced():
     assert list(tour) == want_t and L == want_L
     assert list(info["elite_rb"].astype(bool)) == ref.elite_log
     assert info["restarts"] > 0
+
+
+@pytest.mark.parametrize("ls,n,k,m,I,seed", [(1, 30, 6, 4, 15, 5), (2, 30, 6, 4, 15, 5), (2, 40, 8, 6, 10, 12),
+                                              (2, 24, 5, 3, 25, 2)])
+def test_local_search_equals_textbook_mmas(ls, n, k, m, I, seed):
+    # the same reduction with the neighbour-list 2-opt: on the iteration best
+    # (ls = 1) and on every ant's tour, the placement of Alg. 1 (ls = 2)
+    inst = wl.random_instance(n, seed=seed, heat="empty", k=k, ants=m, iterations=I, local_search=ls,
+                              k_ls=8)
+    ref = TextbookMMAS(inst, ls=ls, k_ls=8)
+    want_t, want_L = ref.run()
+    st, tour, L, info = oracle.decode(inst, state=True)
+    assert st == 0 and info["kappa"] == 0.0
+    assert list(tour) == want_t
+    assert L == want_L
+
+
+def test_local_search_every_ant_changes_the_search():
+    # ls = 2 must differ from ls = 1 somewhere on a run long enough for the
+    # improved non-best ants to matter; a planted no-op fails this
+    inst1 = wl.random_instance(40, seed=3, heat="empty", k=8, ants=6, iterations=12, local_search=1, k_ls=8)
+    inst2 = wl.random_instance(40, seed=3, heat="empty", k=8, ants=6, iterations=12, local_search=2, k_ls=8)
+    _, _, _, i1 = oracle.decode(inst1, state=True)
+    _, _, _, i2 = oracle.decode(inst2, state=True)
+    assert not np.array_equal(i1["ant_len"], i2["ant_len"])
