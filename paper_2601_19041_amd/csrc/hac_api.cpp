@@ -121,7 +121,7 @@ hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_para
     return fail(HAC_EINVAL, "parameter out of range");
   if (p->degree_target < 0 || p->bf_period < 0 || p->restart_stall < 0 || p->ugb_max < 1 ||
       (p->baseline_scope != 0 && p->baseline_scope != 1) ||
-      (p->local_search != 0 && p->local_search != 1) || (p->local_search && p->k_ls < 1))
+      p->local_search < 0 || p->local_search > 2 || (p->local_search && p->k_ls < 1))
     return fail(HAC_EINVAL, "integer parameter out of range");
   if (p->alpha != 1.0) return fail(HAC_EUNSUPPORTED, "only alpha = 1 is supported");
   if (p->k > HAC_MAX_K) return fail(HAC_EUNSUPPORTED, "k above HAC_MAX_K");
@@ -144,6 +144,7 @@ Layout make_layout(const hac_instance* inst, const hac_csr* csr, const hac_param
   L.iterations = p->iterations;
   L.coords = inst->kind == HAC_COORDS_EUC2D;
   L.ls = p->local_search != 0;
+  L.ls_tours = p->local_search == 2 ? p->ants : 1;
   L.nnz = csr->nnz;
   L.gside = (L.coords && L.n >= kGridMinN) ? grid_side(L.n) : 0;
   return L;
@@ -158,7 +159,7 @@ size_t Layout::bytes() const {
   b += align256(4 * nn * (size_t)kg);
   b += align256(4 * nn * (size_t)ants) + align256(8 * (size_t)ants);
   b += 6 * align256(4 * nn);
-  b += ls ? align256(12 * nn) : 0;
+  b += ls ? align256(12 * nn * (size_t)ls_tours) : 0;
   if (gside > 0) {
     const size_t cells = (size_t)gside * gside;
     b += align256(4 * (cells + 1)) + align256(4 * cells) + align256(4 * nn) + align256(16 * nn) +
@@ -192,7 +193,7 @@ void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve) {
   d.nn_tour = (int32_t*)carve(4 * nn);
   d.succ = (int32_t*)carve(4 * nn);
   d.pred = (int32_t*)carve(4 * nn);
-  d.ls_work = L.ls ? (int32_t*)carve(12 * nn) : nullptr;
+  d.ls_work = L.ls ? (int32_t*)carve(12 * nn * (size_t)L.ls_tours) : nullptr;
   d.gside = L.gside;
   if (L.gside > 0) {
     const size_t cells = (size_t)L.gside * L.gside;
@@ -877,9 +878,10 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   LaunchShape used{0, 0, 0, 0, 0};
   if (m > 0) {
     bool any_ls = false;
-    int32_t max_iter = 0, max_n = 0, all_coords = 1;
+    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1;
     for (auto& h : hs) {
       any_ls |= h.p.local_search != 0;
+      if (h.p.local_search == 2) ls_tours = std::max(ls_tours, h.p.ants);
       max_iter = std::max(max_iter, h.p.iterations);
       max_n = std::max(max_n, h.lay.n);
       if (!h.lay.coords) all_coords = 0;
@@ -904,7 +906,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
                                       shape.bytes, shape.kmax, lds, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
-        e = launch_local_search(d_descs, m, max_n, all_coords, s);
+        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, s);
         if (e != hipSuccess) return e;
       }
       return launch_iter_end(d_descs, m, s);
@@ -921,7 +923,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
                                       shape.bytes, shape.kmax, lds, s));
         CTX_HIP(hipEventRecord(c->events[2 * it + 1], s));
-        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, s));
+        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
       }
       CTX_HIP(hipStreamSynchronize(s));

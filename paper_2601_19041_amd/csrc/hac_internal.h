@@ -68,7 +68,8 @@ struct InstDesc {
   int32_t* nn_tour;           // [n]
   int32_t* succ;              // [n]
   int32_t* pred;              // [n]
-  int32_t* ls_work;           // [3n] pos, queue, in-queue for 2-opt
+  int32_t* ls_work;           // [3n] pos, queue, in-queue for 2-opt ([ants][3n] when
+                              // every ant's tour is searched)
   int32_t gside;              // grid cells per side (0: no grid)
   int32_t* g_start;           // [side^2 + 1] first slot of each cell
   int32_t* g_cur;             // [side^2] build cursors
@@ -100,8 +101,10 @@ hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
                             int32_t bytes, int32_t max_k, size_t lds_bytes, hipStream_t s);
+// tours_per_inst: blocks per instance (the largest ant count among instances
+// that search every ant's tour, else 1)
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
-                               int32_t all_coords, hipStream_t s);
+                               int32_t all_coords, int32_t tours_per_inst, hipStream_t s);
 hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const* d_out_tours,
                          double* d_out_lens, hipStream_t s);

@@ -744,7 +744,8 @@ static __host__ __device__ inline size_t ls_lds_need(int n, int mode) {
 }
 
 template <int MODE>
-__device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain) {
+__device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain,
+                                             int32_t* work) {
   extern __shared__ int32_t ls_lds[];
   const int n = D.n;
   LsFast F{nullptr, 0.0, 0.0};
@@ -785,7 +786,7 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
   } else {
     HAC_AS1 int32_t* tour = as_global(tour_g);
-    HAC_AS1 int32_t* pos = as_global(D.ls_work);
+    HAC_AS1 int32_t* pos = as_global(work);
     HAC_AS1 int32_t* queue = pos + n;
     HAC_AS1 uint8_t* inq = reinterpret_cast<HAC_AS1 uint8_t*>(queue + n);
     two_opt_block(D, tour, pos, queue, inq, min_gain, F);
@@ -800,7 +801,7 @@ template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) two_opt_nn_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search) return;
-  two_opt_tour<MODE>(D, D.nn_tour, D.st->min_gain);
+  two_opt_tour<MODE>(D, D.nn_tour, D.st->min_gain, D.ls_work);
   if (threadIdx.x < WAVE) {
     const double len = tour_length_wave(D, D.nn_tour);
     if (threadIdx.x == 0) {
@@ -1491,12 +1492,30 @@ __device__ void iteration_best_wave(const InstDesc& D, int& ib, double& lib) {
   lib = bk;
 }
 
+// Local search of one iteration.  local_search = 1: block (i, 0) improves
+// a copy of instance i's iteration-best tour.  local_search = 2 (Alg. 1's
+// placement): block (i, y) improves ant tours y, y + gridDim.y, ... in place
+// and replaces their lengths, so the iteration best is then taken among the
+// improved tours.
 template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || D.st->t > D.iterations) return;
-  __shared__ int sh_ib;
   const int n = D.n;
+  if (D.local_search == 2) {
+    for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
+      int32_t* tour = D.tours + (int64_t)a * n;
+      two_opt_tour<MODE>(D, tour, D.st->min_gain, D.ls_work + (int64_t)a * 3 * n);
+      if (threadIdx.x < WAVE) {
+        const double len = tour_length_wave(D, tour);
+        if (threadIdx.x == 0) D.lens[a] = len;
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  if (blockIdx.y != 0) return;
+  __shared__ int sh_ib;
   if (threadIdx.x < WAVE) {
     int ib;
     double lib;
@@ -1509,7 +1528,7 @@ __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const Ins
   for (int s = threadIdx.x; s < n; s += blockDim.x) D.t_ib[s] = src[s];
   __threadfence_block();
   __syncthreads();
-  two_opt_tour<MODE>(D, D.t_ib, D.st->min_gain);
+  two_opt_tour<MODE>(D, D.t_ib, D.st->min_gain, D.ls_work);
   if (threadIdx.x < WAVE) {
     const double len = tour_length_wave(D, D.t_ib);
     if (threadIdx.x == 0) {
@@ -1547,7 +1566,7 @@ __global__ void __launch_bounds__(1024) iter_end_kernel(const InstDesc* insts) {
 
   // iteration best (first ant with the smallest length)
   const int32_t* t_ib;
-  if (D.local_search) {
+  if (D.local_search == 1) {
     if (tid == 0) {
       s_ib = st->ib;
       s_lib = st->l_ib;
@@ -1938,9 +1957,9 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
 }
 
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
-                               int32_t all_coords, hipStream_t s) {
+                               int32_t all_coords, int32_t tours_per_inst, hipStream_t s) {
   const int mode = ls_mode(max_n, all_coords);
-  const dim3 grid(count), block(LS_WAVES * WAVE);
+  const dim3 grid(count, std::max(tours_per_inst, 1)), block(LS_WAVES * WAVE);
   if (mode == 2)
     hipLaunchKernelGGL(local_search_kernel<2>, grid, block, ls_lds_need(max_n, 2), s, d_insts);
   else if (mode == 1)

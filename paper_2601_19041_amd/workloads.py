@@ -38,6 +38,7 @@ WL_TSP500 = 2
 WL_BATCH64 = 3
 WL_TSP10K = 4
 WL_SERVE = 5
+WL_PAPER = 6
 
 
 def _rng(workload: int, instance: int, stream: int = 0) -> np.random.Generator:
@@ -316,6 +317,24 @@ def tsp10k(count: int = 8, iterations: int = 200, n: int = 10000) -> List[Instan
         heat = softdist_heatmap(xy, 20)
         out.append(Instance(n, "coords", True, xy, None, heat, ants=100, iterations=iterations,
                             k=20, local_search=1, k_ls=20, seed=1 + x, name=f"tsp10k#{x}"))
+    return out
+
+
+def paper_budget(n: int, count: int = 1, local_search: int = 0, iterations: int = 5000,
+                 first: int = 0) -> List[Instance]:
+    """The paper's own decode setting (Section IV-C) on synthetic uniform
+    instances standing in for its TSP500/1K/10K test sets: 32 ants, 5000
+    iterations, k = 20, rho = 0.8 for the symmetric TSP, and with local
+    search the 2-opt on every ant's tour (local_search = 2, 20 neighbours).
+    The heatmap is the top-20 generator without noise."""
+    out = []
+    for x in range(first, first + count):
+        rng = _rng(WL_PAPER, n * 1000 + x)
+        xy = uniform_coords(n, rng)
+        heat = softdist_heatmap(xy, 20)
+        out.append(Instance(n, "coords", True, xy, None, heat, ants=32, iterations=iterations, k=20,
+                            local_search=local_search, k_ls=20, rho=0.8, seed=1 + x,
+                            name=f"paper{n}#{x}"))
     return out
 
 

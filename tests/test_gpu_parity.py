@@ -71,13 +71,22 @@ def test_tsp100_seeds(ctx, seed):
 
 
 @pytest.mark.parametrize("name", ["atsp", "symmatrix", "ls", "symmatrix_ls", "ls_grid", "ls_offset", "empty",
-                                  "grid_ties", "k_full", "scope1", "ugb_restart"])
+                                  "grid_ties", "k_full", "scope1", "ugb_restart", "ls_every",
+                                  "symmatrix_ls_every", "ls_every_grid"])
 def test_small_variants(ctx, name):
     over = {}
     if name == "symmatrix_ls":
         # 2-opt on a distance matrix: int32 working arrays, no FP32 filter
         inst = wl.random_instance(120, seed=13, kind="matrix", symmetric=True, k=8, ants=10, iterations=20,
                                   local_search=1, k_ls=10)
+    elif name == "ls_every":
+        # 2-opt on every ant's tour (Alg. 1): the ant tours compared below are the improved ones
+        inst = wl.random_instance(150, seed=7, k=10, ants=12, iterations=25, local_search=2, k_ls=12)
+    elif name == "symmatrix_ls_every":
+        inst = wl.random_instance(110, seed=17, kind="matrix", symmetric=True, k=8, ants=9, iterations=15,
+                                  local_search=2, k_ls=10)
+    elif name == "ls_every_grid":
+        inst = wl.random_instance(130, seed=18, grid=12, k=10, ants=7, iterations=15, local_search=2, k_ls=12)
     elif name == "ls_grid":
         # lattice points: many equal distances, so the FP32 2-opt tests fall
         # inside their error bound and are decided in FP64
@@ -212,12 +221,31 @@ def test_grid_search(ctx, name):
     assert ctx.stats()["fallback_steps"] == info["fallback_steps"]
 
 
+@pytest.mark.parametrize("ls", [1, 2])
 @pytest.mark.parametrize("mode", ["0", "1", "2"])
-def test_two_opt_modes(ctx, mode, monkeypatch):
+def test_two_opt_modes(ctx, mode, ls, monkeypatch):
     """The 2-opt working-array modes (global memory; int32 arrays in LDS;
     uint16 arrays with FP32 coordinates in LDS and FP64 rechecks inside the
-    error bound) give the same tours."""
-    inst = wl.random_instance(600, seed=21, k=10, ants=8, iterations=6, local_search=1, k_ls=16)
+    error bound) give the same tours, on the iteration best and on every ant."""
+    inst = wl.random_instance(600, seed=21, k=10, ants=8, iterations=6, local_search=ls, k_ls=16)
     monkeypatch.setenv("HAC_LS_MODE", mode)
-    print(f"case 2-opt mode {mode}", flush=True)
+    print(f"case 2-opt mode {mode} local_search {ls}", flush=True)
     _same(ctx.decode(inst), oracle.decode(inst), f"ls mode {mode}")
+    if ls == 2:
+        _state_parity(ctx, inst)
+
+
+def test_batch_mixed_local_search(ctx):
+    """One batch holding instances without local search, with 2-opt on the
+    iteration best and with 2-opt on every ant (different ant counts): each
+    result equals the oracle's and the instance decoded alone."""
+    insts = [wl.random_instance(80, seed=41, k=8, ants=6, iterations=12),
+             wl.random_instance(100, seed=42, k=8, ants=8, iterations=10, local_search=1, k_ls=10),
+             wl.random_instance(120, seed=43, k=10, ants=10, iterations=12, local_search=2, k_ls=10),
+             wl.random_instance(90, seed=44, k=6, ants=4, iterations=14, local_search=2, k_ls=8)]
+    print("case batch mixed local search", flush=True)
+    got = ctx.decode_batch(insts)
+    for x, inst in enumerate(insts):
+        _same(got[x], oracle.decode(inst), f"mixed{x}")
+        alone = ctx.decode(inst)
+        assert np.array_equal(alone[0], got[x][0]) and alone[1] == got[x][1]

@@ -125,3 +125,20 @@ def test_two_opt_in_global_memory(ctx):
     inst.ants = 6
     print("case 2-opt global n=13000", flush=True)
     _check(ctx.decode(inst), inst)
+
+
+def test_paper_budget_tsp500_every_ant_two_opt(ctx):
+    """The paper's setting (32 ants, k = 20, rho = 0.8) with 2-opt on every
+    ant's tour, at n = 500, for its first 12 iterations: final tour, the
+    last iteration's improved ant tours, pheromone and per-iteration trace
+    equal the oracle's."""
+    inst = wl.paper_budget(500, local_search=2, iterations=12)[0]
+    print(f"case {inst.name} ls=2 12 iterations", flush=True)
+    got = ctx.decode(inst)
+    st, tour, L, info = oracle.decode(inst, trace=True, state=True)
+    assert st == 0 and np.array_equal(got[0], tour) and abs(got[1] - L) <= 1e-12 * L
+    g = ctx.debug_state(0, inst.n, inst.k, inst.ants)
+    for name in ("tau", "weight", "ant_tours", "ant_len"):
+        assert np.array_equal(g[name], info[name]), name
+    tr = ctx.debug_trace(0, inst.iterations)
+    assert np.array_equal(tr["l_ib"], info["l_ib"]) and np.array_equal(tr["l_gb"], info["l_gb"])
