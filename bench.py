@@ -332,12 +332,71 @@ def run_serve(args, hac, wl, cpu):
     return out
 
 
+# The paper's own per-instance decode times on 8 CPU cores (heatmap inference
+# excluded), 32 ants x 5000 iterations, k = 20: Table I (learned heatmaps,
+# the range over the four predictors) and Table VII (SoftDist heatmap).
+PAPER_TIMES_S = {
+    (500, 0): {"table_I": [1.71, 2.01], "table_VII_softdist": 1.64},
+    (1000, 0): {"table_I": [4.18, 4.58], "table_VII_softdist": 3.98},
+    (10000, 0): {"table_I": [151.2, 222.0], "table_VII_softdist": 354.0},
+    (500, 2): {"table_I": [3.99, 4.21], "table_VII_softdist": 1.95},
+    (1000, 2): {"table_I": [8.37, 8.49], "table_VII_softdist": 4.30},
+    (10000, 2): {"table_I": [112.2, 142.2], "table_VII_softdist": 60.92},
+}
+
+
+def run_paper(args, hac, wl):
+    """The paper's decode setting (32 ants, 5000 iterations, k = 20,
+    rho = 0.8; with --ls 2 the 2-opt on every ant's tour) on synthetic
+    uniform instances of the paper's test-set sizes: a batched decode of the
+    whole set and plain decodes of a sample, with tours asserted identical."""
+    n, ls = args.paper_n, args.ls
+    count = args.instances or (16 if n >= 10000 else 128)
+    insts = wl.paper_budget(n, count, local_search=ls, iterations=args.iterations or 5000)
+    ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
+    ctx = hac.Context(0)
+    db = hac.DeviceBatch(insts)
+    wall, times, cms, launches = timed_batches(ctx, db, args.steps, args.warmup)
+    batched = db.results()
+    st = ctx.stats()
+    lat, psteps, equal = plain_sample(ctx, insts, max(1, min(args.plain_sample, count)), batched)
+    assert equal, "plain and batched tours differ"
+    mean_len = float(np.mean([batched[x][1] for x in range(count)]))
+    desc = (f"paper{n}: {count} uniform TSP instances, n={n}, top-20 heatmaps, 32 ants, "
+            f"{insts[0].iterations} iterations, k=20, rho=0.8, "
+            + ("2-opt (20 neighbours) on every ant's tour" if ls == 2 else "no local search"))
+    out = base_line(args, f"ant-steps/s, batched decode at the paper's budget (n={n}, ls={ls})",
+                    ant_steps * args.steps / wall, 1000.0 * wall / args.steps,
+                    {"workload": desc, "instances": count, "iterations": insts[0].iterations, "ants": 32,
+                     "k": 20, "inputs": "resident in HBM (hac_decode_batch_dev)",
+                     "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
+                                      "ants_per_wave": st["ants_per_wave"], "byte_marks": st["byte_marks"]}})
+    ctx_paper = PAPER_TIMES_S.get((n, ls))
+    out.update({
+        "decodes_per_s": count * args.steps / wall,
+        "per_instance_s": {"plain_p50": percentile(lat, 0.5), "batched_equivalent": wall / args.steps / count},
+        "plain": {"decodes_per_s": len(lat) / sum(lat), "sample": len(lat)},
+        "batched_vs_plain": (count * args.steps / wall) / (len(lat) / sum(lat)),
+        "equal_gap": equal,
+        "mean_length": mean_len,
+        "roofline": roofline(insts, cms, launches),
+        "paper_context": None if ctx_paper is None else dict(
+            ctx_paper, hardware="8 CPU cores (model unstated)", note="different instances and heatmaps; "
+            "context only"),
+    })
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve"])
+    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve", "paper"])
+    ap.add_argument("--paper-n", type=int, default=500, help="paper workload: instance size (500, 1000, 10000)")
+    ap.add_argument("--ls", type=int, default=0, choices=[0, 2], help="paper workload: 2 = 2-opt on every ant")
+    ap.add_argument("--instances", type=int, default=None, help="paper workload: instances in the batch")
     ap.add_argument("--iterations", type=int, default=None, help="override the workload's iteration count")
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=16)
@@ -368,6 +427,10 @@ def main():
     from paper_2601_19041_amd import workloads as wl
 
     it = args.iterations
+    if args.workload == "paper":
+        import paper_2601_19041_amd as hac
+        print(json.dumps(run_paper(args, hac, wl)))
+        return
     if args.workload == "batch64":
         insts = wl.batch64(64, iterations=it or 500)
     elif args.workload == "tsp100":

@@ -115,12 +115,17 @@ int32_t construct_group_lanes(int32_t max_k);
 // bitsets of the rows that carry ants (rows_per_wave of each wave's four;
 // the other rows follow row 0 of their wave and read its bitset),
 // optionally each such row's list of unvisited nodes (uint16), and for
-// STAGED launches the {candidate, weight} table and the coordinates.
+// staged launches the candidate table (8-byte {id, weight} entries, or ids
+// as uint16 and weights as FP32, six bytes per slot) and the coordinates.
 struct ConstructLds {
   size_t rows, vis_words, list_words, total;  // total in bytes
 };
+__host__ __device__ inline size_t staged_ids_bytes(int32_t n, int32_t k) {
+  return (((size_t)n * k * 2 + 15) / 16) * 16;
+}
+// staged: 0 none, 1 8-byte {id, weight} entries, 2 uint16 ids + FP32 weights
 __host__ __device__ inline ConstructLds construct_lds_layout(int32_t n, int32_t k, int32_t ants_per_block,
-                                                             int32_t rows_per_wave, bool staged, bool lists,
+                                                             int32_t rows_per_wave, int32_t staged, bool lists,
                                                              bool bytes) {
   ConstructLds L;
   L.rows = (size_t)rows_per_wave * (size_t)((ants_per_block + rows_per_wave - 1) / rows_per_wave);
@@ -129,7 +134,9 @@ __host__ __device__ inline ConstructLds construct_lds_layout(int32_t n, int32_t 
   L.list_words = (size_t)(((n + 7) >> 3) << 2);  // n uint16 rounded up to 16 bytes
   size_t total = L.rows * L.vis_words * 4;
   if (lists) total += L.rows * L.list_words * 4;
-  if (staged) total += (((size_t)n * k * 8 + 15) / 16) * 16 + (size_t)16 * n;
+  // staged table (8-byte entries, or uint16 ids then FP32 weights), then the coordinates
+  if (staged == 1) total += (((size_t)n * k * 8 + 15) / 16) * 16 + (size_t)16 * n;
+  if (staged == 2) total += staged_ids_bytes(n, k) + (((size_t)n * k * 4 + 15) / 16) * 16 + (size_t)16 * n;
   L.total = total;
   return L;
 }

@@ -1117,12 +1117,17 @@ __device__ __forceinline__ uint32_t row_scan(uint32_t v) {
 // far away in cells, while the compacted list is short.
 constexpr int kListScanMax = 1024;
 
-template <bool STAGED, int S, bool BYTES>
+// STAGED: 0 the candidate table is read from global memory; 1 it is copied
+// to LDS as 8-byte {id, weight} entries; 2 as uint16 ids and FP32 weights
+// (six bytes per slot, for tables that do not fit as 8-byte entries).
+template <int STAGED, int S, bool BYTES>
 struct AntRows {
   int n, k, kg, u, g;
   const HAC_AS1 char* cw_g;       // the candidate table in global memory
-  uint32_t k8;                    // bytes per table row
-  uint32_t lane_off[S];           // byte offset of slot min(S u + s, k - 1) (staged: its LDS address)
+  uint32_t k8;                    // bytes per table row (STAGED 2: of the id table)
+  uint32_t w_from_id;             // STAGED 2: weight address = 2 x id address + w_from_id
+  uint32_t lane_off[S];           // byte offset of slot min(S u + s, k - 1) (staged: its LDS address;
+                                  // STAGED 2: its id's)
   int t_base[S];                  // 150, or 150 + 1024 for a slot at or past k (never open)
   uint32_t vmask[S];              // all ones for a slot below k, else 0
   uint32_t ra[S];                 // where this lane's slots of the current row are
@@ -1157,10 +1162,17 @@ struct AntRows {
   uint32_t fallbacks;
 
   __device__ __forceinline__ uint64_t entry(uint32_t a) const {
-    if constexpr (STAGED)
+    if constexpr (STAGED == 1) {
       return *reinterpret_cast<const __attribute__((address_space(3))) uint64_t*>((uintptr_t)a);
-    else
+    } else if constexpr (STAGED == 2) {
+      // the id (uint16) at a and its weight (FP32) at 2a + w_from_id
+      const uint32_t id = *reinterpret_cast<const __attribute__((address_space(3))) uint16_t*>((uintptr_t)a);
+      const uint32_t wb = *reinterpret_cast<const __attribute__((address_space(3))) uint32_t*>(
+          (uintptr_t)(2u * a + w_from_id));
+      return (uint64_t)id | ((uint64_t)wb << 32);
+    } else {
       return *reinterpret_cast<const HAC_AS1 uint64_t*>(cw_g + a);
+    }
   }
   // the current node's row, from its byte offset in the table
   __device__ __forceinline__ void set_row(uint32_t rb) {
@@ -1330,7 +1342,7 @@ __device__ __forceinline__ void sum_row_in_order(double& len, double d) {
   }
 }
 
-template <bool STAGED, int S, bool BYTES>
+template <int STAGED, int S, bool BYTES>
 __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
                                                          int ants_per_block, int rows_per_wave,
@@ -1351,13 +1363,30 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   const int staged_off = use_list ? list_off + rows * (int)L.list_words : list_off;
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const double2* xy_lds = nullptr;
+  // words of the staged table before the coordinates, and of its id part
+  const uint32_t ids_words = STAGED == 2 ? (uint32_t)(staged_ids_bytes(n, k) / 4) : 0u;
+  const uint32_t table_words = STAGED == 2 ? ids_words + (uint32_t)((((size_t)n * k * 4 + 15) / 16) * 4)
+                                           : (uint32_t)((((size_t)n * k * 8 + 15) / 16) * 4);
   if (STAGED) {
-    u32x4* dst = reinterpret_cast<u32x4*>(lds + staged_off);
-    const HAC_AS1 u32x4* src = reinterpret_cast<const HAC_AS1 u32x4*>(as_global(I.cw));
-    const int vec = (n * k * 8 + 15) / 16;
-    for (int x = threadIdx.x; x < vec; x += blockDim.x) dst[x] = src[x];
+    const HAC_AS1 uint64_t* src = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.cw));
+    if constexpr (STAGED == 2) {
+      // the {id, weight} table, split into uint16 ids and FP32 weights
+      uint16_t* dst_id = reinterpret_cast<uint16_t*>(lds + staged_off);
+      uint32_t* dst_w = lds + staged_off + ids_words;
+      const int nk = n * k;
+      for (int x = threadIdx.x; x < nk; x += blockDim.x) {
+        const uint64_t e = src[x];
+        dst_id[x] = (uint16_t)(uint32_t)e;
+        dst_w[x] = (uint32_t)(e >> 32);
+      }
+    } else {
+      u32x4* dst = reinterpret_cast<u32x4*>(lds + staged_off);
+      const HAC_AS1 u32x4* src4 = reinterpret_cast<const HAC_AS1 u32x4*>(src);
+      const int vec = (n * k * 8 + 15) / 16;
+      for (int x = threadIdx.x; x < vec; x += blockDim.x) dst[x] = src4[x];
+    }
     if (I.xy) {
-      u32x4* dxy = dst + vec;
+      u32x4* dxy = reinterpret_cast<u32x4*>(lds + staged_off + table_words);
       const HAC_AS1 u32x4* sxy = reinterpret_cast<const HAC_AS1 u32x4*>(as_global(I.xy));
       for (int x = threadIdx.x; x < n; x += blockDim.x) dxy[x] = sxy[x];
       xy_lds = reinterpret_cast<const double2*>(dxy);
@@ -1379,14 +1408,17 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   // and writing nothing, so only live rows need LDS
   const int ant = A.live ? bm.ant0 + row : first_ant;
   A.cw_g = reinterpret_cast<const HAC_AS1 char*>(as_global(I.cw));
-  A.k8 = 8u * (uint32_t)k;
-  // LDS address of the staged table
+  A.k8 = (STAGED == 2 ? 2u : 8u) * (uint32_t)k;
+  // LDS addresses of the staged ids and weights
   const uint32_t table_at =
       (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t*)(lds + staged_off);
+  const uint32_t weights_at = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t*)(
+      lds + staged_off + ids_words);
+  A.w_from_id = weights_at - 2u * table_at;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int slot = S * A.u + s;
-    A.lane_off[s] = 8u * (uint32_t)min(slot, k - 1) + (STAGED ? table_at : 0u);
+    A.lane_off[s] = (STAGED == 2 ? 2u : 8u) * (uint32_t)min(slot, k - 1) + (STAGED ? table_at : 0u);
     A.t_base[s] = slot < k ? 150 : 150 + 1024;
     A.vmask[s] = slot < k ? 0xffffffffu : 0u;
     // opaque to the optimiser, so that the masking stays plain ALU work off
@@ -1751,17 +1783,17 @@ bool construct_bytes_fit(int32_t n, int32_t k, int32_t ants_per_block, int32_t r
                          int32_t staged) {
   // byte marks are used only together with the unvisited lists
   return n <= 65535 &&
-         construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, true, true).total <=
+         construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged, true, true).total <=
              (size_t)max_lds_bytes();
 }
 
 size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t rows_per_wave,
                            int32_t staged, int32_t bytes) {
-  if (bytes) return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, true, true).total;
+  if (bytes) return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged, true, true).total;
   // bit marks: the unvisited lists are included whenever they fit
-  const ConstructLds with = construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, true, false);
+  const ConstructLds with = construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged, true, false);
   if (n <= 65535 && with.total <= (size_t)max_lds_bytes()) return with.total;
-  return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged != 0, false, false).total;
+  return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged, false, false).total;
 }
 
 hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s) {
@@ -1946,10 +1978,13 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
     else if (S == 2) HAC_LAUNCH(ST, 2, BY); \
     else HAC_LAUNCH(ST, 4, BY);          \
   }
-  if (staged) {
-    if (bytes) HAC_LAUNCH_S(true, true) else HAC_LAUNCH_S(true, false)
+  if (staged < 0 || staged > 2) return hipErrorInvalidValue;
+  if (staged == 2) {
+    if (bytes) HAC_LAUNCH_S(2, true) else HAC_LAUNCH_S(2, false)
+  } else if (staged == 1) {
+    if (bytes) HAC_LAUNCH_S(1, true) else HAC_LAUNCH_S(1, false)
   } else {
-    if (bytes) HAC_LAUNCH_S(false, true) else HAC_LAUNCH_S(false, false)
+    if (bytes) HAC_LAUNCH_S(0, true) else HAC_LAUNCH_S(0, false)
   }
 #undef HAC_LAUNCH_S
 #undef HAC_LAUNCH

@@ -142,3 +142,20 @@ def test_paper_budget_tsp500_every_ant_two_opt(ctx):
         assert np.array_equal(g[name], info[name]), name
     tr = ctx.debug_trace(0, inst.iterations)
     assert np.array_equal(tr["l_ib"], info["l_ib"]) and np.array_equal(tr["l_gb"], info["l_gb"])
+
+
+def test_paper1000_packed_staging(ctx, monkeypatch):
+    """n = 1000, k = 20: the candidate table fits in LDS only as uint16 ids
+    and FP32 weights.  A 16-instance batch at that launch shape, and at the
+    shape the tuner picks, equals the oracle on sampled instances."""
+    insts = wl.paper_budget(1000, count=16, iterations=10)
+    print("case paper1000 tuned", flush=True)
+    tuned = ctx.decode_batch(insts)
+    monkeypatch.setenv("HAC_SHAPE", "16,2,4")
+    print("case paper1000 16,2,4", flush=True)
+    forced = ctx.decode_batch(insts)
+    assert ctx.stats()["lds_staged"] == 2
+    for x in (0, 9, 15):
+        _check(forced[x], insts[x])
+    for x in range(len(insts)):
+        assert np.array_equal(tuned[x][0], forced[x][0]) and tuned[x][1] == forced[x][1]
