@@ -47,6 +47,7 @@ class Problem(ctypes.Structure):
         ("restart_stall", ctypes.c_int32), ("ugb_max", ctypes.c_int32),
         ("baseline_scope", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("kappa_fixed", ctypes.c_double),
     ]
 
 
@@ -103,7 +104,7 @@ def _ptr(a: Optional[np.ndarray]):
 
 DEFAULTS = dict(alpha=1.0, beta=2.0, rho=0.2, p_best=0.05, c_cap=0.5, theta_h=1e-4, eps=1e-9,
                 xi_bf=0.05, lambda_bf=1.0 + 1e-5, clip=40.0, degree_target=0, bf_period=100,
-                restart_stall=250, ugb_max=25, baseline_scope=0)
+                restart_stall=250, ugb_max=25, baseline_scope=0, kappa_fixed=-1.0)
 
 
 class OracleProblem:

@@ -311,7 +311,11 @@ double orc_evidence(const orc_problem* p, const int32_t* cand, int32_t k_eff, do
   }
   /* eq. (13)-(14) */
   double r = r_hat(p, k_eff);
-  double kappa = (q90 > 0.0 && r > 1.0) ? p->c_cap * p->alpha * log(r) / q90 : 0.0;
+  double kappa;
+  if (p->kappa_fixed >= 0.0)
+    kappa = p->kappa_fixed; /* the ablation replaces eq. (14) by a constant */
+  else
+    kappa = (q90 > 0.0 && r > 1.0) ? p->c_cap * p->alpha * log(r) / q90 : 0.0;
   /* fold */
   if (heur) {
     for (int32_t i = 0; i < n; i++)
@@ -540,6 +544,7 @@ static int valid_problem(const orc_problem* p) {
   if (!(p->rho > 0.0 && p->rho < 1.0) || !(p->p_best > 0.0 && p->p_best < 1.0)) return 0;
   if (p->alpha != 1.0) return 0;
   if (p->local_search < 0 || p->local_search > 2) return 0;
+  if (!isfinite(p->kappa_fixed)) return 0;
   if (p->kind == ORC_MATRIX && !p->symmetric && p->local_search) return 0;
   if (p->row_ptr[0] != 0) return 0;
   for (int32_t i = 0; i < p->n; i++) {

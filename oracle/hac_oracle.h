@@ -33,6 +33,9 @@ typedef struct {
   double alpha, beta, rho, p_best, c_cap, theta_h, eps, xi_bf, lambda_bf, clip;
   int32_t degree_target, bf_period, restart_stall, ugb_max, baseline_scope;
   uint64_t seed;
+  /* kappa_fixed < 0: kappa from eq. (14); >= 0: kappa set to this value
+     (Sec. IV-E ablation "fixed kappa = 1") */
+  double kappa_fixed;
 } orc_problem;
 
 /* optional outputs; any pointer may be NULL */

@@ -246,6 +246,33 @@ def test_fold_matches_power_law():
     assert mult.max() <= math.exp(0.5) * (1 + 1e-6)
 
 
+def test_fixed_kappa_ablation():
+    # Section IV-E "fixed kappa = 1": the scale of eq. (14) is replaced by a
+    # constant, so S = eta^2 e on every candidate edge; e itself is unchanged.
+    # Checked on the worked rows, whose e values are written out by hand.
+    rows = [l for l in open(os.path.join(GOLDEN, "evidence_examples.txt")) if l.strip() and not l.startswith("#")]
+    for line in rows:
+        lhs, rhs = line.split("->")
+        lhs = lhs.split()
+        dstar = int(lhs[0])
+        confs = [float(x) for x in lhs[1:]]
+        want_e = np.array([float(x) for x in rhs.split()][1:])
+        inst = _row_instance(confs)
+        cand = oracle.candidates(inst)
+        for kap in (1.0, 0.25):
+            ev = oracle.evidence(inst, cand, degree_target=dstar, kappa_fixed=kap)
+            assert ev["kappa"] == kap
+            eta2 = (1.0 / (0.1 * np.arange(1, len(confs) + 1))) ** 2
+            np.testing.assert_allclose(ev["heur"][0].astype(np.float64), eta2 * want_e ** kap, rtol=1e-6)
+    # on a real heatmap the fixed scale leaves e and q90 alone and ignores c_cap
+    inst = wl.tsp100()
+    cand = oracle.candidates(inst)
+    a = oracle.evidence(inst, cand)
+    b = oracle.evidence(inst, cand, kappa_fixed=1.0, c_cap=7.0)
+    assert np.array_equal(a["evid"], b["evid"]) and a["q90"] == b["q90"] and b["kappa"] == 1.0
+    assert a["kappa"] != 1.0 and not np.array_equal(a["heur"], b["heur"])
+
+
 def test_parameters_match_paper():
     prm = json.load(open(os.path.join(GOLDEN, "paper_parameters.json")))
     d = oracle.DEFAULTS

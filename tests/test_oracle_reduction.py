@@ -250,11 +250,13 @@ def test_empty_heatmap_equals_textbook_mmas(n, k, m, I, seed):
     assert L == want_L
 
 
-def test_capped_zero_equals_textbook_mmas():
-    # c_cap = 0 makes kappa = 0 even with an informative heatmap
+@pytest.mark.parametrize("over", [dict(c_cap=0.0), dict(kappa_fixed=0.0)])
+def test_capped_zero_equals_textbook_mmas(over):
+    # c_cap = 0, or the ablation's fixed scale at 0, makes kappa = 0 even
+    # with an informative heatmap
     inst = wl.random_instance(20, seed=4, topk=6, k=6, ants=4, iterations=15)
     want_t, want_L = TextbookMMAS(inst).run()
-    st, tour, L, info = oracle.decode(inst, c_cap=0.0)
+    st, tour, L, info = oracle.decode(inst, **over)
     assert info["kappa"] == 0.0
     assert list(tour) == want_t and L == want_L
 
