@@ -388,13 +388,45 @@ def run_paper(args, hac, wl):
     return out
 
 
+def run_ablation(args, hac, wl):
+    """Section IV-E on synthetic instances: the main setting, the fixed-scale
+    ablation (kappa = 1), plain MMAS weights (kappa = 0) and the c_cap sweep,
+    each a batched decode of the same instances and seeds.  Reports the mean
+    tour length of each setting and its ratio to the main setting (optimal
+    lengths are not available, so no gaps)."""
+    n, ls = args.paper_n, args.ls
+    count = args.instances or 16
+    insts = wl.paper_budget(n, count, local_search=ls, iterations=args.iterations or 1000)
+    settings = [("main (c_cap 0.5)", {}), ("fixed kappa = 1", {"kappa_fixed": 1.0}),
+                ("kappa = 0 (plain MMAS weights)", {"kappa_fixed": 0.0})]
+    settings += [(f"c_cap {c}", {"c_cap": c}) for c in (0.0625, 0.125, 0.25, 1.0, 2.0)]
+    ctx = hac.Context(0)
+    rows, main = [], None
+    t0 = time.perf_counter()
+    for name, over in settings:
+        t = time.perf_counter()
+        got = ctx.decode_batch(insts, [over] * len(insts))
+        wall = time.perf_counter() - t
+        mean = float(np.mean([g[1] for g in got]))
+        main = mean if main is None else main
+        rows.append({"setting": name, "mean_length": mean, "vs_main": mean / main,
+                     "kappa_first_instance": ctx.stats()["kappa"], "wall_s": wall})
+    ctx.close()
+    return {"metric": "mean tour length by evidence-scale setting", "unit": "length", "n_gpus": 1,
+            "higher_is_better": False, "data": "synthetic", "dtype": "f32+f64",
+            "config": {"workload": f"ablation: {count} uniform TSP instances, n={n}, top-20 heatmaps, 32 ants, "
+                                   f"{insts[0].iterations} iterations, k=20, rho=0.8, "
+                                   + ("2-opt on every ant" if ls == 2 else "no local search")},
+            "settings": rows, "wall_s": time.perf_counter() - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve", "paper"])
-    ap.add_argument("--paper-n", type=int, default=500, help="paper workload: instance size (500, 1000, 10000)")
+    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve", "paper", "ablation"])
+    ap.add_argument("--paper-n", type=int, default=500, help="paper/ablation workload: instance size")
     ap.add_argument("--ls", type=int, default=0, choices=[0, 2], help="paper workload: 2 = 2-opt on every ant")
     ap.add_argument("--instances", type=int, default=None, help="paper workload: instances in the batch")
     ap.add_argument("--iterations", type=int, default=None, help="override the workload's iteration count")
@@ -427,9 +459,10 @@ def main():
     from paper_2601_19041_amd import workloads as wl
 
     it = args.iterations
-    if args.workload == "paper":
+    if args.workload in ("paper", "ablation"):
         import paper_2601_19041_amd as hac
-        print(json.dumps(run_paper(args, hac, wl)))
+        run = run_paper if args.workload == "paper" else run_ablation
+        print(json.dumps(run(args, hac, wl)))
         return
     if args.workload == "batch64":
         insts = wl.batch64(64, iterations=it or 500)

@@ -105,6 +105,9 @@ typedef struct hac_params {
   int32_t restart_stall;  /* restart only after more stalled iterations    */
   int32_t ugb_max;        /* first tier of the u_gb schedule               */
   int32_t baseline_scope; /* eq. (10) row: 0 candidate row, 1 heatmap row  */
+  double kappa_fixed;     /* < 0: kappa from eq. (14); >= 0: kappa is this */
+                          /* value (the fixed-scale ablation of Sec. IV-E  */
+                          /* uses 1; 0 gives plain MMAS weights)           */
 } hac_params;
 
 typedef struct hac_ctx hac_ctx;

@@ -57,6 +57,7 @@ class hac_params(ctypes.Structure):
         ("degree_target", ctypes.c_int32), ("bf_period", ctypes.c_int32),
         ("restart_stall", ctypes.c_int32), ("ugb_max", ctypes.c_int32),
         ("baseline_scope", ctypes.c_int32),
+        ("kappa_fixed", ctypes.c_double),
     ]
 
 

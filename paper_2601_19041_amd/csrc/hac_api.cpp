@@ -117,7 +117,7 @@ hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_para
   if (!(p->p_best > 0.0 && p->p_best < 1.0)) return fail(HAC_EINVAL, "p_best outside (0,1)");
   if (!finite_nonneg(p->beta) || !finite_nonneg(p->c_cap) || !finite_nonneg(p->theta_h) ||
       !(p->eps > 0.0 && std::isfinite(p->eps)) || !(p->xi_bf >= 0.0 && p->xi_bf <= 1.0) ||
-      !std::isfinite(p->lambda_bf) || !finite_nonneg(p->clip))
+      !std::isfinite(p->lambda_bf) || !finite_nonneg(p->clip) || !std::isfinite(p->kappa_fixed))
     return fail(HAC_EINVAL, "parameter out of range");
   if (p->degree_target < 0 || p->bf_period < 0 || p->restart_stall < 0 || p->ugb_max < 1 ||
       (p->baseline_scope != 0 && p->baseline_scope != 1) ||
@@ -330,6 +330,7 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
     in.theta_h = h.p.theta_h;
     in.eps = h.p.eps;
     in.c_cap = h.p.c_cap;
+    in.kappa_fixed = h.p.kappa_fixed;
     in.alpha = h.p.alpha;
     in.beta = h.p.beta;
     in.clip = h.p.clip;
@@ -646,6 +647,7 @@ void hac_params_default(hac_params* p) {
   p->rho = 0.2;
   p->p_best = 0.05;
   p->c_cap = 0.5;
+  p->kappa_fixed = -1.0;
   p->theta_h = 1e-4;
   p->eps = 1e-9;
   p->xi_bf = 0.05;

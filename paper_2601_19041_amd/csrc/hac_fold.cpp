@@ -107,7 +107,9 @@ int fold_instance(const FoldInput& in, const int32_t* cand, float* heur, FoldOut
   }
   // eq. (13)-(14)
   const double range = fold_range(n, k, in.local_search, in.p_best);
-  const double kappa = (q90 > 0.0 && range > 1.0) ? in.c_cap * in.alpha * std::log(range) / q90 : 0.0;
+  const double kappa = in.kappa_fixed >= 0.0 ? in.kappa_fixed
+                       : (q90 > 0.0 && range > 1.0) ? in.c_cap * in.alpha * std::log(range) / q90
+                                                    : 0.0;
 
   // fold: S = eta^beta * exp(min(kappa log e, clip))
   float hmin = FLT_MAX, hmax = 0.0f;

@@ -15,6 +15,7 @@ struct FoldInput {
   const int32_t* col;
   const float* val;
   double theta_h, eps, c_cap, alpha, beta, clip, p_best, rho;
+  double kappa_fixed;  // >= 0 replaces eq. (14)
 };
 
 struct FoldOutput {

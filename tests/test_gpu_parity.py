@@ -251,3 +251,15 @@ def test_batch_mixed_local_search(ctx):
         _same(got[x], oracle.decode(inst), f"mixed{x}")
         alone = ctx.decode(inst)
         assert np.array_equal(alone[0], got[x][0]) and alone[1] == got[x][1]
+
+
+@pytest.mark.parametrize("over", [dict(kappa_fixed=1.0), dict(kappa_fixed=0.0), dict(c_cap=0.0625), dict(c_cap=0.125),
+                                  dict(c_cap=0.25), dict(c_cap=1.0), dict(c_cap=2.0)])
+def test_ablation_settings(ctx, over):
+    """Section IV-E: the fixed-scale ablation and the c_cap sweep."""
+    inst = wl.tsp100(instance=3, seed=4, iterations=30)
+    print(f"case ablation {over}", flush=True)
+    gpu = ctx.decode(inst, **over)
+    ref = oracle.decode(inst, **over)
+    _same(gpu, ref, str(over))
+    assert ctx.stats()["kappa"] == ref[3]["kappa"]
