@@ -504,14 +504,14 @@ __global__ void __launch_bounds__(64) nn_tour_kernel(const InstDesc* insts) {
 
 // ------------------------------------------------------------------------
 // First-improvement 2-opt over the geometric lists with a FIFO don't-look
-// queue (Section III-D), one block of LS_WAVES waves per tour.
+// queue (Section III-D), one block of up to LS_WAVES waves per tour.
 //
 // Sequentially, node a leaves the queue head and its moves are scanned:
 // successor direction, then predecessor, each in list order and stopping at
 // the first neighbour c with d(a,c) >= d(a,b).  The first improving move is
 // applied, its end nodes are queued if absent, and a is examined again.  A
 // node without an improving move only leaves the queue.  The block
-// therefore evaluates the next LS_WAVES queue entries at once, one wave per
+// therefore evaluates the next W queue entries at once (W = its waves), one wave per
 // entry and all against the same tour (lanes 0..31 the successor moves,
 // 32..63 the predecessor moves).  The entries before the first one with an
 // improving move are consumed exactly as a sequential scan would consume
@@ -644,6 +644,7 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
   __shared__ int sh_head, sh_count;
   __shared__ LsMove sh_mv[LS_WAVES];
   const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
+  const int nw = (int)(blockDim.x / WAVE);  // 1 .. LS_WAVES entries per batch
   if (n < 5 || kls < 1) return;
   const GDist G(D);
   const HAC_AS1 int32_t* geo = as_global(D.geo);
@@ -665,7 +666,7 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
   for (;;) {
     const int head = sh_head, count = sh_count;
     const int re = pend >= 0 ? 1 : 0;
-    const int nq = min(LS_WAVES - re, count);  // queue entries in this batch
+    const int nq = min(nw - re, count);  // queue entries in this batch
     const int nb = nq + re;
     if (nb == 0) break;
     if (wave < nb) {
@@ -1991,10 +1992,28 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
   return hipGetLastError();
 }
 
+// Waves per 2-opt block.  Results do not depend on it (the speculative
+// batch keeps the sequential outcome).  One tour per instance gets the full
+// LS_WAVES; when every ant's tour is searched, blocks shrink to as few as 4
+// waves so that as many tours run at once as LDS allows on a CU (32 waves
+// per CU).  HAC_LS_WAVES pins the count.
+static int ls_block_waves(int32_t max_n, int mode, int64_t tours) {
+  if (const char* env = std::getenv("HAC_LS_WAVES")) {
+    const int w = std::atoi(env);
+    if (w >= 1 && w <= LS_WAVES) return w;
+  }
+  if (tours <= 256) return LS_WAVES;
+  const size_t need = ls_lds_need(max_n, mode);
+  const int by_lds = need ? (int)std::max<size_t>(1, (size_t)max_lds_bytes() / need) : 8;
+  return std::max(4, std::min(LS_WAVES, 32 / std::min(by_lds, 8)));
+}
+
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                int32_t all_coords, int32_t tours_per_inst, hipStream_t s) {
   const int mode = ls_mode(max_n, all_coords);
-  const dim3 grid(count, std::max(tours_per_inst, 1)), block(LS_WAVES * WAVE);
+  const int tpi = std::max(tours_per_inst, 1);
+  const int waves = tpi > 1 ? ls_block_waves(max_n, mode, (int64_t)count * tpi) : LS_WAVES;
+  const dim3 grid(count, tpi), block(waves * WAVE);
   if (mode == 2)
     hipLaunchKernelGGL(local_search_kernel<2>, grid, block, ls_lds_need(max_n, 2), s, d_insts);
   else if (mode == 1)

@@ -263,3 +263,14 @@ def test_ablation_settings(ctx, over):
     ref = oracle.decode(inst, **over)
     _same(gpu, ref, str(over))
     assert ctx.stats()["kappa"] == ref[3]["kappa"]
+
+
+@pytest.mark.parametrize("waves", ["1", "3", "16"])
+def test_every_ant_block_waves(ctx, waves, monkeypatch):
+    """The waves of a 2-opt block set how many queue entries are evaluated
+    at once; the outcome stays the sequential one."""
+    inst = wl.random_instance(300, seed=23, k=10, ants=12, iterations=5, local_search=2, k_ls=12)
+    monkeypatch.setenv("HAC_LS_WAVES", waves)
+    print(f"case every-ant 2-opt, {waves} waves per block", flush=True)
+    _same(ctx.decode(inst), oracle.decode(inst), f"waves {waves}")
+    _state_parity(ctx, inst)
