@@ -356,9 +356,11 @@ def run_paper(args, hac, wl):
     ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
     ctx = hac.Context(0)
     db = hac.DeviceBatch(insts)
+    print(f"paper{n} ls={ls}: batched decode of {count} instances", file=sys.stderr, flush=True)
     wall, times, cms, launches = timed_batches(ctx, db, args.steps, args.warmup)
     batched = db.results()
     st = ctx.stats()
+    print(f"paper{n} ls={ls}: batched {wall:.1f} s; plain decodes", file=sys.stderr, flush=True)
     lat, psteps, equal = plain_sample(ctx, insts, max(1, min(args.plain_sample, count)), batched)
     assert equal, "plain and batched tours differ"
     mean_len = float(np.mean([batched[x][1] for x in range(count)]))
