@@ -156,15 +156,17 @@ def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_b
     print(json.dumps(d[key]))
 
 
-def roofline(insts, cms, launches):
-    """Construction kernel: one launch = one iteration of every instance."""
+def roofline(insts, cms, launches, traffic_key=None):
+    """Construction kernel: one launch = one iteration of every instance.
+    `traffic` is the counter-measured HBM bytes per launch, available only
+    for the launch the counters were taken on (traffic_key), else null."""
     bytes_per_launch = sum(x.ants * (x.n - 1) * construct_bytes_per_step(x.k, x.kind) for x in insts)
     avg_launch_s = (cms / 1000.0) / max(launches, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     src = open(os.path.join(ROOT, "paper_2601_19041_amd", "csrc", "hac_kernels.hip"), "rb").read()
     return {"bound": "hbm", "kernel": "construct_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_from_profile(hashlib.sha256(src).hexdigest(), "batch64"),
+            "traffic": traffic_from_profile(hashlib.sha256(src).hexdigest(), traffic_key) if traffic_key else None,
             "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
             "algorithmic_bytes_per_launch": bytes_per_launch}
 
@@ -210,7 +212,7 @@ def base_line(args, metric, value, ms_per_step, config):
             "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic", "config": config}
 
 
-def run_batched(args, hac, insts, cpu, name, desc, plain_count):
+def run_batched(args, hac, insts, cpu, name, desc, plain_count, traffic_key=None):
     count = len(insts)
     ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
     ctx = hac.Context(0)
@@ -236,7 +238,7 @@ def run_batched(args, hac, insts, cpu, name, desc, plain_count):
         "latency_ms": {"batched_p50": 1000 * percentile(times, 0.5), "batched_p99": 1000 * percentile(times, 0.99),
                        "plain_p50": 1000 * percentile(lat, 0.5), "plain_p99": 1000 * percentile(lat, 0.99)},
         "fallback_fraction": st["fallback_steps"] / max(1, st["ant_steps"]),
-        "roofline": roofline(insts, cms, launches),
+        "roofline": roofline(insts, cms, launches, traffic_key),
         "cpu_baseline": cpu,
     })
     ctx.close()
@@ -484,7 +486,7 @@ def main():
     if args.workload == "batch64":
         out = run_batched(args, hac, insts, cpu, "64 TSP instances, n 500-1000",
                           "batch64: 64 TSP instances, n uniform on [500,1000], top-10 SoftDist heatmaps, "
-                          "k=10, 50 ants, 500 iterations, no local search", args.plain_sample)
+                          "k=10, 50 ants, 500 iterations, no local search", args.plain_sample, "batch64")
     elif args.workload == "tsp10k":
         out = run_batched(args, hac, insts, cpu, "8 TSP instances, n 10000, 2-opt",
                           "tsp10k: 8 TSP instances, n=10000, top-20 heatmaps, k=20, 100 ants, 200 iterations, "
