@@ -159,3 +159,41 @@ def test_paper1000_packed_staging(ctx, monkeypatch):
         _check(forced[x], insts[x])
     for x in range(len(insts)):
         assert np.array_equal(tuned[x][0], forced[x][0]) and tuned[x][1] == forced[x][1]
+
+
+def test_beyond_uint16_node_ids(ctx):
+    """n = 66 000 (node ids past 16 bits): no LDS staging, bit marks without
+    unvisited lists, the grid search, global-memory 2-opt.  A full decode of
+    3 ants for 2 iterations with 2-opt on the iteration best equals the
+    oracle's."""
+    from scipy.spatial import cKDTree
+    n = 66000
+    rng = np.random.Generator(np.random.Philox(key=[77, 1]))
+    xy = wl.uniform_coords(n, rng)
+    # a heatmap over each node's 8 nearest (k-d tree: the dense generators
+    # are too slow at this size), softmax(-d/0.05), symmetrised by max
+    d, idx = cKDTree(xy).query(xy, k=9)
+    d, idx = d[:, 1:], idx[:, 1:]
+    w = np.exp(-(d - d[:, :1]) / 0.05)
+    w /= w.sum(axis=1, keepdims=True)
+    r = np.repeat(np.arange(n), 8)
+    c = idx.reshape(-1)
+    v = w.reshape(-1)
+    key = np.concatenate([r * n + c, c * n + r])
+    val = np.concatenate([v, v])
+    order = np.lexsort((-val, key))
+    key, val = key[order], val[order]
+    first = np.ones(len(key), dtype=bool)
+    first[1:] = key[1:] != key[:-1]
+    key, val = key[first], val[first]
+    rows, cols = key // n, key % n
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(row_ptr, rows + 1, 1)
+    heat = wl.Heatmap(n, np.cumsum(row_ptr).astype(np.int32), cols.astype(np.int32), val.astype(np.float32))
+    inst = wl.Instance(n, "coords", True, xy, None, heat, ants=3, iterations=2, k=8, local_search=1, k_ls=8,
+                       seed=5, name="n66000")
+    print("case n=66000", flush=True)
+    got = ctx.decode(inst)
+    st = ctx.stats()
+    assert st["lds_staged"] == 0 and st["byte_marks"] in (0, 1)
+    _check(got, inst)
