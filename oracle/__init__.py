@@ -94,6 +94,8 @@ def lib():
         L.orc_two_opt.argtypes = [P, vp, ctypes.c_int32, ctypes.c_double, vp]
         L.orc_decode.argtypes = [P, vp, vp, ctypes.POINTER(Trace)]
         L.orc_decode.restype = ctypes.c_int32
+        L.orc_diagnostics.argtypes = [P, vp, vp, vp]
+        L.orc_diagnostics.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -246,3 +248,18 @@ def decode(inst, trace: bool = False, state: bool = False, **over):
     for name, arr in bufs.items():
         info[name] = arr[:iters] if name in ("l_ib", "l_gb", "elite_rb") else arr
     return st, tour, L.value, info
+
+
+def diagnostics(inst, tour, **over) -> dict:
+    """Heatmap diagnostics against a known tour (Section V): Edges/n,
+    coverage, Miss% and P(e>1).  Returns None on invalid input."""
+    p = OracleProblem(inst, **over)
+    t = np.ascontiguousarray(tour, dtype=np.int32)
+    out = np.zeros(4)
+    cnt = np.zeros(3, dtype=np.int64)
+    st = lib().orc_diagnostics(p.ref, _ptr(t), _ptr(out), _ptr(cnt))
+    if st != 0:
+        return None
+    return dict(edges_per_node=float(out[0]), coverage=float(out[1]), miss_pct=float(out[2]),
+                p_evidence=float(out[3]), entries=int(cnt[0]), evidence_slots=int(cnt[1]),
+                evidence_on_tour=int(cnt[2]))

@@ -560,6 +560,68 @@ static int valid_problem(const orc_problem* p) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Section V: heatmap diagnostics against a known tour.                       */
+/* ------------------------------------------------------------------------ */
+int32_t orc_diagnostics(const orc_problem* p, const int32_t* tour, double out[4], int64_t counts[3]) {
+  int32_t n = p->n;
+  if (!valid_problem(p) || n < 2) return -1;
+  int sym = is_sym(p);
+  /* the known tour's successor and predecessor of every node */
+  int32_t* succ = (int32_t*)malloc(4 * (size_t)n);
+  int32_t* pred = (int32_t*)malloc(4 * (size_t)n);
+  uint8_t* seen = (uint8_t*)calloc((size_t)n, 1);
+  for (int32_t s = 0; s < n; s++) {
+    int32_t a = tour[s];
+    if (a < 0 || a >= n || seen[a]) { free(succ); free(pred); free(seen); return -1; }
+    seen[a] = 1;
+  }
+  for (int32_t s = 0; s < n; s++) {
+    succ[tour[s]] = tour[(s + 1) % n];
+    pred[tour[s]] = tour[(s + n - 1) % n];
+  }
+  /* E_theta: directed entries above the threshold; and which tour edges
+     they cover (edge s is (tour[s], tour[s+1])) */
+  int64_t entries = 0, covered = 0;
+  uint8_t* has_out = (uint8_t*)calloc((size_t)n, 1); /* (a, succ a) present   */
+  uint8_t* has_in = (uint8_t*)calloc((size_t)n, 1);  /* (succ a, a) present   */
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; e++) {
+      int32_t j = p->col[e];
+      if (j == i || !((double)p->val[e] > p->theta_h)) continue;
+      entries++;
+      if (j == succ[i]) has_out[i] = 1;
+      if (j == pred[i]) has_in[j] = 1; /* the reversed direction of edge (j, i) */
+    }
+  for (int32_t a = 0; a < n; a++)
+    if (has_out[a] || (sym && has_in[a])) covered++;
+  /* P(e > 1) over the candidate slots */
+  int32_t k_eff = p->k < n - 1 ? p->k : n - 1;
+  int64_t nk = (int64_t)n * k_eff;
+  int32_t* cand = (int32_t*)malloc(4 * nk);
+  double* evid = (double*)malloc(sizeof(double) * nk);
+  orc_candidates(p, cand);
+  orc_evidence(p, cand, k_eff, NULL, NULL, evid, NULL, NULL, NULL);
+  int64_t strong = 0, on_tour = 0;
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t u = 0; u < k_eff; u++) {
+      int64_t x = (int64_t)i * k_eff + u;
+      if (!(evid[x] > 1.0)) continue;
+      strong++;
+      int32_t j = cand[x];
+      if (j == succ[i] || (sym && j == pred[i])) on_tour++;
+    }
+  out[0] = (double)entries / (2.0 * (double)n);
+  out[1] = (double)covered / (double)n;
+  out[2] = 100.0 * (1.0 - out[1]);
+  out[3] = strong > 0 ? (double)on_tour / (double)strong : 0.0;
+  counts[0] = entries;
+  counts[1] = strong;
+  counts[2] = on_tour;
+  free(succ); free(pred); free(seen); free(has_out); free(has_in); free(cand); free(evid);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Alg. 1: the decode loop.                                                   */
 /* ------------------------------------------------------------------------ */
 int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc_trace* tr) {

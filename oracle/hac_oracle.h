@@ -89,6 +89,18 @@ void orc_two_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min
 /* Whole decode (Alg. 1).  tour_out [n] canonical, len_out.  0 on success. */
 int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc_trace* tr);
 
+/* Heatmap diagnostics against a known tour (Section V):
+ *   out[0] Edges/n: directed heatmap entries h_ij > theta_h (i != j) over 2n
+ *   out[1] coverage: share of the known tour's n edges among those entries
+ *          (an undirected edge counts if either direction is present; ATSP
+ *          edges are directed)
+ *   out[2] Miss%: 100 (1 - coverage)
+ *   out[3] P(e>1): share of the candidate slots with e > 1 (eq. 11) whose
+ *          edge is on the known tour (0 when no slot has e > 1)
+ *   counts[0] entries, counts[1] slots with e > 1, counts[2] those on the tour
+ * Returns 0, or -1 on invalid input (tour not a permutation, n < 2). */
+int32_t orc_diagnostics(const orc_problem* p, const int32_t* tour, double out[4], int64_t counts[3]);
+
 #ifdef __cplusplus
 }
 #endif

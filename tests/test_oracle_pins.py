@@ -604,3 +604,73 @@ def test_invalid_inputs_rejected():
     assert oracle.decode(inst, rho=1.5)[0] != 0
     assert oracle.decode(inst, alpha=2.0)[0] != 0
     assert oracle.decode(inst)[0] == 0
+
+
+# --------------------------------------------------------------------------
+# Section V: heatmap diagnostics against a known tour
+# --------------------------------------------------------------------------
+def _hexagon(entries, kind="coords"):
+    n = 6
+    xy = np.array([[math.cos(2 * math.pi * i / n), math.sin(2 * math.pi * i / n)] for i in range(n)])
+    keys = sorted(entries)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    for i, _ in keys:
+        rp[i + 1] += 1
+    heat = wl.Heatmap(n, np.cumsum(rp).astype(np.int32), np.array([j for _, j in keys], dtype=np.int32),
+                      np.array([entries[x] for x in keys], dtype=np.float32))
+    if kind == "coords":
+        return wl.Instance(n, "coords", True, xy, None, heat, ants=2, iterations=1, k=3)
+    d = np.sqrt(((xy[:, None, :] - xy[None, :, :]) ** 2).sum(-1))
+    return wl.Instance(n, "matrix", False, None, d, heat, ants=2, iterations=1, k=3)
+
+
+def _hexagon_entries():
+    # tour 0-1-2-3-4-5 with both directions at 1.0, except {2,3} at 0.1; a
+    # chord {0,3} at 1.0; a directed chord (2,5) at 1.0; (1,4) below theta_h
+    e = {}
+    for i in range(6):
+        e[(i, (i + 1) % 6)] = 1.0
+        e[((i + 1) % 6, i)] = 1.0
+    e[(2, 3)] = e[(3, 2)] = 0.1
+    e[(0, 3)] = e[(3, 0)] = 1.0
+    e[(2, 5)] = 1.0
+    e[(1, 4)] = 5e-5
+    return e
+
+
+def test_diagnostics_worked_example():
+    # Worked by hand (d* = 2, k = 3):
+    #  entries above theta_h: 12 tour directions + (0,3), (3,0), (2,5) = 15,
+    #  so Edges/n = 15 / 12; every tour edge is present: coverage 1, Miss 0.
+    #  Row 0: three equal confidences, b = 1, no e > 1.  Rows 1, 4, 5: two
+    #  supported candidates, b = eps, both tour neighbours get e > 1.  Row 2:
+    #  {1: 1, 3: 0.1, 5: 1}, b = 0.1, e > 1 on 1 (tour) and 5 (chord).  Row 3:
+    #  {2: 0.1, 4: 1, 0: 1}, e > 1 on 4 (tour) and 0 (chord).  10 slots, 8 on
+    #  the tour: P(e>1) = 0.8.
+    d = oracle.diagnostics(_hexagon(_hexagon_entries()), np.arange(6))
+    assert d["entries"] == 15 and d["edges_per_node"] == 15 / 12
+    assert d["coverage"] == 1.0 and d["miss_pct"] == 0.0
+    assert d["evidence_slots"] == 10 and d["evidence_on_tour"] == 8 and d["p_evidence"] == 0.8
+    # the same tour read backwards covers the same undirected edges
+    d2 = oracle.diagnostics(_hexagon(_hexagon_entries()), np.arange(6)[::-1])
+    assert d2["coverage"] == 1.0 and d2["p_evidence"] == 0.8
+
+
+def test_diagnostics_directed_coverage():
+    # Drop the direction (2,3): a symmetric instance still covers tour edge
+    # {2,3} through (3,2); on the ATSP the directed edge 2 -> 3 is missing.
+    e = _hexagon_entries()
+    del e[(2, 3)]
+    sym = oracle.diagnostics(_hexagon(e), np.arange(6))
+    asym = oracle.diagnostics(_hexagon(e, kind="matrix"), np.arange(6))
+    assert sym["coverage"] == 1.0
+    assert asym["coverage"] == 5 / 6 and asym["miss_pct"] == pytest.approx(100 / 6, rel=1e-12)
+    # an entry below the threshold does not count
+    e2 = _hexagon_entries()
+    e2[(4, 5)] = e2[(5, 4)] = 5e-5
+    assert oracle.diagnostics(_hexagon(e2), np.arange(6))["coverage"] == 5 / 6
+
+
+def test_diagnostics_invalid_tour():
+    assert oracle.diagnostics(_hexagon(_hexagon_entries()), [0, 1, 2, 3, 4, 4]) is None
+    assert oracle.diagnostics(_hexagon(_hexagon_entries()), [0, 1, 2, 3, 4, 6]) is None
