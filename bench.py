@@ -424,12 +424,34 @@ def run_ablation(args, hac, wl):
             "settings": rows, "wall_s": time.perf_counter() - t0}
 
 
+def run_diagnostics(args, hac, wl):
+    """Section V diagnostics of the synthetic heatmaps: candidate density,
+    coverage of a known tour and P(e>1).  The known tour is the decoder's
+    own best tour for each workload's settings (optimal tours are not
+    available)."""
+    cases = [("tsp500", wl.tsp500()), ("batch64#0", wl.batch64(1)[0]),
+             ("atsp1000", wl.serve_request("atsp1000", 0)), ("tsp10k#0", wl.tsp10k(1)[0])]
+    ctx = hac.Context(0)
+    rows = []
+    for name, inst in cases:
+        print(f"diagnostics: {name}", file=sys.stderr, flush=True)
+        tour, length = ctx.decode(inst)
+        d = ctx.diagnostics(inst, tour)
+        d.update({"workload": name, "n": inst.n, "known_tour": f"decoded best, length {length:.4f}"})
+        rows.append(d)
+    ctx.close()
+    return {"metric": "heatmap diagnostics (Edges/n, Miss%, P(e>1))", "unit": "mixed", "n_gpus": 1,
+            "data": "synthetic", "config": {"workload": "diagnostics of the synthetic workload heatmaps"},
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve", "paper", "ablation"])
+    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve", "paper", "ablation",
+                             "diagnostics"])
     ap.add_argument("--paper-n", type=int, default=500, help="paper/ablation workload: instance size")
     ap.add_argument("--ls", type=int, default=0, choices=[0, 2], help="paper workload: 2 = 2-opt on every ant")
     ap.add_argument("--instances", type=int, default=None, help="paper workload: instances in the batch")
@@ -463,9 +485,9 @@ def main():
     from paper_2601_19041_amd import workloads as wl
 
     it = args.iterations
-    if args.workload in ("paper", "ablation"):
+    if args.workload in ("paper", "ablation", "diagnostics"):
         import paper_2601_19041_amd as hac
-        run = run_paper if args.workload == "paper" else run_ablation
+        run = {"paper": run_paper, "ablation": run_ablation, "diagnostics": run_diagnostics}[args.workload]
         print(json.dumps(run(args, hac, wl)))
         return
     if args.workload == "batch64":

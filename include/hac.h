@@ -202,6 +202,38 @@ hac_status hac_decode_batch_dev(hac_ctx* ctx, int32_t count, const hac_instance*
 
 hac_status hac_last_stats(const hac_ctx* ctx, hac_stats* out);
 
+/* Heatmap diagnostics against a known tour (Section V): how dense the
+ * thresholded heatmap is, whether it holds the known tour's edges, and how
+ * many of the candidate edges that eq. (11) marks with evidence (e > 1) lie
+ * on that tour.  The candidate lists and the evidence are those a decode
+ * with these parameters builds (the candidate kernel on the device, the
+ * fold of eq. (9)-(11)); no iteration runs.
+ *   edges_per_node  directed entries with h_ij > theta_h, i != j, over 2n
+ *   coverage        share of the known tour's n edges present among them;
+ *                   for a symmetric instance an edge counts if either
+ *                   direction is present, for the ATSP the tour's direction
+ *   miss_pct        100 (1 - coverage)
+ *   p_evidence      share of candidate slots with e > 1 whose edge is on
+ *                   the known tour (either tour neighbour for a symmetric
+ *                   instance, the successor for the ATSP); 0 if none
+ * Inputs are host pointers, read only; known_tour is int32[n], a
+ * permutation of 0..n-1.  Errors: HAC_EINVAL (null argument, n < 2, a tour
+ * that is not a permutation, or any decode input error), HAC_ERANGE as for
+ * a decode; *out is untouched on error. */
+typedef struct hac_diagnostics {
+  double edges_per_node;
+  double coverage;
+  double miss_pct;
+  double p_evidence;
+  int64_t heatmap_edges;    /* directed entries above theta_h                 */
+  int64_t evidence_slots;   /* candidate slots with e > 1                    */
+  int64_t evidence_on_tour; /* those on the known tour                       */
+} hac_diagnostics;
+
+hac_status hac_heatmap_diagnostics(hac_ctx* ctx, const hac_instance* inst, const hac_csr* heat,
+                                   const hac_params* params, const int32_t* known_tour,
+                                   hac_diagnostics* out);
+
 /* Test/inspection hook: after a decode, copies the final state of instance
  * `which` of the last call: candidate lists int32[n][k'], folded heuristic
  * float[n][k'], pheromone float[n][k'], choice weights float[n][k'], the

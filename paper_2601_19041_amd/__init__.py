@@ -61,6 +61,13 @@ class hac_params(ctypes.Structure):
     ]
 
 
+class hac_diagnostics(ctypes.Structure):
+    _fields_ = [("edges_per_node", ctypes.c_double), ("coverage", ctypes.c_double),
+                ("miss_pct", ctypes.c_double), ("p_evidence", ctypes.c_double),
+                ("heatmap_edges", ctypes.c_int64), ("evidence_slots", ctypes.c_int64),
+                ("evidence_on_tour", ctypes.c_int64)]
+
+
 class hac_stats(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
                 ("search_ms", ctypes.c_double), ("construct_ms", ctypes.c_double),
@@ -79,7 +86,7 @@ EXPORTS = ["hac_params_default", "hac_strerror", "hac_validate", "hac_create", "
            "hac_decode_batch_dev",
            "hac_last_stats", "hac_debug_state", "hac_debug_trace", "hac_footprint",
            "hac_server_create", "hac_server_submit", "hac_server_poll", "hac_server_wait",
-           "hac_server_cancel", "hac_server_counters", "hac_server_destroy"]
+           "hac_server_cancel", "hac_server_counters", "hac_server_destroy", "hac_heatmap_diagnostics"]
 
 _lib = None
 
@@ -128,6 +135,8 @@ def lib():
         L.hac_debug_state.restype = i32
         L.hac_debug_trace.argtypes = [vp, i32, vp, vp, vp]
         L.hac_debug_trace.restype = i32
+        L.hac_heatmap_diagnostics.argtypes = [vp, PI, PC, PP, vp, ctypes.POINTER(hac_diagnostics)]
+        L.hac_heatmap_diagnostics.restype = i32
         if hasattr(L, "hac_footprint"):
             L.hac_footprint.argtypes = [PI, PC, PP]
             L.hac_footprint.restype = u64
@@ -321,6 +330,18 @@ class Context:
                                                       "ant_len", "nn_tour")])
         self._check(st, "hac_debug_state")
         return out
+
+    def diagnostics(self, inst, known_tour, **over) -> dict:
+        """Heatmap diagnostics against a known tour (hac_heatmap_diagnostics)."""
+        m = Marshalled(inst, **over)
+        t = np.ascontiguousarray(known_tour, dtype=np.int32)
+        d = hac_diagnostics()
+        st = lib().hac_heatmap_diagnostics(self._h, ctypes.byref(m.s_inst), ctypes.byref(m.s_csr),
+                                           ctypes.byref(m.s_params), t.ctypes.data, ctypes.byref(d))
+        self._check(st, "hac_heatmap_diagnostics")
+        return dict(edges_per_node=d.edges_per_node, coverage=d.coverage, miss_pct=d.miss_pct,
+                    p_evidence=d.p_evidence, entries=d.heatmap_edges, evidence_slots=d.evidence_slots,
+                    evidence_on_tour=d.evidence_on_tour)
 
     def debug_trace(self, which: int, iterations: int) -> dict:
         out = dict(l_ib=np.zeros(iterations), l_gb=np.zeros(iterations),

@@ -337,6 +337,10 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
     in.p_best = h.p.p_best;
     in.rho = h.p.rho;
     const size_t nk = (size_t)L.n * L.k;
+    if (h.want_evid) {
+      h.evid_gt1.assign(nk, 0);
+      in.evid_gt1 = h.evid_gt1.data();
+    }
     heur[x].assign(nk + 4, 0.0f);
     frc[x] = fold_instance(in, h.cand_h.data(), heur[x].data(), &h.fold);
     // lower bound on any tour: every node leaves once, at least to its nearest
@@ -1069,6 +1073,94 @@ hac_status hac_debug_state(hac_ctx* c, int32_t which, int32_t* cand, float* heur
   if (ant_len) CTX_HIP(hipMemcpyAsync(ant_len, h.d.lens, 8 * (size_t)h.p.ants, hipMemcpyDeviceToHost, s));
   if (nn_tour) CTX_HIP(hipMemcpyAsync(nn_tour, h.d.nn_tour, 4 * nn, hipMemcpyDeviceToHost, s));
   CTX_HIP(hipStreamSynchronize(s));
+  return HAC_OK;
+}
+
+hac_status hac_heatmap_diagnostics(hac_ctx* c, const hac_instance* inst, const hac_csr* heat,
+                                   const hac_params* p, const int32_t* known_tour, hac_diagnostics* out) {
+  if (!c) return HAC_EINVAL;
+  c->err.clear();
+  if (!inst || !heat || !p || !known_tour || !out) return set_err(c, HAC_EINVAL, "null argument");
+  std::string why;
+  const hac_status vs = validate(inst, heat, p, &why);
+  if (vs != HAC_OK) return set_err(c, vs, why);
+  const int32_t n = inst->n;
+  if (n < 2) return set_err(c, HAC_EINVAL, "diagnostics need n >= 2");
+  std::vector<int32_t> succ(n), pred(n);
+  std::vector<char> seen(n, 0);
+  for (int32_t s = 0; s < n; ++s) {
+    const int32_t a = known_tour[s];
+    if (a < 0 || a >= n || seen[a]) return set_err(c, HAC_EINVAL, "known tour is not a permutation");
+    seen[a] = 1;
+  }
+  for (int32_t s = 0; s < n; ++s) {
+    succ[known_tour[s]] = known_tour[(s + 1) % n];
+    pred[known_tour[s]] = known_tour[(s + n - 1) % n];
+  }
+  // the candidate lists and evidence of a decode with these parameters
+  CTX_HIP(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  hac_params q = *p;
+  q.iterations = 0;
+  HostInst h{};
+  h.inst = *inst;
+  h.csr = *heat;
+  h.p = q;
+  h.seed = 0;
+  h.lay = make_layout(inst, heat, &q);
+  h.dstar = degree_target_of(inst, &q);
+  h.sym = (inst->kind == HAC_COORDS_EUC2D || inst->symmetric) ? 1 : 0;
+  h.p_x = fold_p_x(q.p_best, n);
+  h.want_evid = true;
+  const size_t total = align256(sizeof(InstDesc)) + h.lay.bytes();
+  if (c->budget && total > c->budget) return set_err(c, HAC_ENOMEM, "instance exceeds the context budget");
+  {
+    hipError_t e = c->arena.reserve(total);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return set_err(c, HAC_ENOMEM, "device memory");
+    CTX_HIP(e);
+  }
+  InstDesc* d_descs = (InstDesc*)c->arena.carve(sizeof(InstDesc));
+  assign_slot(h, [&](size_t b) { return c->arena.carve(b); });
+  fill_desc_scalars(h);
+  CTX_HIP(upload_inputs(h, s));
+  CTX_HIP(hipMemcpyAsync(d_descs, &h.d, sizeof(InstDesc), hipMemcpyHostToDevice, s));
+  std::vector<HostInst> hs{h};
+  std::string err;
+  const hac_status ps = prepare_instances(hs, d_descs, s, &err);
+  if (ps != HAC_OK) return set_err(c, ps, err);
+  CTX_HIP(hipStreamSynchronize(s));
+  const HostInst& g = hs[0];
+  // Edges/n and coverage, from the heatmap as given
+  int64_t entries = 0, covered = 0;
+  std::vector<char> has_out(n, 0), has_in(n, 0);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t e = heat->row_ptr[i]; e < heat->row_ptr[i + 1]; ++e) {
+      const int32_t j = heat->col[e];
+      if (j == i || !((double)heat->val[e] > q.theta_h)) continue;
+      ++entries;
+      if (j == succ[i]) has_out[i] = 1;
+      if (j == pred[i]) has_in[j] = 1;  // the reverse of tour edge (j, i)
+    }
+  for (int32_t a = 0; a < n; ++a)
+    if (has_out[a] || (g.sym && has_in[a])) ++covered;
+  // P(e > 1) over the candidate slots
+  int64_t strong = 0, on_tour = 0;
+  const int32_t k = g.lay.k;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t u = 0; u < k; ++u) {
+      const size_t x = (size_t)i * k + u;
+      if (!g.evid_gt1[x]) continue;
+      ++strong;
+      const int32_t j = g.cand_h[x];
+      if (j == succ[i] || (g.sym && j == pred[i])) ++on_tour;
+    }
+  out->edges_per_node = (double)entries / (2.0 * (double)n);
+  out->coverage = (double)covered / (double)n;
+  out->miss_pct = 100.0 * (1.0 - out->coverage);
+  out->p_evidence = strong > 0 ? (double)on_tour / (double)strong : 0.0;
+  out->heatmap_edges = entries;
+  out->evidence_slots = strong;
+  out->evidence_on_tour = on_tour;
   return HAC_OK;
 }
 

@@ -92,6 +92,8 @@ int fold_instance(const FoldInput& in, const int32_t* cand, float* heur, FoldOut
     }
   }
 
+  if (in.evid_gt1)
+    for (int64_t x = 0; x < nk; ++x) in.evid_gt1[x] = evid[x] > 1.0 ? 1 : 0;
   // eq. (12): 0.9-quantile of the positive log-margins, linear interpolation
   std::vector<double> margins;
   for (int64_t x = 0; x < nk; ++x)

@@ -16,6 +16,7 @@ struct FoldInput {
   const float* val;
   double theta_h, eps, c_cap, alpha, beta, clip, p_best, rho;
   double kappa_fixed;  // >= 0 replaces eq. (14)
+  uint8_t* evid_gt1;   // optional output, [n][k]: 1 where e > 1 (eq. 11)
 };
 
 struct FoldOutput {

@@ -53,6 +53,8 @@ struct HostInst {
   double l_nn;
   InstDesc d;  // device pointers
   std::vector<int32_t> cand_h;  // host copy, used by the fold
+  bool want_evid = false;         // keep the fold's e > 1 flags (diagnostics)
+  std::vector<uint8_t> evid_gt1;
   // inputs that already live in device memory are copied device-to-device
   bool from_device = false;
   hac_instance dev_inst{};

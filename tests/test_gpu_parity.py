@@ -274,3 +274,36 @@ def test_every_ant_block_waves(ctx, waves, monkeypatch):
     print(f"case every-ant 2-opt, {waves} waves per block", flush=True)
     _same(ctx.decode(inst), oracle.decode(inst), f"waves {waves}")
     _state_parity(ctx, inst)
+
+
+@pytest.mark.parametrize("which", ["tsp500", "atsp1000", "empty", "scope1"])
+def test_heatmap_diagnostics(ctx, which):
+    """Section V diagnostics through the C ABI equal the oracle's, against
+    the oracle's NN tour and against a decoded tour."""
+    over = {}
+    if which == "tsp500":
+        inst = wl.tsp500(iterations=5)
+    elif which == "atsp1000":
+        inst = wl.serve_request("atsp1000", 4, iterations=5)
+    elif which == "empty":
+        inst = wl.random_instance(60, seed=8, heat="empty", k=8, ants=6, iterations=5)
+    else:
+        inst = wl.random_instance(90, seed=11, k=6, ants=6, iterations=5)
+        over = dict(baseline_scope=1)
+    print(f"case diagnostics {which}", flush=True)
+    st, t, L, info = oracle.decode(inst, state=True, **over)
+    for tour in (info["nn_tour"], t):
+        got = ctx.diagnostics(inst, tour, **over)
+        want = oracle.diagnostics(inst, tour, **over)
+        assert got == want, (got, want)
+    if which == "empty":
+        assert want["entries"] == 0 and want["coverage"] == 0.0 and want["evidence_slots"] == 0
+
+
+def test_heatmap_diagnostics_rejects_bad_tours(ctx):
+    import paper_2601_19041_amd as hac
+    inst = wl.random_instance(30, seed=3)
+    for bad in ([0] * 30, list(range(29)) + [30]):
+        with pytest.raises(hac.HacError) as e:
+            ctx.diagnostics(inst, bad)
+        assert e.value.status == hac.HAC_EINVAL
