@@ -138,7 +138,7 @@ Layout make_layout(const hac_instance* inst, const hac_csr* csr, const hac_param
   Layout L;
   L.n = inst->n;
   L.k = std::min(p->k, inst->n - 1);
-  L.kg = std::min(inst->n - 1, 32);
+  L.kg = std::min(inst->n - 1, 64);
   L.kls = p->local_search ? std::min(p->k_ls, inst->n - 1) : 0;
   L.ants = p->ants;
   L.iterations = p->iterations;

@@ -6,7 +6,7 @@
 //   heur  f32  [n][k]   S = eta^beta e^kappa (folded on the host)
 //   tau   f32  [n][k]   pheromone on candidate edges only
 //   w     f32  [n][k]   choice weights tau * S (rewritten by every update)
-//   geo   int32[n][kg]  geometric nearest neighbours, kg = min(n-1, 32)
+//   geo   int32[n][kg]  geometric nearest neighbours, kg = min(n-1, 64)
 //
 // Numerical contract: this file is compiled with -ffp-contract=off and
 // without fast-math, so every FP32/FP64 expression rounds exactly as
@@ -1074,7 +1074,7 @@ __device__ __forceinline__ int geo_first_unvisited(const HAC_AS1 int32_t* geo, i
 // a first lane is needed).  The lane of the chosen slot marks the visited
 // bit with the bitset word it has just read.
 //
-// Exhausted rows look up their geometric list (the kg <= 32 nearest nodes
+// Exhausted rows look up their geometric list (the kg <= 64 nearest nodes
 // in (distance, index) order, so the first unvisited entry is the answer)
 // inside their own row; rows whose list is exhausted as well run a
 // wave-wide scan of all nodes, one row after another.
@@ -1190,7 +1190,9 @@ struct AntRows {
     // the geometric list of the current node, needed only if the row is
     // exhausted: loaded now so that its latency hides behind the step
     const uint32_t go = __umul24((uint32_t)cur, (uint32_t)kg);
-    const int ga = geo[go + (uint32_t)min(2 * u, kg - 1)], gb = geo[go + (uint32_t)min(2 * u + 1, kg - 1)];
+    int gl[4];  // entries 4u .. 4u + 3 of the list
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gl[q] = geo[go + (uint32_t)min(4 * u + q, kg - 1)];
     int c[S];
     uint32_t wb[S], mk[S], vw[S], bit[S];
     // t = 150 - (biased exponent), plus 512 once the slot's node is visited
@@ -1274,24 +1276,25 @@ struct AntRows {
     }
     const bool exhausted = sh >= 256;
     if (__builtin_amdgcn_ballot_w64(exhausted)) {
-      j = fallback(exhausted, j, ga, gb);
+      j = fallback(exhausted, j, gl);
       if (exhausted) set_row(__umul24((uint32_t)j, k8));
     }
     --left;
     return j;
   }
 
-  __device__ __forceinline__ int fallback(bool exhausted, int j, int id0, int id1) {
+  __device__ __forceinline__ int fallback(bool exhausted, int j, const int (&gl)[4]) {
     int jg = -1;
-    if (exhausted) {  // whole rows: the geometric list, two entries per lane
-      const bool v0 = visited(vis_g, id0), v1 = visited(vis_g, id1);  // ids are valid in every lane
-      const bool o0 = (2 * u < kg) & !v0;
-      const bool o1 = (2 * u + 1 < kg) & !v1;
-      const uint64_t bm = __builtin_amdgcn_ballot_w64(o0 | o1);
+    if (exhausted) {  // whole rows: the geometric list, four entries per lane
+      bool o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = (4 * u + q < kg) & !visited(vis_g, gl[q]);  // ids are valid in every lane
+      const uint64_t bm = __builtin_amdgcn_ballot_w64(o[0] | o[1] | o[2] | o[3]);
       const uint32_t field = (uint32_t)(bm >> (16 * g)) & 0xffffu;
       if (field) {
         const int f = (int)__builtin_ctz(field);
-        jg = (int)row_reduce(u == f ? (uint32_t)(o0 ? id0 : id1) : 0u, OpOr());
+        const int first = o[0] ? gl[0] : (o[1] ? gl[1] : (o[2] ? gl[2] : gl[3]));
+        jg = (int)row_reduce(u == f ? (uint32_t)first : 0u, OpOr());
       }
     }
     // live rows still without a node: wave-wide scans, one row at a time
