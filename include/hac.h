@@ -130,7 +130,8 @@ typedef struct hac_stats {
   int32_t lds_staged;             /* candidate table: 0 read from global    */
                                   /* memory; staged in LDS as 1 8-byte      */
                                   /* {id, weight} entries, 2 uint16 ids and */
-                                  /* FP32 weights                           */
+                                  /* FP32 weights, 3 the same without the   */
+                                  /* coordinates                            */
   int32_t ants_per_wave;          /* 1-4 ants per wave, 16 lanes each       */
   int32_t byte_marks;             /* 1: visited marks are bytes, 0: bits    */
 } hac_stats;

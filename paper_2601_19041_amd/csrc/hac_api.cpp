@@ -534,7 +534,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     // independence): A ants per block, rows (1..4, default 4) ants per wave
     LaunchShape sh{1, 0, kmax, 4, 0};
     const int got = std::sscanf(force, "%d,%d,%d", &sh.ants_per_block, &sh.staged, &sh.rows_per_wave);
-    if (got >= 2 && sh.ants_per_block >= 1 && sh.staged >= 0 && sh.staged <= 2) {
+    if (got >= 2 && sh.ants_per_block >= 1 && sh.staged >= 0 && sh.staged <= 3) {
       if (got < 3 || sh.rows_per_wave < 1 || sh.rows_per_wave > 4) sh.rows_per_wave = 4;
       sh = with_marks(hs, sh);
       if (const char* bits = std::getenv("HAC_BIT_MARKS")) {
@@ -557,7 +557,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
   std::vector<LaunchShape> cands;
   for (int rpw : {4, 2, 1})
     for (int waves : {1, 2, 4, 8, 16})
-      for (int st : {0, 1, 2}) {
+      for (int st : {0, 1, 2, 3}) {
         const LaunchShape sh = with_marks(hs, {rpw * waves, st, kmax, rpw, 0});
         if (shape_fits(hs, sh)) cands.push_back(sh);
       }

@@ -123,7 +123,8 @@ struct ConstructLds {
 __host__ __device__ inline size_t staged_ids_bytes(int32_t n, int32_t k) {
   return (((size_t)n * k * 2 + 15) / 16) * 16;
 }
-// staged: 0 none, 1 8-byte {id, weight} entries, 2 uint16 ids + FP32 weights
+// staged: 0 none, 1 8-byte {id, weight} entries, 2 uint16 ids + FP32 weights,
+// 3 as 2 without the coordinates
 __host__ __device__ inline ConstructLds construct_lds_layout(int32_t n, int32_t k, int32_t ants_per_block,
                                                              int32_t rows_per_wave, int32_t staged, bool lists,
                                                              bool bytes) {
@@ -137,6 +138,7 @@ __host__ __device__ inline ConstructLds construct_lds_layout(int32_t n, int32_t 
   // staged table (8-byte entries, or uint16 ids then FP32 weights), then the coordinates
   if (staged == 1) total += (((size_t)n * k * 8 + 15) / 16) * 16 + (size_t)16 * n;
   if (staged == 2) total += staged_ids_bytes(n, k) + (((size_t)n * k * 4 + 15) / 16) * 16 + (size_t)16 * n;
+  if (staged == 3) total += staged_ids_bytes(n, k) + (((size_t)n * k * 4 + 15) / 16) * 16;
   L.total = total;
   return L;
 }

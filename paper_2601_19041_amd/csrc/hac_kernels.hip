@@ -1120,7 +1120,8 @@ constexpr int kListScanMax = 1024;
 
 // STAGED: 0 the candidate table is read from global memory; 1 it is copied
 // to LDS as 8-byte {id, weight} entries; 2 as uint16 ids and FP32 weights
-// (six bytes per slot, for tables that do not fit as 8-byte entries).
+// (six bytes per slot, for tables that do not fit as 8-byte entries); 3 as
+// in 2 but without the coordinates, which leaves room for unvisited lists.
 template <int STAGED, int S, bool BYTES>
 struct AntRows {
   int n, k, kg, u, g;
@@ -1165,7 +1166,7 @@ struct AntRows {
   __device__ __forceinline__ uint64_t entry(uint32_t a) const {
     if constexpr (STAGED == 1) {
       return *reinterpret_cast<const __attribute__((address_space(3))) uint64_t*>((uintptr_t)a);
-    } else if constexpr (STAGED == 2) {
+    } else if constexpr (STAGED >= 2) {
       // the id (uint16) at a and its weight (FP32) at 2a + w_from_id
       const uint32_t id = *reinterpret_cast<const __attribute__((address_space(3))) uint16_t*>((uintptr_t)a);
       const uint32_t wb = *reinterpret_cast<const __attribute__((address_space(3))) uint32_t*>(
@@ -1368,12 +1369,12 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const double2* xy_lds = nullptr;
   // words of the staged table before the coordinates, and of its id part
-  const uint32_t ids_words = STAGED == 2 ? (uint32_t)(staged_ids_bytes(n, k) / 4) : 0u;
-  const uint32_t table_words = STAGED == 2 ? ids_words + (uint32_t)((((size_t)n * k * 4 + 15) / 16) * 4)
+  const uint32_t ids_words = STAGED >= 2 ? (uint32_t)(staged_ids_bytes(n, k) / 4) : 0u;
+  const uint32_t table_words = STAGED >= 2 ? ids_words + (uint32_t)((((size_t)n * k * 4 + 15) / 16) * 4)
                                            : (uint32_t)((((size_t)n * k * 8 + 15) / 16) * 4);
   if (STAGED) {
     const HAC_AS1 uint64_t* src = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.cw));
-    if constexpr (STAGED == 2) {
+    if constexpr (STAGED >= 2) {
       // the {id, weight} table, split into uint16 ids and FP32 weights
       uint16_t* dst_id = reinterpret_cast<uint16_t*>(lds + staged_off);
       uint32_t* dst_w = lds + staged_off + ids_words;
@@ -1389,7 +1390,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
       const int vec = (n * k * 8 + 15) / 16;
       for (int x = threadIdx.x; x < vec; x += blockDim.x) dst[x] = src4[x];
     }
-    if (I.xy) {
+    if (STAGED != 3 && I.xy) {
       u32x4* dxy = reinterpret_cast<u32x4*>(lds + staged_off + table_words);
       const HAC_AS1 u32x4* sxy = reinterpret_cast<const HAC_AS1 u32x4*>(as_global(I.xy));
       for (int x = threadIdx.x; x < n; x += blockDim.x) dxy[x] = sxy[x];
@@ -1412,7 +1413,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   // and writing nothing, so only live rows need LDS
   const int ant = A.live ? bm.ant0 + row : first_ant;
   A.cw_g = reinterpret_cast<const HAC_AS1 char*>(as_global(I.cw));
-  A.k8 = (STAGED == 2 ? 2u : 8u) * (uint32_t)k;
+  A.k8 = (STAGED >= 2 ? 2u : 8u) * (uint32_t)k;
   // LDS addresses of the staged ids and weights
   const uint32_t table_at =
       (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t*)(lds + staged_off);
@@ -1422,7 +1423,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int slot = S * A.u + s;
-    A.lane_off[s] = (STAGED == 2 ? 2u : 8u) * (uint32_t)min(slot, k - 1) + (STAGED ? table_at : 0u);
+    A.lane_off[s] = (STAGED >= 2 ? 2u : 8u) * (uint32_t)min(slot, k - 1) + (STAGED ? table_at : 0u);
     A.t_base[s] = slot < k ? 150 : 150 + 1024;
     A.vmask[s] = slot < k ? 0xffffffffu : 0u;
     // opaque to the optimiser, so that the masking stays plain ALU work off
@@ -1982,8 +1983,10 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
     else if (S == 2) HAC_LAUNCH(ST, 2, BY); \
     else HAC_LAUNCH(ST, 4, BY);          \
   }
-  if (staged < 0 || staged > 2) return hipErrorInvalidValue;
-  if (staged == 2) {
+  if (staged < 0 || staged > 3) return hipErrorInvalidValue;
+  if (staged == 3) {
+    if (bytes) HAC_LAUNCH_S(3, true) else HAC_LAUNCH_S(3, false)
+  } else if (staged == 2) {
     if (bytes) HAC_LAUNCH_S(2, true) else HAC_LAUNCH_S(2, false)
   } else if (staged == 1) {
     if (bytes) HAC_LAUNCH_S(1, true) else HAC_LAUNCH_S(1, false)

@@ -151,14 +151,15 @@ def test_paper1000_packed_staging(ctx, monkeypatch):
     insts = wl.paper_budget(1000, count=16, iterations=10)
     print("case paper1000 tuned", flush=True)
     tuned = ctx.decode_batch(insts)
-    monkeypatch.setenv("HAC_SHAPE", "16,2,4")
-    print("case paper1000 16,2,4", flush=True)
-    forced = ctx.decode_batch(insts)
-    assert ctx.stats()["lds_staged"] == 2
-    for x in (0, 9, 15):
-        _check(forced[x], insts[x])
-    for x in range(len(insts)):
-        assert np.array_equal(tuned[x][0], forced[x][0]) and tuned[x][1] == forced[x][1]
+    for shape, staged in (("16,2,4", 2), ("16,3,4", 3)):
+        monkeypatch.setenv("HAC_SHAPE", shape)
+        print(f"case paper1000 {shape}", flush=True)
+        forced = ctx.decode_batch(insts)
+        assert ctx.stats()["lds_staged"] == staged
+        for x in (0, 9, 15):
+            _check(forced[x], insts[x])
+        for x in range(len(insts)):
+            assert np.array_equal(tuned[x][0], forced[x][0]) and tuned[x][1] == forced[x][1]
 
 
 def test_beyond_uint16_node_ids(ctx):
