@@ -33,6 +33,8 @@ def _mix():
         out.append(wl.random_instance(60 + 37 * x, seed=200 + x, k=8 + x, ants=6 + x, iterations=10 + 3 * x))
     out.append(wl.random_instance(80, seed=300, kind="matrix", symmetric=False, k=9, ants=7, iterations=14))
     out.append(wl.random_instance(120, seed=301, k=10, ants=8, iterations=9, local_search=1, k_ls=10))
+    # 2-opt on every ant's tour (its work area is per ant)
+    out.append(wl.random_instance(140, seed=303, k=10, ants=6, iterations=8, local_search=2, k_ls=10))
     out.append(wl.random_instance(1, seed=302))
     return out
 
@@ -105,3 +107,20 @@ def test_cancel_and_oversize(ctx, hac):
         srv.submit(huge)
     assert e.value.status == hac.HAC_ENOMEM
     srv.close()
+
+
+def test_served_ablation_settings_equal_alone(ctx, hac):
+    """Requests with the fixed-kappa ablation and a c_cap of the sweep are
+    served with their own parameters, beside default ones."""
+    inst = wl.random_instance(110, seed=310, k=8, ants=6, iterations=10)
+    overs = [{}, dict(kappa_fixed=1.0), dict(c_cap=0.125), dict(kappa_fixed=0.0)]
+    alone = [ctx.decode(inst, **o) for o in overs]
+    print("case serve ablation", flush=True)
+    srv = hac.Server(ctx, budget=1 << 30, max_slots=4)
+    tickets = [srv.submit(inst, **o) for o in overs]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for x, o in enumerate(overs):
+        assert np.array_equal(res[x][0], alone[x][0]) and res[x][1] == alone[x][1], o
+        st, ot, ol, _ = oracle.decode(inst, **o)
+        assert np.array_equal(res[x][0], ot), o
