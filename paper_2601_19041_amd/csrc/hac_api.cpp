@@ -554,10 +554,18 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
       if (shape_fits(hs, sh)) return sh;
     }
   }
+  // Staging forms tried: the table in global memory, and 8-byte entries in
+  // LDS, or where those do not fit in any shape, the two packed forms (the
+  // packed read costs a little more than one 8-byte read, so 8-byte entries
+  // win wherever they fit).
+  bool fits8 = false;
+  for (int rpw : {4, 2, 1})
+    for (int waves : {1, 2, 4, 8, 16}) fits8 |= shape_fits(hs, with_marks(hs, {rpw * waves, 1, kmax, rpw, 0}));
+  std::vector<int> forms = fits8 ? std::vector<int>{0, 1} : std::vector<int>{0, 2, 3};
   std::vector<LaunchShape> cands;
   for (int rpw : {4, 2, 1})
     for (int waves : {1, 2, 4, 8, 16})
-      for (int st : {0, 1, 2, 3}) {
+      for (int st : forms) {
         const LaunchShape sh = with_marks(hs, {rpw * waves, st, kmax, rpw, 0});
         if (shape_fits(hs, sh)) cands.push_back(sh);
       }
