@@ -298,15 +298,15 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   int32_t max_n = 0;
   for (auto& h : hs) max_n = std::max(max_n, h.lay.n);
   // candidate and geometric lists (eq. 3)
-  for (int x = 0; x < count; ++x) HAC_HIP(launch_candidates(d_descs, x, hs[x].lay.n, s));
-  std::vector<std::vector<int32_t>> geo0(count);
+  HAC_HIP(launch_candidates(d_descs, count, max_n, s));
+  std::vector<std::vector<int32_t>> nn1(count);  // each node's nearest neighbour
   for (int x = 0; x < count; ++x) {
     HostInst& h = hs[x];
     const size_t nk = (size_t)h.lay.n * h.lay.k;
     h.cand_h.resize(nk);
-    geo0[x].resize((size_t)h.lay.n * h.lay.kg);
+    nn1[x].resize((size_t)h.lay.n);
     HAC_HIP(hipMemcpyAsync(h.cand_h.data(), h.d.cand, 4 * nk, hipMemcpyDeviceToHost, s));
-    HAC_HIP(hipMemcpyAsync(geo0[x].data(), h.d.geo, 4 * geo0[x].size(), hipMemcpyDeviceToHost, s));
+    HAC_HIP(hipMemcpyAsync(nn1[x].data(), h.d.succ, 4 * (size_t)h.lay.n, hipMemcpyDeviceToHost, s));
   }
   HAC_HIP(hipStreamSynchronize(s));
   // host fold (eq. 9-14)
@@ -346,7 +346,7 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
     // lower bound on any tour: every node leaves once, at least to its nearest
     double lb = 0.0;
     for (int32_t i = 0; i < L.n; ++i) {
-      const int32_t j = geo0[x][(size_t)i * L.kg];
+      const int32_t j = nn1[x][(size_t)i];
       if (in.coords) {
         const double dx = in.coords[2 * i] - in.coords[2 * j];
         const double dy = in.coords[2 * i + 1] - in.coords[2 * j + 1];

@@ -89,7 +89,9 @@ struct BlockMap {
 };
 
 // ---- launchers (defined in hac_kernels.hip) ----
-hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s);
+// candidate and geometric lists of every instance (and each node's nearest
+// neighbour, in the successor array)
+hipError_t launch_candidates(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
 hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
 // 2-opt launches: all_coords = 1 when every instance of the batch has
 // coordinates (the FP32-filtered LDS mode needs them)

@@ -271,8 +271,9 @@ __device__ void topk_offer(WaveTopK& t, double key, int id, bool valid) {
   }
 }
 
-__global__ void __launch_bounds__(256) candidates_kernel(const InstDesc* insts, int inst) {
-  const InstDesc& D = insts[inst];
+// One launch for a whole batch: blockIdx.y is the instance.
+__global__ void __launch_bounds__(256) candidates_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.y];
   const int n = D.n, k = D.k, kg = D.kg, lane = lane_id();
   const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
   if (i >= n) return;
@@ -321,6 +322,9 @@ __global__ void __launch_bounds__(256) candidates_kernel(const InstDesc* insts, 
   if (lane < s) out[rank_s] = sup.id;
   if (lane < need) out[rank_f] = fill.id;
   if (lane < kg) D.geo[(int64_t)i * kg + lane] = geo.id;
+  // each node's nearest neighbour, for the host's lower bound on a tour;
+  // the successor array holds it until the first update overwrites it
+  if (lane == 0) D.succ[i] = geo.id;
 }
 
 // Visited tests over an ant's two representations: one bit per node, or
@@ -1801,10 +1805,10 @@ size_t construct_lds_bytes(int32_t n, int32_t k, int32_t ants_per_block, int32_t
   return construct_lds_layout(n, k, ants_per_block, rows_per_wave, staged, false, false).total;
 }
 
-hipError_t launch_candidates(const InstDesc* d_insts, int32_t inst, int32_t n, hipStream_t s) {
+hipError_t launch_candidates(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s) {
   const int waves = 4;
-  hipLaunchKernelGGL(candidates_kernel, dim3((n + waves - 1) / waves), dim3(waves * WAVE), 0, s,
-                     d_insts, inst);
+  hipLaunchKernelGGL(candidates_kernel, dim3((max_n + waves - 1) / waves, count), dim3(waves * WAVE), 0, s,
+                     d_insts);
   return hipGetLastError();
 }
 
