@@ -1699,18 +1699,40 @@ __global__ void __launch_bounds__(1024) iter_end_kernel(const InstDesc* insts) {
   const float tmax_f = s_tmax, tmin_f = s_tmin;
   const int nk = n * k;
   const bool sym = D.sym != 0;
-  for (int x = tid; x < nk; x += nthr) {
-    const int i = x / k;
-    const int j = D.cand[x];
-    const bool on = j == D.succ[i] || (sym && j == D.pred[i]);
-    float v = keep * D.tau[x];
-    v = v + (on ? delta : 0.0f);
-    v = fmaxf(tmin_f, v);
-    v = fminf(tmax_f, v);
-    const float w = v * D.heur[x];
-    D.tau[x] = v;
-    D.w[x] = w;
-    D.cw[x].y = __float_as_uint(w);
+  // four slots per thread per pass, their inputs loaded before any store so
+  // that the loads of the four are in flight together (each slot is
+  // computed on its own, exactly as written above)
+  constexpr int U = 4;
+  for (int x0 = tid; x0 < nk; x0 += U * nthr) {
+    int jv[U], sv[U], pv[U];
+    float tv[U], hv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = x0 + u * nthr;
+      if (x < nk) {
+        const int i = x / k;
+        jv[u] = D.cand[x];
+        sv[u] = D.succ[i];
+        pv[u] = D.pred[i];
+        tv[u] = D.tau[x];
+        hv[u] = D.heur[x];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = x0 + u * nthr;
+      if (x < nk) {
+        const bool on = jv[u] == sv[u] || (sym && jv[u] == pv[u]);
+        float v = keep * tv[u];
+        v = v + (on ? delta : 0.0f);
+        v = fmaxf(tmin_f, v);
+        v = fminf(tmax_f, v);
+        const float w = v * hv[u];
+        D.tau[x] = v;
+        D.w[x] = w;
+        D.cw[x].y = __float_as_uint(w);
+      }
+    }
   }
 
   // branching-factor restart
