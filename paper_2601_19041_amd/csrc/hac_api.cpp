@@ -636,6 +636,7 @@ struct hac_ctx {
   hac_stats stats{};
   bool timing = false;
   DeviceArena arena, scratch;
+  DeviceArena stage;  // gathered inputs and copy lists of the device-input path
   std::vector<HostInst> last;  // descriptors of the last call (debug hooks)
   std::vector<hipEvent_t> events;
 };
@@ -719,6 +720,7 @@ void hac_destroy(hac_ctx* c) {
   for (auto e : c->events) (void)hipEventDestroy(e);
   c->arena.release();
   c->scratch.release();
+  c->stage.release();
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -759,48 +761,80 @@ static double ms_since(Clock::time_point t0) {
 // out_dev: per-instance device tour pointers (or null: results to host)
 // Host copies of inputs that live in device memory: validation and the
 // evidence fold read them on the host.
-struct Mirror {
-  std::vector<double> xy, dm;
-  std::vector<int32_t> rp, col;
-  std::vector<float> val;
-};
-
+// Inputs that live in device memory are also needed on the host (the
+// validation and the evidence fold read them).  Every array of every
+// instance is gathered into one staging buffer by one copy kernel and
+// brought back with one copy; hi / hc then point into `blob`.
 hac_status mirror_inputs(hac_ctx* c, int32_t count, const hac_instance* insts, const hac_csr* csrs,
-                         std::vector<Mirror>& mir, std::vector<hac_instance>& hi,
-                         std::vector<hac_csr>& hc) {
-  mir.resize(count);
+                         std::vector<char>& blob, std::vector<hac_instance>& hi, std::vector<hac_csr>& hc) {
   hi.assign(insts, insts + count);
   hc.assign(csrs, csrs + count);
+  std::vector<CopyItem> items;
+  std::vector<size_t> at;
+  size_t total = 0;
+  uint64_t maxb = 0;
+  auto add = [&](const void* src, size_t bytes) {
+    items.push_back(CopyItem{src, nullptr, (uint64_t)bytes});
+    at.push_back(total);
+    total += align256(bytes);
+    maxb = std::max<uint64_t>(maxb, bytes);
+    return at.back();
+  };
+  struct Off {
+    size_t geo, rp, col, val;
+  };
+  std::vector<Off> off(count);
   for (int32_t x = 0; x < count; ++x) {
     const int32_t n = insts[x].n;
     if (n < 1 || n > HAC_MAX_N || csrs[x].n != n || csrs[x].nnz < 0 || !csrs[x].row_ptr)
       return set_err(c, HAC_EINVAL, "instance " + std::to_string(x) + ": bad sizes");
-    Mirror& m = mir[x];
     if (insts[x].kind == HAC_COORDS_EUC2D) {
       if (!insts[x].coords) return set_err(c, HAC_EINVAL, "coords missing");
-      m.xy.resize(2 * (size_t)n);
-      CTX_HIP(hipMemcpyAsync(m.xy.data(), insts[x].coords, 16 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
-      hi[x].coords = m.xy.data();
+      off[x].geo = add(insts[x].coords, 16 * (size_t)n);
     } else {
       if (!insts[x].dist) return set_err(c, HAC_EINVAL, "distance matrix missing");
-      m.dm.resize((size_t)n * n);
-      CTX_HIP(hipMemcpyAsync(m.dm.data(), insts[x].dist, 8 * (size_t)n * n, hipMemcpyDeviceToHost, c->stream));
-      hi[x].dist = m.dm.data();
+      off[x].geo = add(insts[x].dist, 8 * (size_t)n * n);
     }
-    m.rp.resize(n + 1);
-    m.col.resize(std::max(csrs[x].nnz, 1));
-    m.val.resize(std::max(csrs[x].nnz, 1));
-    CTX_HIP(hipMemcpyAsync(m.rp.data(), csrs[x].row_ptr, 4 * (size_t)(n + 1), hipMemcpyDeviceToHost, c->stream));
+    off[x].rp = add(csrs[x].row_ptr, 4 * (size_t)(n + 1));
+    off[x].col = off[x].val = 0;
     if (csrs[x].nnz > 0) {
       if (!csrs[x].col || !csrs[x].val) return set_err(c, HAC_EINVAL, "col/val missing");
-      CTX_HIP(hipMemcpyAsync(m.col.data(), csrs[x].col, 4 * (size_t)csrs[x].nnz, hipMemcpyDeviceToHost, c->stream));
-      CTX_HIP(hipMemcpyAsync(m.val.data(), csrs[x].val, 4 * (size_t)csrs[x].nnz, hipMemcpyDeviceToHost, c->stream));
+      off[x].col = add(csrs[x].col, 4 * (size_t)csrs[x].nnz);
+      off[x].val = add(csrs[x].val, 4 * (size_t)csrs[x].nnz);
     }
-    hc[x].row_ptr = m.rp.data();
-    hc[x].col = m.col.data();
-    hc[x].val = m.val.data();
   }
-  CTX_HIP(hipStreamSynchronize(c->stream));
+  const size_t data = total;
+  const size_t list_at = total;
+  total += align256(sizeof(CopyItem) * items.size());
+  {
+    hipError_t e = c->stage.reserve(total);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return set_err(c, HAC_ENOMEM, "device memory");
+    CTX_HIP(e);
+  }
+  char* d = (char*)c->stage.carve(total);
+  for (size_t q = 0; q < items.size(); ++q) items[q].dst = d + at[q];
+  hipStream_t s = c->stream;
+  CTX_HIP(hipMemcpyAsync(d + list_at, items.data(), sizeof(CopyItem) * items.size(), hipMemcpyHostToDevice, s));
+  hipError_t ke = launch_copy_items((const CopyItem*)(d + list_at), (int32_t)items.size(), maxb, s);
+  if (ke == hipErrorInvalidValue) {  // an item too large for one launch: copy them one by one
+    ke = hipSuccess;
+    for (size_t q = 0; q < items.size() && ke == hipSuccess; ++q)
+      ke = hipMemcpyAsync(items[q].dst, items[q].src, items[q].bytes, hipMemcpyDeviceToDevice, s);
+  }
+  CTX_HIP(ke);
+  blob.resize(std::max<size_t>(data, 16));
+  CTX_HIP(hipMemcpyAsync(blob.data(), d, data, hipMemcpyDeviceToHost, s));
+  CTX_HIP(hipStreamSynchronize(s));
+  for (int32_t x = 0; x < count; ++x) {
+    char* b = blob.data();
+    if (insts[x].kind == HAC_COORDS_EUC2D)
+      hi[x].coords = (const double*)(b + off[x].geo);
+    else
+      hi[x].dist = (const double*)(b + off[x].geo);
+    hc[x].row_ptr = (const int32_t*)(b + off[x].rp);
+    hc[x].col = (const int32_t*)(b + off[x].col);
+    hc[x].val = (const float*)(b + off[x].val);
+  }
   return HAC_OK;
 }
 
@@ -812,7 +846,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   c->stats = hac_stats{};
   if (count < 1 || !insts_in || !csrs_in || !params || !seeds || !tours_out || !lengths_out)
     return set_err(c, HAC_EINVAL, "null or empty batch");
-  std::vector<Mirror> mir;
+  std::vector<char> mir;
   std::vector<hac_instance> hi;
   std::vector<hac_csr> hc;
   if (inputs_on_device) {
@@ -868,12 +902,42 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   int32_t** d_out_ptrs = m ? (int32_t**)c->arena.carve(sizeof(int32_t*) * m) : nullptr;
   double* d_out_lens = m ? (double*)c->arena.carve(8 * (size_t)m) : nullptr;
   std::vector<int32_t*> out_ptrs(m);
+  std::vector<CopyItem> up;  // device-resident inputs, gathered in one launch
   for (int32_t y = 0; y < m; ++y) {
     HostInst& h = hs[y];
     assign_slot(h, [&](size_t b) { return c->arena.carve(b); });
     fill_desc_scalars(h);
     out_ptrs[y] = outputs_on_device ? tours_out[which[y]] : (int32_t*)c->arena.carve(4 * (size_t)h.lay.n);
-    CTX_HIP(upload_inputs(h, s));
+    if (h.from_device) {
+      // the caller's device arrays, gathered into the slot below
+      const Layout& L = h.lay;
+      const size_t nn = (size_t)L.n;
+      if (L.coords)
+        up.push_back(CopyItem{h.dev_inst.coords, (void*)h.d.xy, 16 * nn});
+      else
+        up.push_back(CopyItem{h.dev_inst.dist, (void*)h.d.dist, 8 * nn * nn});
+      up.push_back(CopyItem{h.dev_csr.row_ptr, (void*)h.d.row_ptr, 4 * (nn + 1)});
+      if (L.nnz > 0) {
+        up.push_back(CopyItem{h.dev_csr.col, (void*)h.d.col, 4 * (size_t)L.nnz});
+        up.push_back(CopyItem{h.dev_csr.val, (void*)h.d.val, 4 * (size_t)L.nnz});
+      }
+    } else {
+      CTX_HIP(upload_inputs(h, s));
+    }
+  }
+  if (!up.empty()) {
+    uint64_t maxb = 0;
+    for (auto& it : up) maxb = std::max<uint64_t>(maxb, it.bytes);
+    CTX_HIP(c->stage.reserve(align256(sizeof(CopyItem) * up.size())));
+    CopyItem* d_up = (CopyItem*)c->stage.carve(sizeof(CopyItem) * up.size());
+    CTX_HIP(hipMemcpyAsync(d_up, up.data(), sizeof(CopyItem) * up.size(), hipMemcpyHostToDevice, s));
+    hipError_t ke = launch_copy_items(d_up, (int32_t)up.size(), maxb, s);
+    if (ke == hipErrorInvalidValue) {
+      ke = hipSuccess;
+      for (size_t q = 0; q < up.size() && ke == hipSuccess; ++q)
+        ke = hipMemcpyAsync(up[q].dst, up[q].src, up[q].bytes, hipMemcpyDeviceToDevice, s);
+    }
+    CTX_HIP(ke);
   }
   if (m > 0) {
     std::vector<InstDesc> descs(m);

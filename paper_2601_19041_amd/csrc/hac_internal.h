@@ -88,7 +88,18 @@ struct BlockMap {
   int32_t ant0;
 };
 
+// One device-to-device copy of a gather: bytes is a multiple of 4 and both
+// addresses are 4-byte aligned.
+struct CopyItem {
+  const void* src;
+  void* dst;
+  uint64_t bytes;
+};
+
 // ---- launchers (defined in hac_kernels.hip) ----
+// all items of a list (device memory) in one launch; max_bytes bounds the
+// largest item
+hipError_t launch_copy_items(const CopyItem* d_items, int32_t count, uint64_t max_bytes, hipStream_t s);
 // candidate and geometric lists of every instance (and each node's nearest
 // neighbour, in the successor array)
 hipError_t launch_candidates(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);

@@ -1981,6 +1981,28 @@ __global__ void __launch_bounds__(1024) grid_kernel(const InstDesc* insts) {
   }
 }
 
+// Gathers many device-to-device copies into one launch: blockIdx.x is the
+// item, blockIdx.y a 64 KiB chunk of it.
+__global__ void __launch_bounds__(256) copy_items_kernel(const CopyItem* items) {
+  const CopyItem it = items[blockIdx.x];
+  const uint64_t words = it.bytes / 4;
+  const uint64_t beg = (uint64_t)blockIdx.y * 16384u;
+  if (beg >= words) return;
+  const uint64_t end = beg + 16384u < words ? beg + 16384u : words;
+  const HAC_AS1 uint32_t* src = as_global(static_cast<const uint32_t*>(it.src));
+  HAC_AS1 uint32_t* dst = as_global(static_cast<uint32_t*>(it.dst));
+  for (uint64_t w = beg + threadIdx.x; w < end; w += blockDim.x) dst[w] = src[w];
+}
+
+hipError_t launch_copy_items(const CopyItem* d_items, int32_t count, uint64_t max_bytes, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const uint64_t chunks = (max_bytes / 4 + 16383u) / 16384u;
+  if (chunks == 0) return hipSuccess;
+  if (chunks > 65535u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_items_kernel, dim3(count, (unsigned)chunks), dim3(256), 0, s, d_items);
+  return hipGetLastError();
+}
+
 hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s) {
   hipLaunchKernelGGL(grid_kernel, dim3(count), dim3(1024), 0, s, d_insts);
   return hipGetLastError();
