@@ -292,8 +292,40 @@ static void parallel_for(int count, const std::function<void(int)>& fn) {
   for (auto& t : pool) t.join();
 }
 
+// Moves many device arrays to or from one host blob through a staging
+// arena: one gather (or scatter) launch and one copy instead of a copy per
+// array.  `items` give the device side (src for a readback, dst for an
+// upload) and the host offsets; the staging regions follow `base`.
+static hipError_t stage_copies(DeviceArena& stage, std::vector<CopyItem>& items, const std::vector<size_t>& host_at,
+                               char* host, size_t bytes, bool to_host, hipStream_t s) {
+  const size_t list_bytes = sizeof(CopyItem) * items.size();
+  hipError_t e = stage.reserve(align256(bytes) + align256(list_bytes));
+  if (e != hipSuccess) return e;
+  char* base = (char*)stage.carve(bytes);
+  CopyItem* d_list = (CopyItem*)stage.carve(list_bytes);
+  uint64_t maxb = 0;
+  for (size_t q = 0; q < items.size(); ++q) {
+    if (to_host)
+      items[q].dst = base + host_at[q];
+    else
+      items[q].src = base + host_at[q];
+    maxb = std::max<uint64_t>(maxb, items[q].bytes);
+  }
+  if (!to_host && (e = hipMemcpyAsync(base, host, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_list, items.data(), list_bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  e = launch_copy_items(d_list, (int32_t)items.size(), maxb, s);
+  if (e == hipErrorInvalidValue) {  // an item too large for one launch
+    e = hipSuccess;
+    for (size_t q = 0; q < items.size() && e == hipSuccess; ++q)
+      e = hipMemcpyAsync(items[q].dst, items[q].src, items[q].bytes, hipMemcpyDeviceToDevice, s);
+  }
+  if (e != hipSuccess) return e;
+  if (to_host) e = hipMemcpyAsync(host, base, bytes, hipMemcpyDeviceToHost, s);
+  return e;
+}
+
 hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipStream_t s,
-                             std::string* err) {
+                             std::string* err, DeviceArena* stage) {
   const int count = (int)hs.size();
   int32_t max_n = 0;
   for (auto& h : hs) max_n = std::max(max_n, h.lay.n);
@@ -302,13 +334,37 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   std::vector<std::vector<int32_t>> nn1(count);  // each node's nearest neighbour
   for (int x = 0; x < count; ++x) {
     HostInst& h = hs[x];
-    const size_t nk = (size_t)h.lay.n * h.lay.k;
-    h.cand_h.resize(nk);
+    h.cand_h.resize((size_t)h.lay.n * h.lay.k);
     nn1[x].resize((size_t)h.lay.n);
-    HAC_HIP(hipMemcpyAsync(h.cand_h.data(), h.d.cand, 4 * nk, hipMemcpyDeviceToHost, s));
-    HAC_HIP(hipMemcpyAsync(nn1[x].data(), h.d.succ, 4 * (size_t)h.lay.n, hipMemcpyDeviceToHost, s));
   }
-  HAC_HIP(hipStreamSynchronize(s));
+  if (stage) {
+    std::vector<CopyItem> items;
+    std::vector<size_t> at;
+    size_t bytes = 0;
+    for (int x = 0; x < count; ++x) {
+      const HostInst& h = hs[x];
+      items.push_back(CopyItem{h.d.cand, nullptr, 4 * (uint64_t)h.cand_h.size()});
+      at.push_back(bytes);
+      bytes += align256(4 * h.cand_h.size());
+      items.push_back(CopyItem{h.d.succ, nullptr, 4 * (uint64_t)h.lay.n});
+      at.push_back(bytes);
+      bytes += align256(4 * (size_t)h.lay.n);
+    }
+    std::vector<char> blob(bytes);
+    HAC_HIP(stage_copies(*stage, items, at, blob.data(), bytes, true, s));
+    HAC_HIP(hipStreamSynchronize(s));
+    for (int x = 0; x < count; ++x) {
+      std::memcpy(hs[x].cand_h.data(), blob.data() + at[2 * x], 4 * hs[x].cand_h.size());
+      std::memcpy(nn1[x].data(), blob.data() + at[2 * x + 1], 4 * nn1[x].size());
+    }
+  } else {
+    for (int x = 0; x < count; ++x) {
+      HostInst& h = hs[x];
+      HAC_HIP(hipMemcpyAsync(h.cand_h.data(), h.d.cand, 4 * h.cand_h.size(), hipMemcpyDeviceToHost, s));
+      HAC_HIP(hipMemcpyAsync(nn1[x].data(), h.d.succ, 4 * (size_t)h.lay.n, hipMemcpyDeviceToHost, s));
+    }
+    HAC_HIP(hipStreamSynchronize(s));
+  }
   // host fold (eq. 9-14)
   std::vector<std::vector<float>> heur(count);
   std::vector<int> frc(count, FOLD_OK);
@@ -367,10 +423,26 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
       return HAC_ERANGE;
     }
   }
-  for (int x = 0; x < count; ++x) {
-    HostInst& h = hs[x];
-    const size_t nk = (size_t)h.lay.n * h.lay.k;
-    HAC_HIP(hipMemcpyAsync((void*)h.d.heur, heur[x].data(), 4 * nk, hipMemcpyHostToDevice, s));
+  std::vector<char> heur_blob;  // kept until the stream is synchronised below
+  if (stage) {
+    std::vector<CopyItem> items;
+    std::vector<size_t> at;
+    size_t bytes = 0;
+    for (int x = 0; x < count; ++x) {
+      const size_t nk = (size_t)hs[x].lay.n * hs[x].lay.k;
+      items.push_back(CopyItem{nullptr, (void*)hs[x].d.heur, 4 * (uint64_t)nk});
+      at.push_back(bytes);
+      bytes += align256(4 * nk);
+    }
+    heur_blob.resize(bytes);
+    for (int x = 0; x < count; ++x) std::memcpy(heur_blob.data() + at[x], heur[x].data(), items[x].bytes);
+    HAC_HIP(stage_copies(*stage, items, at, heur_blob.data(), bytes, false, s));
+  } else {
+    for (int x = 0; x < count; ++x) {
+      HostInst& h = hs[x];
+      const size_t nk = (size_t)h.lay.n * h.lay.k;
+      HAC_HIP(hipMemcpyAsync((void*)h.d.heur, heur[x].data(), 4 * nk, hipMemcpyHostToDevice, s));
+    }
   }
   // coordinate grids, NN tour (+ 2-opt), then the range check on the first bounds
   HAC_HIP(launch_grid(d_descs, count, s));
@@ -383,9 +455,24 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   }
   if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n, all_coords, s));
   std::vector<State> sts(count);
-  for (int x = 0; x < count; ++x)
-    HAC_HIP(hipMemcpyAsync(&sts[x], hs[x].d.st, sizeof(State), hipMemcpyDeviceToHost, s));
-  HAC_HIP(hipStreamSynchronize(s));
+  if (stage) {
+    // after the weights' scatter on the same stream: the staging arena is reused
+    std::vector<CopyItem> items;
+    std::vector<size_t> at;
+    for (int x = 0; x < count; ++x) {
+      items.push_back(CopyItem{hs[x].d.st, nullptr, sizeof(State)});
+      at.push_back((size_t)x * align256(sizeof(State)));
+    }
+    std::vector<char> blob((size_t)count * align256(sizeof(State)));
+    HAC_HIP(hipStreamSynchronize(s));
+    HAC_HIP(stage_copies(*stage, items, at, blob.data(), blob.size(), true, s));
+    HAC_HIP(hipStreamSynchronize(s));
+    for (int x = 0; x < count; ++x) std::memcpy(&sts[x], blob.data() + at[x], sizeof(State));
+  } else {
+    for (int x = 0; x < count; ++x)
+      HAC_HIP(hipMemcpyAsync(&sts[x], hs[x].d.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HAC_HIP(hipStreamSynchronize(s));
+  }
   for (int x = 0; x < count; ++x) {
     HostInst& h = hs[x];
     h.l_nn = sts[x].l_gb;
@@ -945,7 +1032,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     CTX_HIP(hipMemcpyAsync(d_descs, descs.data(), sizeof(InstDesc) * m, hipMemcpyHostToDevice, s));
     CTX_HIP(hipMemcpyAsync(d_out_ptrs, out_ptrs.data(), sizeof(int32_t*) * m, hipMemcpyHostToDevice, s));
     std::string err;
-    hac_status ps = prepare_instances(hs, d_descs, s, &err);
+    hac_status ps = prepare_instances(hs, d_descs, s, &err, &c->stage);
     if (ps != HAC_OK) return set_err(c, ps, err);
   }
   const double prep_ms = ms_since(t0);
@@ -1043,8 +1130,17 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   std::vector<State> sts(m);
   if (m > 0) {
     CTX_HIP(hipMemcpyAsync(lens.data(), d_out_lens, 8 * (size_t)m, hipMemcpyDeviceToHost, s));
-    for (int32_t y = 0; y < m; ++y)
-      CTX_HIP(hipMemcpyAsync(&sts[y], hs[y].d.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    // the final states, gathered into one readback
+    std::vector<CopyItem> items;
+    std::vector<size_t> at;
+    for (int32_t y = 0; y < m; ++y) {
+      items.push_back(CopyItem{hs[y].d.st, nullptr, sizeof(State)});
+      at.push_back((size_t)y * align256(sizeof(State)));
+    }
+    std::vector<char> blob((size_t)m * align256(sizeof(State)));
+    CTX_HIP(stage_copies(c->stage, items, at, blob.data(), blob.size(), true, s));
+    CTX_HIP(hipStreamSynchronize(s));
+    for (int32_t y = 0; y < m; ++y) std::memcpy(&sts[y], blob.data() + at[y], sizeof(State));
     if (!outputs_on_device)
       for (int32_t y = 0; y < m; ++y)
         CTX_HIP(hipMemcpyAsync(tours_out[which[y]], out_ptrs[y], 4 * (size_t)hs[y].lay.n,

@@ -100,8 +100,10 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
 
 // Prepares instances whose inputs are already uploaded into their slots:
 // candidates, host fold, NN tour (+2-opt), range checks, initialisation.
+// stage: when given, readbacks and uploads of the whole batch go through it
+// as one gather launch and one copy each, instead of a copy per array
 hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipStream_t s,
-                             std::string* err);
+                             std::string* err, DeviceArena* stage = nullptr);
 
 // Fills the device pointers of h.d from a carver (256-byte aligned pieces).
 void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve);
