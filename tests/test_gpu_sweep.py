@@ -1,0 +1,64 @@
+"""GPU parity over the random sweep cases: one mixed batch, each case alone,
+and all cases through the request server.  Every tour equals the oracle's
+and every length agrees within 1e-12 relative."""
+
+import numpy as np
+import pytest
+
+import oracle
+from _sweep import sweep_cases
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def hac():
+    import paper_2601_19041_amd as hac
+    return hac
+
+
+@pytest.fixture(scope="module")
+def ctx(hac):
+    c = hac.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def cases():
+    out = []
+    for inst, over in sweep_cases():
+        st, tour, L, _ = oracle.decode(inst, **over)
+        assert st == 0, inst.name
+        out.append((inst, over, tour, L))
+    return out
+
+
+def _same(got, ref_tour, ref_len, what):
+    tour, L = got[0], got[1]
+    assert np.array_equal(tour, ref_tour), f"{what}: tours differ at {np.flatnonzero(tour != ref_tour)[:5]}"
+    assert abs(L - ref_len) <= REL * max(ref_len, 1.0), (what, L, ref_len)
+
+
+def test_sweep_batch_and_alone(ctx, cases):
+    print(f"case sweep batch of {len(cases)}", flush=True)
+    got = ctx.decode_batch([c[0] for c in cases], [c[1] for c in cases])
+    for (inst, over, tour, L), g in zip(cases, got):
+        _same(g, tour, L, "batch " + inst.name)
+    for inst, over, tour, L in cases:
+        print(f"case sweep alone {inst.name}", flush=True)
+        _same(ctx.decode(inst, **over), tour, L, "alone " + inst.name)
+
+
+def test_sweep_served(hac, ctx, cases):
+    print(f"case sweep served {len(cases)}", flush=True)
+    srv = hac.Server(ctx, budget=1 << 30, max_slots=5)
+    try:
+        tickets = [srv.submit(inst, **over) for inst, over, _, _ in cases]
+        for t, (inst, over, tour, L) in zip(tickets, cases):
+            got = srv.wait(t)
+            _same(got, tour, L, "served " + inst.name)
+    finally:
+        srv.close()
