@@ -62,3 +62,27 @@ def test_sweep_served(hac, ctx, cases):
             _same(got, tour, L, "served " + inst.name)
     finally:
         srv.close()
+
+
+def test_sweep_device_inputs(hac, ctx, cases):
+    """hac_decode_batch_dev: inputs and outputs in device memory."""
+    print(f"case sweep device inputs {len(cases)}", flush=True)
+    b = hac.DeviceBatch([c[0] for c in cases], [c[1] for c in cases])
+    ctx.decode_batch_dev(b)
+    lens = b.lengths.cpu().numpy()
+    for x, (inst, over, tour, L) in enumerate(cases):
+        _same((b.tours[x].cpu().numpy(), float(lens[x])), tour, L, "device " + inst.name)
+
+
+@pytest.mark.parametrize("shape", ["2,0,1", "7,1,2", "12,2,4", "5,3,3", "16,1,4", "3,2,1"])
+def test_sweep_pinned_shapes(ctx, cases, shape, monkeypatch):
+    """The cases below the grid size in one batch at pinned launch shapes
+    (ants per block, LDS staging form, ants per wave)."""
+    small = [c for c in cases if c[0].n < 2048]
+    monkeypatch.setenv("HAC_SHAPE", shape)
+    print(f"case sweep shape {shape} ({len(small)} cases)", flush=True)
+    got = ctx.decode_batch([c[0] for c in small], [c[1] for c in small])
+    st = ctx.stats()
+    assert (st["ants_per_block"], st["lds_staged"], st["ants_per_wave"]) == tuple(map(int, shape.split(",")))
+    for (inst, over, tour, L), g in zip(small, got):
+        _same(g, tour, L, f"shape {shape} " + inst.name)
