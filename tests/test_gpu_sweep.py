@@ -86,3 +86,20 @@ def test_sweep_pinned_shapes(ctx, cases, shape, monkeypatch):
     assert (st["ants_per_block"], st["lds_staged"], st["ants_per_wave"]) == tuple(map(int, shape.split(",")))
     for (inst, over, tour, L), g in zip(small, got):
         _same(g, tour, L, f"shape {shape} " + inst.name)
+
+
+@pytest.mark.parametrize("env", [(("HAC_LS_MODE", "0"),), (("HAC_LS_MODE", "1"),), (("HAC_LS_WAVES", "3"),),
+                                 (("HAC_BIT_MARKS", "1"), ("HAC_SHAPE", "8,0,4"))],
+                         ids=["ls_global", "ls_lds_int32", "ls_3_waves", "bit_marks"])
+def test_sweep_pinned_variants(ctx, cases, env, monkeypatch):
+    """2-opt working arrays in global memory or as int32 in LDS, 2-opt blocks
+    of three waves, and bit visited marks: the tours do not change."""
+    use = [c for c in cases if c[0].n < 2048] if dict(env).get("HAC_SHAPE") else cases
+    for name, value in env:
+        monkeypatch.setenv(name, value)
+    print(f"case sweep {env} ({len(use)} cases)", flush=True)
+    got = ctx.decode_batch([c[0] for c in use], [c[1] for c in use])
+    if dict(env).get("HAC_BIT_MARKS"):
+        assert ctx.stats()["byte_marks"] == 0
+    for (inst, over, tour, L), g in zip(use, got):
+        _same(g, tour, L, f"{env} " + inst.name)
