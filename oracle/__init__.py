@@ -17,7 +17,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hac_oracle.c")
-_SO = os.path.join(_HERE, "liboracle.so")
+_SO_BUILT = os.path.join(_HERE, "liboracle.so")
+# HAC_ORACLE_LIB loads another build of the same source instead (the
+# mutation tests point it at copies with one planted mistake each)
+_SO = os.environ.get("HAC_ORACLE_LIB") or _SO_BUILT
 
 GCC_FLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
              "-Wall", "-Wno-unused-function"]
@@ -25,11 +28,11 @@ GCC_FLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno
 
 def build(force: bool = True) -> str:
     """Compile the oracle into oracle/liboracle.so."""
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp"
+    if force or not os.path.exists(_SO_BUILT):
+        tmp = _SO_BUILT + ".tmp"
         subprocess.check_call(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _SO)
-    return _SO
+        os.replace(tmp, _SO_BUILT)
+    return _SO_BUILT
 
 
 class Problem(ctypes.Structure):
@@ -71,7 +74,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        if _SO == _SO_BUILT and (not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC)):
             build()
         L = ctypes.CDLL(_SO)
         P = ctypes.POINTER(Problem)

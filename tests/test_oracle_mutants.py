@@ -1,0 +1,132 @@
+"""Mutation check of the oracle's pins.
+
+Each mutant plants one plausible mistake in a copy of oracle/hac_oracle.c:
+a dropped term, a wrong sign or operator, an off-by-one index, a flipped
+comparison or tie rule.  The copy is built with the oracle's own gcc flags,
+and the pin tests (tests/test_oracle_pins.py, tests/test_oracle_reduction.py)
+run against it in a subprocess (HAC_ORACLE_LIB).  At least one pin must fail
+for every mutant.  The oracle source itself is never changed; every mutant
+keeps the oracle terminating.
+"""
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hac_oracle.c")
+
+# (what the mutant gets wrong, text in the oracle, its replacement)
+MUTANTS = [
+    ("eq. (1): closing edge dropped",
+     "  len += dist(p, tour[n - 1], tour[0]);\n  return len;", "  return len;"),
+    ("eq. (3): threshold comparison reversed",
+     "      if ((double)p->val[e] > p->theta_h) {\n        member[j] = 1;",
+     "      if ((double)p->val[e] < p->theta_h) {\n        member[j] = 1;"),
+    ("eq. (3): ties broken to the higher index",
+     "return ka < kb || (ka == kb && a < b);", "return ka < kb || (ka == kb && a > b);"),
+    ("eq. (10): order statistic off by one",
+     "double order_stat = cnt >= dstar + 1 ? sorted[dstar] : 0.0;",
+     "double order_stat = cnt >= dstar ? sorted[dstar - 1] : 0.0;"),
+    ("eq. (11): ratio inverted",
+     "double ratio = (ci > p->eps ? ci : p->eps) / b[i];",
+     "double ratio = b[i] / (ci > p->eps ? ci : p->eps);"),
+    ("eq. (12): quantile position off by one",
+     "double h = 0.9 * (double)(nl - 1);", "double h = 0.9 * (double)nl;"),
+    ("eq. (14): q90 multiplied instead of divided",
+     "p->c_cap * p->alpha * log(r) / q90", "p->c_cap * p->alpha * log(r) * q90"),
+    ("eq. (13): k instead of k - 1",
+     "return (((double)(k_eff - 1) / 2.0) * px) / (1.0 - px);",
+     "return (((double)k_eff / 2.0) * px) / (1.0 - px);"),
+    ("eq. (6): p_x divided instead of multiplied",
+     "*tmin = *tmax * (1.0 - px) / (((double)(k_eff - 1) / 2.0) * px);",
+     "*tmin = *tmax * (1.0 - px) / (((double)(k_eff - 1) / 2.0) / px);"),
+    ("eq. (5): rho dropped from tau_max",
+     "*tmax = 1.0 / (p->rho * len);", "*tmax = 1.0 / len;"),
+    ("fold: evidence factor with the wrong sign",
+     "heur[x] = (float)(eta_pow(eta, p->beta) * exp(lw));",
+     "heur[x] = (float)(eta_pow(eta, p->beta) * exp(-lw));"),
+    ("fold: eta^(beta + 1)",
+     "for (int b = 0; b < (int)beta; b++) r = r * eta;", "for (int b = 0; b <= (int)beta; b++) r = r * eta;"),
+    ("fold: clip not applied",
+     "        if (lw > p->clip) lw = p->clip;\n", ""),
+    ("eq. (4): prefix compared with >=",
+     "if (acc > r) return s;", "if (acc >= r) return s;"),
+    ("eq. (4): visited slots count towards the exponent",
+     "    if (visited[cand_row[s]]) continue;\n    int ex;", "    int ex;"),
+    ("eq. (4): one bit less resolution",
+     "double scaled = floor(ldexp((double)w_row[s], 23 - emax));",
+     "double scaled = floor(ldexp((double)w_row[s], 22 - emax));"),
+    ("eq. (7): evaporation dropped", "float v = keep * tau[x];", "float v = tau[x];"),
+    ("eq. (7): symmetric deposit on the successor only",
+     "int on_tour = j == succ[i] || (sym && j == pred[i]);", "int on_tour = j == succ[i];"),
+    ("eq. (8): lower clamp dropped", "        v = fmaxf(tmin_f, v);\n", ""),
+    ("restart-best replaced on ties",
+     "if (!rb_valid || l_ib < l_rb) {", "if (!rb_valid || l_ib <= l_rb) {"),
+    ("iteration best: last of equal ants",
+     "if (lens[a] < lens[ib]) ib = a;", "if (lens[a] <= lens[ib]) ib = a;"),
+    ("global best replaced on ties", "if (l_ib < l_gb) {", "if (l_ib <= l_gb) {"),
+    ("elite: restart-best on the wrong iterations",
+     "int use_rb = (t % ugb) == 0;", "int use_rb = (t % ugb) == 1;"),
+    ("u_gb: second tier 4 instead of 5", "if (stall < 75) return 5;", "if (stall < 75) return 4;"),
+    ("branching factor not divided by d*",
+     "double bf = (double)branches / ((double)n * (double)dstar);", "double bf = (double)branches / (double)n;"),
+    ("restart resets tau to tau_min",
+     "stall > p->restart_stall) {\n        for (int64_t x = 0; x < nk; x++) { tau[x] = tmax_f;",
+     "stall > p->restart_stall) {\n        for (int64_t x = 0; x < nk; x++) { tau[x] = tmin_f;"),
+    ("2-opt: fourth end node not re-queued",
+     "PUSH(a); PUSH(b); PUSH(c); PUSH(e);", "PUSH(a); PUSH(b); PUSH(c);"),
+    ("2-opt: gain threshold 1e-3", "double min_gain = 1e-9 * l_nn_raw", "double min_gain = 1e-3 * l_nn_raw"),
+    ("Philox: wrong round multiplier", "0xD2511F53", "0xD2511F55"),
+    ("start node drawn from n - 1 nodes",
+     "int32_t start = (int32_t)scale32(orc_draw(p->seed, t, a, 0), (uint64_t)n);",
+     "int32_t start = (int32_t)scale32(orc_draw(p->seed, t, a, 0), (uint64_t)(n - 1));"),
+    ("NN tour starts at node 1",
+     "  tour[0] = 0;\n  vis[0] = 1;", "  tour[0] = 1;\n  vis[1] = 1;"),
+    ("output read in the other direction",
+     "if (sym && n >= 3 && tour_out[1] > tour_out[n - 1]) {", "if (sym && n >= 3 && tour_out[1] < tour_out[n - 1]) {"),
+    ("diagnostics: Edges/n without the factor 2",
+     "out[0] = (double)entries / (2.0 * (double)n);", "out[0] = (double)entries / (double)n;"),
+]
+
+
+def _build(tmp, x, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutant {x}: anchor not found once in the oracle"
+    path = os.path.join(tmp, f"mutant{x}.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    so = os.path.join(tmp, f"libmutant{x}.so")
+    subprocess.check_call(["gcc", *oracle.GCC_FLAGS, "-I", os.path.dirname(SRC), path, "-o", so, "-lm"])
+    return so
+
+
+def _pins_fail(so):
+    env = dict(os.environ, HAC_ORACLE_LIB=so)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                        "tests/test_oracle_pins.py", "tests/test_oracle_reduction.py"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode, r.stdout[-600:]
+
+
+def test_mutants_are_caught_by_the_pins(tmp_path):
+    sos = [_build(str(tmp_path), x, old, new) for x, (_, old, new) in enumerate(MUTANTS)]
+    with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(_pins_fail, sos))
+    survivors = []
+    for (what, _, _), (rc, out) in zip(MUTANTS, results):
+        # 1: some test failed; 0: every pin passed
+        assert rc in (0, 1), f"{what}: pytest exited with {rc}\n{out}"
+        if rc == 0:
+            survivors.append(what)
+    assert not survivors, f"mutants no pin catches: {survivors}"
+
+
+def test_unmutated_copy_passes(tmp_path):
+    """The harness itself: the oracle built from an unchanged copy passes."""
+    so = _build(str(tmp_path), "copy", "/* Eq. (1)", "/* Eq. (1)")
+    rc, out = _pins_fail(so)
+    assert rc == 0, out

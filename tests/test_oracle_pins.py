@@ -362,6 +362,32 @@ def _select_mass(cand, w, vis):
     return np.array(mass)
 
 
+def test_select_intervals_are_half_open():
+    # Eq. (4) sampled by inverse CDF: slot s owns the draws whose scaled
+    # value lies in [prefix before s, prefix through s).  Two open slots of
+    # equal weight split the 2^32 draws into equal halves, the lower half
+    # to the first slot and the point 2^31 itself to the second.
+    cand = np.array([1, 2], dtype=np.int32)
+    w = np.array([3.0, 3.0], dtype=np.float32)
+    vis = np.zeros(3, dtype=np.uint8)
+    assert oracle.select(cand, w, vis, 2 ** 31 - 1) == 0
+    assert oracle.select(cand, w, vis, 2 ** 31) == 1
+
+
+@pytest.mark.parametrize("light", [3, 5, 1000])
+def test_select_exact_for_weights_on_the_24_bit_grid(light):
+    # With the largest open weight 1 (exponent 0), whole multiples of 2^-23
+    # are on the grid the roulette works at, so it adds no error of its own:
+    # the share of the 2^32 draws that pick the light slot equals eq. (4)'s
+    # w1 / (w0 + w1) to within the draw granularity 2^-32.
+    w1 = light * 2.0 ** -23
+    cand = np.array([1, 2], dtype=np.int32)
+    w = np.array([1.0, w1], dtype=np.float32)
+    vis = np.zeros(3, dtype=np.uint8)
+    mass = _select_mass(cand, w, vis)
+    assert abs(mass[1] - w1 / (1.0 + w1)) <= 2.0 ** -32
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_select_probabilities_within_the_discretisation_bound(seed):
     """Each slot's probability under the fixed-point roulette is within

@@ -298,3 +298,25 @@ def test_local_search_every_ant_changes_the_search():
     _, _, _, i1 = oracle.decode(inst1, state=True)
     _, _, _, i2 = oracle.decode(inst2, state=True)
     assert not np.array_equal(i1["ant_len"], i2["ant_len"])
+
+
+def test_lattice_ties_restarts_and_late_elite_tiers():
+    # A full 4 x 4 lattice with spacing 1/4: every tour along lattice edges
+    # is exactly 4 long, so a converged search ties again and again.  Ties
+    # keep the first ant as iteration best and leave the restart-best and
+    # global-best tours in place (strict improvement only).  The run stalls
+    # past the first u_gb tier, and lambda_bf = 1.5 separates a branching
+    # factor normalised by n d* (1 on a converged field, so it restarts)
+    # from an unnormalised one (2, no restart).
+    inst = wl.random_instance(16, seed=21, grid=4, heat="empty", k=5, ants=6, iterations=160)
+    ref = TextbookMMAS(inst, bf_period=10, restart_stall=30, lam=1.5)
+    want_t, want_L = ref.run()
+    st, tour, L, info = oracle.decode(inst, trace=True, bf_period=10, restart_stall=30, lambda_bf=1.5)
+    assert st == 0 and info["kappa"] == 0.0
+    assert list(tour) == want_t and L == want_L
+    assert list(info["elite_rb"].astype(bool)) == ref.elite_log
+    # the case is not vacuous: iteration bests tie the global best, and the
+    # converged field restarts
+    l_ib, l_gb = info["l_ib"], info["l_gb"]
+    assert np.sum(l_ib[1:] == l_gb[:-1]) >= 20
+    assert info["restarts"] >= 1
