@@ -90,6 +90,35 @@ MUTANTS = [
      "if (sym && n >= 3 && tour_out[1] > tour_out[n - 1]) {", "if (sym && n >= 3 && tour_out[1] < tour_out[n - 1]) {"),
     ("diagnostics: Edges/n without the factor 2",
      "out[0] = (double)entries / (2.0 * (double)n);", "out[0] = (double)entries / (double)n;"),
+    ("eq. (9): confidence not thresholded",
+     "c[(int64_t)i * k_eff + u] = h > p->theta_h ? h : 0.0;", "c[(int64_t)i * k_eff + u] = h > 0.0 ? h : 0.0;"),
+    ("eq. (10): eps floor dropped",
+     "b[i] = order_stat > p->eps ? order_stat : p->eps;", "b[i] = order_stat;"),
+    ("eq. (12): interpolation from the upper order statistic",
+     "q90 = lo + 1 < nl ? logs[lo] + frac * (logs[lo + 1] - logs[lo]) : logs[lo];",
+     "q90 = lo + 1 < nl ? logs[lo + 1] + frac * (logs[lo + 1] - logs[lo]) : logs[lo];"),
+    ("eq. (10), full row: diagonal entry counted",
+     "if (p->col[q] != i && h > p->theta_h) sorted[cnt++] = h;", "if (h > p->theta_h) sorted[cnt++] = h;"),
+    ("eq. (7): rho kept instead of 1 - rho",
+     "float keep = (float)(1.0 - p->rho);", "float keep = (float)p->rho;"),
+    ("eq. (7): deposit 1 / L of the iteration best also on restart-best iterations",
+     "double l_elite = use_rb ? l_rb : l_ib;", "double l_elite = l_ib;"),
+    ("elite: global best instead of restart best",
+     "const int32_t* elite = use_rb ? t_rb : t_ib;", "const int32_t* elite = use_rb ? t_gb : t_ib;"),
+    ("initial tau at tau_min",
+     "float* w = (float*)malloc(4 * nk);\n  for (int64_t x = 0; x < nk; x++) { tau[x] = tmax_f;",
+     "float* w = (float*)malloc(4 * nk);\n  for (int64_t x = 0; x < nk; x++) { tau[x] = tmin_f;"),
+    ("2-opt: the longer side reversed", "  if (2 * len > n) {", "  if (2 * len < n) {"),
+    ("draw counter: step and ant swapped", "uint32_t ctr[4] = {s, a, t, 0u};", "uint32_t ctr[4] = {a, s, t, 0u};"),
+    ("start node from another counter",
+     "int32_t start = (int32_t)scale32(orc_draw(p->seed, t, a, 0)",
+     "int32_t start = (int32_t)scale32(orc_draw(p->seed, t, a, (uint32_t)n)"),
+    ("fallback: nearest to the start node, not the current one",
+     "j = nearest_unvisited(p, i, vis);", "j = nearest_unvisited(p, tour[0], vis);"),
+    ("diagnostics: directed coverage counts reversed edges",
+     "if (has_out[a] || (sym && has_in[a])) covered++;", "if (has_out[a] || has_in[a]) covered++;"),
+    ("diagnostics: P(e > 1) ignores the predecessor edge",
+     "if (j == succ[i] || (sym && j == pred[i])) on_tour++;", "if (j == succ[i]) on_tour++;"),
 ]
 
 

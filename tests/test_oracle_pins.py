@@ -145,6 +145,37 @@ def test_evidence_worked_rows():
         assert ev["evid"][0] == pytest.approx(rhs[1:], rel=1e-6)
 
 
+def test_evidence_threshold_worked_row():
+    # eq. (9): confidences at or below theta_h count as 0, so with
+    # theta_h = 0.02 the row 0.5, 0.01, 0.009 has one positive confidence;
+    # eq. (10) then misses the third order statistic (d* = 2) and b = eps
+    inst = _row_instance([0.5, 0.01, 0.009])
+    cand = oracle.candidates(inst, theta_h=0.02)
+    # eq. (3): node 1 is supported, the list is filled with the nearest others
+    assert list(cand[0]) == [1, 2, 3]
+    ev = oracle.evidence(inst, cand, theta_h=0.02, degree_target=2)
+    assert list(ev["conf"][0]) == [0.5, 0.0, 0.0]
+    assert ev["base"][0] == 1e-9
+    assert ev["evid"][0] == pytest.approx([0.5 / 1e-9, 1.0, 1.0], rel=1e-6)
+
+
+def test_evidence_full_row_ignores_the_diagonal():
+    # eq. (10) over the full heatmap row (baseline_scope = 1) takes j in
+    # V \ {i}: a diagonal entry of 0.9 beside 0.5, 0.3, 0.2, 0.1 leaves the
+    # third largest at 0.2, so e = 2.5, 1.5, 1, 1
+    n = 5
+    xy = np.zeros((n, 2))
+    xy[1:, 0] = 0.1 * np.arange(1, n)
+    rp = np.array([0, 5, 5, 5, 5, 5], dtype=np.int32)
+    heat = wl.Heatmap(n, rp, np.arange(5, dtype=np.int32), np.array([0.9, 0.5, 0.3, 0.2, 0.1], dtype=np.float32))
+    inst = wl.Instance(n, "coords", True, xy, None, heat, ants=2, iterations=1, k=4)
+    cand = oracle.candidates(inst)
+    assert list(cand[0]) == [1, 2, 3, 4]
+    ev = oracle.evidence(inst, cand, baseline_scope=1, degree_target=2)
+    assert ev["base"][0] == pytest.approx(0.2, rel=1e-6)
+    assert ev["evid"][0] == pytest.approx([2.5, 1.5, 1.0, 1.0], rel=1e-6)
+
+
 def test_evidence_at_most_dstar_above_one_per_row():
     for inst, dstar in [(wl.tsp500(iterations=1), 2), (wl.serve_request("atsp1000", 1), 1),
                         (wl.random_instance(80, seed=5, topk=12, k=10), 2)]:

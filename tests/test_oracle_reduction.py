@@ -232,6 +232,7 @@ class TextbookMMAS:
                     w = [[f32(tmax * self.heur[i][q]) for q in range(self.k)] for i in range(n)]
                     rb, stall = None, 0
             ugb = (self.ugb_max if stall < 25 else 5 if stall < 75 else 3 if stall < 125 else 2 if stall < 250 else 1)
+        self.tau = tau
         # canonical rotation
         r0 = gb.index(0)
         out = gb[r0:] + gb[:r0]
@@ -268,10 +269,12 @@ def test_elite_schedule_and_restart_forced():
     inst = wl.random_instance(14, seed=9, heat="empty", k=4, ants=3, iterations=40)
     ref = TextbookMMAS(inst, ugb_max=2, bf_period=3, restart_stall=1, lam=1e9)
     want_t, want_L = ref.run()
-    st, tour, L, info = oracle.decode(inst, trace=True, ugb_max=2, bf_period=3, restart_stall=1,
+    st, tour, L, info = oracle.decode(inst, trace=True, state=True, ugb_max=2, bf_period=3, restart_stall=1,
                                       lambda_bf=1e9)
     assert list(tour) == want_t and L == want_L
     assert list(info["elite_rb"].astype(bool)) == ref.elite_log
+    # the deposits themselves: the final pheromone, bit for bit
+    assert np.array_equal(info["tau"], np.array(ref.tau, dtype=np.float32))
     assert info["restarts"] > 0
 
 
@@ -311,12 +314,27 @@ def test_lattice_ties_restarts_and_late_elite_tiers():
     inst = wl.random_instance(16, seed=21, grid=4, heat="empty", k=5, ants=6, iterations=160)
     ref = TextbookMMAS(inst, bf_period=10, restart_stall=30, lam=1.5)
     want_t, want_L = ref.run()
-    st, tour, L, info = oracle.decode(inst, trace=True, bf_period=10, restart_stall=30, lambda_bf=1.5)
+    st, tour, L, info = oracle.decode(inst, trace=True, state=True, bf_period=10, restart_stall=30,
+                                      lambda_bf=1.5)
     assert st == 0 and info["kappa"] == 0.0
     assert list(tour) == want_t and L == want_L
     assert list(info["elite_rb"].astype(bool)) == ref.elite_log
+    assert np.array_equal(info["tau"], np.array(ref.tau, dtype=np.float32))
     # the case is not vacuous: iteration bests tie the global best, and the
     # converged field restarts
     l_ib, l_gb = info["l_ib"], info["l_gb"]
     assert np.sum(l_ib[1:] == l_gb[:-1]) >= 20
     assert info["restarts"] >= 1
+
+
+def test_restart_best_deposit_uses_its_own_length():
+    # eq. (7) with T+ the restart-best tour: on an elite iteration it
+    # deposits 1 / L(T_rb), also when that iteration's own best is longer.
+    # u_gb = 2 makes iteration 2 an elite iteration; seed 4 gives an
+    # iteration-2 best longer than iteration 1's.
+    inst = wl.random_instance(14, seed=4, heat="empty", k=4, ants=3, iterations=2)
+    ref = TextbookMMAS(inst, ugb_max=2, bf_period=0)
+    ref.run()
+    st, tour, L, info = oracle.decode(inst, trace=True, state=True, ugb_max=2, bf_period=0)
+    assert info["l_ib"][1] > info["l_ib"][0] and list(info["elite_rb"]) == [0, 1]
+    assert np.array_equal(info["tau"], np.array(ref.tau, dtype=np.float32))
