@@ -615,10 +615,11 @@ __device__ __forceinline__ LsMove ls_eval(const GDist& G, const HAC_AS1 int32_t*
   return m;
 }
 
-// reverse the tour path from x to y (or its complement when shorter); block-wide
+// Reverse the tour path between positions i and j (or its complement when
+// that is shorter); block-wide.  Every thread passes the same positions,
+// read before any thread of the block can change pos.
 template <class IP>
-__device__ __forceinline__ void ls_reverse(int n, IP tour, IP pos, int x, int y) {
-  int i = pos[x], j = pos[y];
+__device__ __forceinline__ void ls_reverse(int n, IP tour, IP pos, int i, int j) {
   int len = ((j - i + n) % n) + 1;
   if (2 * len > n) {
     const int ni = (j + 1) % n, nj = (i - 1 + n) % n;
@@ -626,7 +627,6 @@ __device__ __forceinline__ void ls_reverse(int n, IP tour, IP pos, int x, int y)
     j = nj;
     len = n - len;
   }
-  __syncthreads();  // every thread has read pos[x], pos[y]
   const int half = len / 2;
   for (int s = threadIdx.x; s < half; s += blockDim.x) {
     int pi = i + s;
@@ -692,7 +692,12 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
     // move improves, else those up to and including the improving one
     const int used = f < 0 ? nq : max(0, f + 1 - re);
     LsMove m{};
-    if (f >= 0) m = sh_mv[f];
+    int ri = 0, rj = 0;  // positions of the ends of the path to reverse
+    if (f >= 0) {
+      m = sh_mv[f];
+      ri = pos[m.dir == 0 ? m.b : m.c];
+      rj = pos[m.dir == 0 ? m.c : m.b];
+    }
     if ((int)threadIdx.x < used) {
       int slot = head + threadIdx.x;
       if (slot >= n) slot -= n;
@@ -710,13 +715,11 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
       __syncthreads();
       continue;
     }
-    // apply the move and queue its end nodes; its node is examined next
-    if (m.dir == 0)
-      ls_reverse(n, tour, pos, m.b, m.c);
-    else
-      ls_reverse(n, tour, pos, m.c, m.b);
-    // the move's end nodes a, b, c, e (four distinct nodes) join the queue
-    // tail in that order if absent: lanes 0..3 of wave 0 take one each
+    // queue the move's end nodes, then apply it; its node is examined next.
+    // The end nodes a, b, c, e (four distinct nodes) join the queue tail in
+    // that order if absent: lanes 0..3 of wave 0 take one each, after lane 0
+    // has moved the head (the queue and the tour are separate arrays, so
+    // this may precede the reversal, whose closing barrier publishes both)
     if (threadIdx.x < 4) {
       const int z = threadIdx.x;
       const int x = z == 0 ? m.a : (z == 1 ? m.b : (z == 2 ? m.c : m.e));
@@ -731,8 +734,8 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
       __builtin_amdgcn_wave_barrier();
       if (z == 0) sh_count += __builtin_popcount(am);
     }
+    ls_reverse(n, tour, pos, ri, rj);
     pend = m.a;
-    __syncthreads();
   }
 }
 
