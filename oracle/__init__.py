@@ -64,7 +64,7 @@ class Trace(ctypes.Structure):
         ("l_ib", ctypes.c_void_p), ("l_gb", ctypes.c_void_p), ("elite_rb", ctypes.c_void_p),
         ("cand", ctypes.c_void_p), ("heur", ctypes.c_void_p), ("tau", ctypes.c_void_p),
         ("weight", ctypes.c_void_p), ("ant_tours", ctypes.c_void_p), ("ant_len", ctypes.c_void_p),
-        ("nn_tour", ctypes.c_void_p),
+        ("nn_tour", ctypes.c_void_p), ("ugb", ctypes.c_void_p), ("restart", ctypes.c_void_p),
     ]
 
 
@@ -234,6 +234,8 @@ def decode(inst, trace: bool = False, state: bool = False, **over):
         bufs["l_ib"] = np.zeros(max(iters, 1))
         bufs["l_gb"] = np.zeros(max(iters, 1))
         bufs["elite_rb"] = np.zeros(max(iters, 1), dtype=np.int32)
+        bufs["ugb"] = np.zeros(max(iters, 1), dtype=np.int32)
+        bufs["restart"] = np.zeros(max(iters, 1), dtype=np.int32)
     if state:
         bufs["cand"] = np.zeros((n, ke), dtype=np.int32)
         bufs["heur"] = np.zeros((n, ke), dtype=np.float32)
@@ -249,7 +251,7 @@ def decode(inst, trace: bool = False, state: bool = False, **over):
                 l_nn_raw=tr.l_nn_raw, ant_steps=tr.ant_steps, fallback_steps=tr.fallback_steps,
                 restarts=tr.restarts)
     for name, arr in bufs.items():
-        info[name] = arr[:iters] if name in ("l_ib", "l_gb", "elite_rb") else arr
+        info[name] = arr[:iters] if name in ("l_ib", "l_gb", "elite_rb", "ugb", "restart") else arr
     return st, tour, L.value, info
 
 

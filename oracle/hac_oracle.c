@@ -24,10 +24,12 @@
  * choice, branching-factor normalisation, u_gb schedule, fixed-point
  * roulette, RNG, summation order, 2-opt move order).
  *
- * Parity status: every function is pinned by the CPU tests except three
- * readings that no passage of the paper can pin (which tour deposits on a
- * u_gb iteration, the u_gb tiers, and the branching-factor normalisation):
- * for those the oracle is "parity unpinned" against the paper.
+ * Parity status: every function is pinned by the CPU tests, the elite
+ * choice and the shape of the u_gb schedule by the properties Section III-B
+ * states.  Two readings no passage of the paper can pin: the u_gb tier
+ * values with their stall thresholds, and the branching-factor
+ * normalisation.  For those the oracle is "parity unpinned" against the
+ * paper.
  */
 #include "hac_oracle.h"
 
@@ -530,7 +532,9 @@ static void tau_bounds(const orc_problem* p, int32_t k_eff, double len, double* 
 
 /* u_gb tiers.  Reading: the paper only says u_gb tightens from 25 to 1 as the
  * search stalls; the tiers are keyed on iterations without restart-best
- * improvement.  (parity unpinned) */
+ * improvement.  (the tier values are parity unpinned; that the schedule
+ * starts at u_gb_max, never grows without an improvement and ends at 1 is
+ * pinned) */
 static int32_t ugb_schedule(const orc_problem* p, int32_t stall) {
   if (stall < 25) return p->ugb_max;
   if (stall < 75) return 5;
@@ -752,6 +756,7 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
     /* elite tour.  Reading: on every u_gb-th iteration the restart-best
        tour deposits (it equals the global best until the first restart). */
     int use_rb = (t % ugb) == 0;
+    int restarted = 0;
     const int32_t* elite = use_rb ? t_rb : t_ib;
     double l_elite = use_rb ? l_rb : l_ib;
     for (int32_t s = 0; s < n; s++) {
@@ -795,14 +800,17 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
         rb_valid = 0;
         stall = 0;
         restarts++;
+        restarted = 1;
       }
     }
-    ugb = ugb_schedule(p, stall);
     if (tr) {
       if (tr->l_ib) tr->l_ib[t - 1] = l_ib;
       if (tr->l_gb) tr->l_gb[t - 1] = l_gb;
       if (tr->elite_rb) tr->elite_rb[t - 1] = use_rb;
+      if (tr->ugb) tr->ugb[t - 1] = ugb;
+      if (tr->restart) tr->restart[t - 1] = restarted;
     }
+    ugb = ugb_schedule(p, stall);
   }
 
   /* canonical output: start at node 0; symmetric tours read with the

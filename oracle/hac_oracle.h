@@ -55,6 +55,10 @@ typedef struct {
                        /* local search when local_search = 2)               */
   double* ant_len;     /* [ants] their lengths                               */
   int32_t* nn_tour;    /* [n] the (optionally 2-opted) NN tour               */
+  int32_t* ugb;        /* [iterations] u_gb in force when iteration t chose   */
+                       /* its elite tour                                     */
+  int32_t* restart;    /* [iterations] 1 if a branching-factor restart ended */
+                       /* iteration t                                        */
 } orc_trace;
 
 /* Philox4x32-10 block */

@@ -3,8 +3,8 @@
 Each mutant plants one plausible mistake in a copy of oracle/hac_oracle.c:
 a dropped term, a wrong sign or operator, an off-by-one index, a flipped
 comparison or tie rule.  The copy is built with the oracle's own gcc flags,
-and the pin tests (tests/test_oracle_pins.py, tests/test_oracle_reduction.py)
-run against it in a subprocess (HAC_ORACLE_LIB).  At least one pin must fail
+and the pin tests (tests/test_oracle_pins.py, tests/test_oracle_reduction.py,
+tests/test_oracle_elite.py) run against it in a subprocess (HAC_ORACLE_LIB).  At least one pin must fail
 for every mutant.  The oracle source itself is never changed; every mutant
 keeps the oracle terminating.
 """
@@ -119,6 +119,47 @@ MUTANTS = [
      "if (has_out[a] || (sym && has_in[a])) covered++;", "if (has_out[a] || has_in[a]) covered++;"),
     ("diagnostics: P(e > 1) ignores the predecessor edge",
      "if (j == succ[i] || (sym && j == pred[i])) on_tour++;", "if (j == succ[i]) on_tour++;"),
+    ("elite: restart-best off the u_gb iterations",
+     "int use_rb = (t % ugb) == 0;", "int use_rb = (t % ugb) != 0;"),
+    ("elite: the restart-best tour never deposits",
+     "int use_rb = (t % ugb) == 0;", "int use_rb = 0;"),
+    ("u_gb not back at its start after an improvement",
+     "if (stall < 25) return p->ugb_max;", "if (stall < 25) return 5;"),
+    ("u_gb keyed on the iteration count (grows back without an improvement)",
+     "ugb = ugb_schedule(p, stall);", "ugb = ugb_schedule(p, t % 200);"),
+    ("u_gb never reaches 1",
+     "if (stall < 250) return 2;\n  return 1;", "if (stall < 250) return 2;\n  return 2;"),
+    ("restart keeps the restart-best tour",
+     "        rb_valid = 0;\n        stall = 0;\n        restarts++;", "        stall = 0;\n        restarts++;"),
+    ("restart forgets the global best",
+     "        restarts++;\n        restarted = 1;", "        restarts++;\n        restarted = 1;\n        l_gb = 1e300;"),
+    ("restart resets the first row only",
+     "for (int64_t x = 0; x < nk; x++) { tau[x] = tmax_f; w[x] = tau[x] * heur[x]; }\n        rb_valid = 0;",
+     "for (int64_t x = 0; x < k_eff; x++) { tau[x] = tmax_f; w[x] = tau[x] * heur[x]; }\n        rb_valid = 0;"),
+]
+
+# Mutants of the elite schedule and the restart (Section III-B).  Each must
+# be caught by tests/test_oracle_elite.py ALONE: those pins state what the
+# section fixes (which tour deposits when, how u_gb moves, what a restart
+# resets and keeps) without restating the oracle's tiers or elite rule, so
+# the pure-Python textbook MMAS of test_oracle_reduction.py (which does
+# restate them) is not what catches these.  The exact tier values (25, 5,
+# 3, 2, 1 at stalls 25, 75, 125, 250) are a reading and stay unpinned: a
+# mutant that only moves a tier value inside the monotone schedule, such as
+# "u_gb: second tier 4 instead of 5", is expected to pass these pins.
+ELITE_MUTANTS = [
+    "elite: restart-best on the wrong iterations",
+    "eq. (7): deposit 1 / L of the iteration best also on restart-best iterations",
+    "elite: global best instead of restart best",
+    "restart resets tau to tau_min",
+    "elite: restart-best off the u_gb iterations",
+    "elite: the restart-best tour never deposits",
+    "u_gb not back at its start after an improvement",
+    "u_gb keyed on the iteration count (grows back without an improvement)",
+    "u_gb never reaches 1",
+    "restart keeps the restart-best tour",
+    "restart forgets the global best",
+    "restart resets the first row only",
 ]
 
 
@@ -133,11 +174,13 @@ def _build(tmp, x, old, new):
     return so
 
 
-def _pins_fail(so):
+PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_reduction.py", "tests/test_oracle_elite.py"]
+
+
+def _pins_fail(so, files=tuple(PIN_FILES)):
     env = dict(os.environ, HAC_ORACLE_LIB=so)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
-                        "tests/test_oracle_pins.py", "tests/test_oracle_reduction.py"],
-                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+                        *files], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode, r.stdout[-600:]
 
 
@@ -158,4 +201,28 @@ def test_unmutated_copy_passes(tmp_path):
     """The harness itself: the oracle built from an unchanged copy passes."""
     so = _build(str(tmp_path), "copy", "/* Eq. (1)", "/* Eq. (1)")
     rc, out = _pins_fail(so)
+    assert rc == 0, out
+
+
+def test_elite_mutants_are_caught_by_the_section_iii_b_pins(tmp_path):
+    names = [m[0] for m in MUTANTS]
+    picked = [(names.index(w), MUTANTS[names.index(w)]) for w in ELITE_MUTANTS]
+    sos = [_build(str(tmp_path), x, old, new) for x, (_, old, new) in picked]
+    with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(lambda so: _pins_fail(so, ("tests/test_oracle_elite.py",)), sos))
+    survivors = []
+    for (_, (what, _, _)), (rc, out) in zip(picked, results):
+        assert rc in (0, 1), f"{what}: pytest exited with {rc}\n{out}"
+        if rc == 0:
+            survivors.append(what)
+    assert not survivors, f"elite mutants the Section III-B pins miss: {survivors}"
+
+
+def test_tier_values_are_not_pinned(tmp_path):
+    """The tier values are the build's reading: moving one inside the
+    monotone schedule passes the Section III-B pins (documents the limit)."""
+    names = [m[0] for m in MUTANTS]
+    x = names.index("u_gb: second tier 4 instead of 5")
+    so = _build(str(tmp_path), x, MUTANTS[x][1], MUTANTS[x][2])
+    rc, out = _pins_fail(so, ("tests/test_oracle_elite.py",))
     assert rc == 0, out
