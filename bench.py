@@ -6,7 +6,8 @@ TSP instances with n uniform on [500, 1000], top-10 SoftDist heatmaps,
 k = 10, 50 ants, 500 iterations each.  One step = one hac_decode_batch_dev
 call over all 64 instances with their inputs already in HBM: candidate
 lists, evidence fold, NN tours, 500 iterations of construction + update
-for every instance, results.
+for every instance, results.  Steps run the production path (iterations
+replayed from a captured hipGraph, no per-kernel timing).
 
 Reported on one JSON line:
   value             ant-steps/s of the batched path (whole job)
@@ -17,9 +18,16 @@ Reported on one JSON line:
                     so the mean gap is equal by construction (asserted)
   latency_ms        p50/p99 per-decode latency of both paths
   roofline          construction kernel: algorithmic bytes per launch over
-                    its mean launch time (HIP events on the library's
-                    stream), against 8 TB/s HBM
+                    its mean launch time, from HIP events on the library's
+                    stream in one extra decode with kernel timing on (the
+                    kernels are the same; only the launch sequence differs)
+  kernels           the same line for the pheromone update and, where it
+                    runs, the 2-opt
   cpu_baseline      the CPU oracle on the host cores, on a bounded sample
+  tsp10k            the 8 x n = 10 000 batch with 2-opt (one step), against
+                    plain decodes of its instances
+  serve             the Poisson serving mix through the request loop,
+                    against plain decodes of each request kind
 """
 
 from __future__ import annotations
@@ -66,22 +74,49 @@ def _oracle_job(args):
     return info["ant_steps"], perf_counter() - t
 
 
+def host_workers() -> int:
+    """Worker processes for host-side work: the cores this process may run
+    on, capped by OMP_NUM_THREADS where the host sets it (a shared GPU machine
+    grants each GPU a share of its cores)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS")
+    return max(1, min(n, int(cap))) if cap and cap.isdigit() else max(1, n)
+
+
 def cpu_baseline(insts, sample: int, iters: int):
     """The oracle as it stands, one process per instance on the host cores."""
     from concurrent.futures import ProcessPoolExecutor
     import oracle
     oracle.build(force=False)
     jobs = [(insts[x], iters) for x in range(min(sample, len(insts)))]
-    cores = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+    cores = min(len(jobs), host_workers())
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=cores) as ex:
         res = list(ex.map(_oracle_job, jobs))
     wall = time.perf_counter() - t0
     steps = sum(r[0] for r in res)
     cpu = sum(r[1] for r in res)
-    return {"value": steps / wall, "unit": "ant-steps/s", "cores": cores, "kind": "oracle",
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": steps / wall, "unit": "ant-steps/s", "cores": cores, "nproc": nproc, "kind": "oracle",
             "sample": f"{len(jobs)} of the {len(insts)} instances at {iters} iterations each "
-                      f"(one process per instance), {cpu:.1f} s of CPU work, {wall:.1f} s wall"}
+                      f"(one process per instance, {cores} at a time), {cpu:.1f} s of CPU work, {wall:.1f} s wall"}
+
+
+def _gen_job(spec):
+    from paper_2601_19041_amd import workloads as wl
+    kind, a, b = spec
+    if kind == "batch64":
+        return wl.batch64_instance(a, b)
+    if kind == "tsp10k":
+        return wl.tsp10k_instance(a, b)
+    return wl.serve_request(kind, a, b)
+
+
+def generate(specs):
+    """Builds instances on the host cores (before the GPU is touched)."""
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(len(specs), host_workers())) as ex:
+        return list(ex.map(_gen_job, specs, chunksize=max(1, len(specs) // (4 * host_workers()))))
 
 
 def traffic_from_profile(kernel_src_hash: str, launches_key: str):
@@ -171,27 +206,66 @@ def roofline(insts, cms, launches, traffic_key=None):
             "algorithmic_bytes_per_launch": bytes_per_launch}
 
 
+def update_bytes(insts) -> int:
+    """Algorithmic bytes of one end-of-iteration launch (eq. 7-8): per
+    candidate slot read tau, S and the candidate id and write tau and W
+    (20 B), per node the elite tour's successor and predecessor (8 B)."""
+    return sum(20 * x.n * min(x.k, x.n - 1) + 8 * x.n for x in insts)
+
+
+def two_opt_bytes(insts) -> int:
+    """Algorithmic bytes of one 2-opt launch over the tours it searches: read
+    the tour (4 B), the coordinates (16 B) and the neighbour list (4 k_ls B)
+    of every node and write the tour (4 B)."""
+    tours = lambda x: x.ants if x.local_search == 2 else (1 if x.local_search else 0)
+    return sum(tours(x) * x.n * (24 + 4 * min(x.k_ls, x.n - 1)) for x in insts)
+
+
+def kernel_line(name, bytes_per_launch, ms, launches):
+    avg_s = (ms / 1000.0) / max(launches, 1)
+    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg_s * 1e6, "launches": launches,
+            "algorithmic_bytes_per_launch": bytes_per_launch}
+
+
+def timing_pass(ctx, decode):
+    """One decode with per-kernel HIP-event timing on: the per-launch
+    durations of construction, 2-opt and update."""
+    ctx.set_timing(True)
+    decode()
+    st = ctx.stats()
+    ctx.set_timing(False)
+    return st
+
+
+def kernel_lines(insts, st, traffic_key=None):
+    lines = {"construct": roofline(insts, st["construct_ms"], st["construct_launches"], traffic_key),
+             "update": kernel_line("iter_end_kernel", update_bytes(insts), st["update_ms"], st["update_launches"])}
+    if st["local_search_launches"]:
+        lines["two_opt"] = kernel_line("local_search_kernel", two_opt_bytes(insts), st["local_search_ms"],
+                                       st["local_search_launches"])
+    return lines
+
+
 def timed_batches(ctx, db, steps, warmup):
-    """Warmup, then `steps` timed hac_decode_batch_dev calls with per-launch
-    HIP-event timing of the construction kernel."""
+    """Warmup, then `steps` timed hac_decode_batch_dev calls on the
+    production path (timing off: the iterations replay a captured graph);
+    then one more call with per-kernel timing for the kernel lines."""
     import torch
     for _ in range(warmup):
         ctx.decode_batch_dev(db)
-    ctx.set_timing(True)
     torch.cuda.synchronize()
-    times, cms, launches = [], 0.0, 0
+    times = []
     t_all = time.perf_counter()
     for _ in range(steps):
         t0 = time.perf_counter()
         ctx.decode_batch_dev(db)
         times.append(time.perf_counter() - t0)
-        st = ctx.stats()
-        cms += st["construct_ms"]
-        launches += st["construct_launches"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_all
-    ctx.set_timing(False)
-    return wall, times, cms, launches
+    st = timing_pass(ctx, lambda: ctx.decode_batch_dev(db))
+    return wall, times, st
 
 
 def plain_sample(ctx, insts, count, batched=None):
@@ -217,17 +291,18 @@ def run_batched(args, hac, insts, cpu, name, desc, plain_count, traffic_key=None
     ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
     ctx = hac.Context(0)
     db = hac.DeviceBatch(insts)
-    wall, times, cms, launches = timed_batches(ctx, db, args.steps, args.warmup)
+    wall, times, st = timed_batches(ctx, db, args.steps, args.warmup)
     batched = db.results()
-    st = ctx.stats()
     lat, psteps, equal = plain_sample(ctx, insts, plain_count, batched)
     assert equal, "plain and batched tours differ"
     plain_dps = len(lat) / sum(lat)
     dps = count * args.steps / wall
+    lines = kernel_lines(insts, st, traffic_key)
     out = base_line(args, f"ant-steps/s, batched decode ({name})", ant_steps * args.steps / wall,
                     1000.0 * wall / args.steps,
                     {"workload": desc, "instances": count, "iterations": insts[0].iterations,
                      "ants": insts[0].ants, "k": insts[0].k, "inputs": "resident in HBM (hac_decode_batch_dev)",
+                     "path": "iterations replayed from a captured hipGraph, kernel timing off",
                      "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
                                       "ants_per_wave": st["ants_per_wave"], "byte_marks": st["byte_marks"]}})
     out.update({
@@ -238,19 +313,53 @@ def run_batched(args, hac, insts, cpu, name, desc, plain_count, traffic_key=None
         "latency_ms": {"batched_p50": 1000 * percentile(times, 0.5), "batched_p99": 1000 * percentile(times, 0.99),
                        "plain_p50": 1000 * percentile(lat, 0.5), "plain_p99": 1000 * percentile(lat, 0.99)},
         "fallback_fraction": st["fallback_steps"] / max(1, st["ant_steps"]),
-        "roofline": roofline(insts, cms, launches, traffic_key),
+        "roofline": lines["construct"],
+        "kernels": {k: v for k, v in lines.items() if k != "construct"},
         "cpu_baseline": cpu,
     })
     ctx.close()
     return out
 
 
+def sub_tsp10k(hac, insts, plain_count=1):
+    """The 8 x n = 10 000 batch with 2-opt on each iteration best: one timed
+    batched decode on the production path, the kernel lines from a timed
+    decode, and plain decodes of the first instances (tours asserted equal)."""
+    import torch
+    ctx = hac.Context(0)
+    db = hac.DeviceBatch(insts)
+    print("bench: tsp10k timing pass", file=sys.stderr, flush=True)
+    st = timing_pass(ctx, lambda: ctx.decode_batch_dev(db))  # also tunes the launch shape
+    print("bench: tsp10k timed step", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.decode_batch_dev(db)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    batched = db.results()
+    print("bench: tsp10k plain decodes", file=sys.stderr, flush=True)
+    lat, _, equal = plain_sample(ctx, insts, plain_count, batched)
+    ctx.close()
+    assert equal, "plain and batched tours differ (tsp10k)"
+    dps, plain_dps = len(insts) / wall, len(lat) / sum(lat)
+    ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
+    lines = kernel_lines(insts, st)
+    return {"workload": "tsp10k: 8 TSP instances, n=10000, top-20 heatmaps, k=20, 100 ants, 200 iterations, "
+                        "neighbour-list 2-opt (20) on each iteration best",
+            "steps": 1, "ms_per_step": 1000 * wall, "ant_steps_per_s": ant_steps / wall,
+            "decodes_per_s": dps, "plain": {"decodes_per_s": plain_dps, "sample": len(lat)},
+            "batched_vs_plain": dps / plain_dps, "equal_gap": equal,
+            "latency_ms": {"batched": 1000 * wall, "plain_p50": 1000 * percentile(lat, 0.5)},
+            "roofline": lines["construct"], "kernels": {k: v for k, v in lines.items() if k != "construct"},
+            "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
+                             "ants_per_wave": st["ants_per_wave"]}}
+
+
 def run_plain(args, hac, inst, cpu, name, desc):
     ctx = hac.Context(0)
     db = hac.DeviceBatch([inst])
-    wall, times, cms, launches = timed_batches(ctx, db, args.steps, args.warmup)
+    wall, times, st = timed_batches(ctx, db, args.steps, args.warmup)
     steps = inst.ants * (inst.n - 1) * inst.iterations
-    st = ctx.stats()
     out = base_line(args, f"ant-steps/s, plain decode ({name})", steps * args.steps / wall,
                     1000.0 * wall / args.steps,
                     {"workload": desc, "instances": 1, "iterations": inst.iterations, "ants": inst.ants,
@@ -260,22 +369,34 @@ def run_plain(args, hac, inst, cpu, name, desc):
     out.update({"decodes_per_s": args.steps / wall,
                 "latency_ms": {"p50": 1000 * percentile(times, 0.5), "p99": 1000 * percentile(times, 0.99)},
                 "fallback_fraction": st["fallback_steps"] / max(1, st["ant_steps"]),
-                "roofline": roofline([inst], cms, launches), "cpu_baseline": cpu})
+                "roofline": roofline([inst], st["construct_ms"], st["construct_launches"]),
+                "kernels": {k: v for k, v in kernel_lines([inst], st).items() if k != "construct"},
+                "cpu_baseline": cpu})
     ctx.close()
     return out
 
 
-def run_serve(args, hac, wl, cpu):
-    """Poisson arrivals of the 40/40/10/10 mix; the rate is 0.7 x the
-    saturated throughput measured by a closed-loop calibration."""
-    kinds = ["tsp500", "tsp1000", "tsp10000", "atsp1000"]
-    count = args.requests
+SERVE_KINDS = ["tsp500", "tsp1000", "tsp10000", "atsp1000"]
+SERVE_FRAC = {"tsp500": 0.4, "tsp1000": 0.4, "tsp10000": 0.1, "atsp1000": 0.1}
+
+
+def serve_specs(count):
+    from paper_2601_19041_amd import workloads as wl
     mix, _ = wl.serve_mix(count, 1.0, seed=1)
-    reqs = [wl.serve_request(k, r) for r, k in enumerate(mix)]
+    return mix, [(k, r, 100) for r, k in enumerate(mix)]
+
+
+def sub_serve(hac, wl, mix, reqs, budget_gb, slots, plain_per_kind=4):
+    """Poisson arrivals of the 40/40/10/10 mix; the rate is 0.7 x the
+    saturated throughput measured by a closed-loop calibration.  The plain
+    baseline decodes `plain_per_kind` requests of each kind alone (the
+    mix-weighted mean time per decode), each checked equal to its served
+    result; latency is reported per request kind, served and alone."""
+    count = len(reqs)
     ctx = hac.Context(0)
-    budget = int(args.serve_budget_gb * (1 << 30))
-    # calibration: the whole request set submitted at once (closed loop)
-    srv = hac.Server(ctx, budget=budget, max_slots=args.slots)
+    budget = int(budget_gb * (1 << 30))
+    print(f"bench: serve calibration, {count} requests at once", file=sys.stderr, flush=True)
+    srv = hac.Server(ctx, budget=budget, max_slots=slots)
     t0 = time.perf_counter()
     tk = [srv.submit(r) for r in reqs]
     for t in tk:
@@ -284,7 +405,8 @@ def run_serve(args, hac, wl, cpu):
     srv.close()
     rate = 0.7 * sat
     _, arrivals = wl.serve_mix(count, rate, seed=2)
-    srv = hac.Server(ctx, budget=budget, max_slots=args.slots)
+    print(f"bench: serve Poisson run at {rate:.1f}/s", file=sys.stderr, flush=True)
+    srv = hac.Server(ctx, budget=budget, max_slots=slots)
     t_start = time.perf_counter()
     tickets = []
     for r, at in zip(reqs, arrivals):
@@ -292,8 +414,7 @@ def run_serve(args, hac, wl, cpu):
         if at > now:
             time.sleep(at - now)
         tickets.append(srv.submit(r))
-    lat = []
-    results = []
+    lat, results = [], []
     for t in tickets:
         tour, L, l = srv.wait(t)
         lat.append(l)
@@ -302,35 +423,53 @@ def run_serve(args, hac, wl, cpu):
     cnt = srv.counters()
     srv.close()
     ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in reqs)
-    # the plain path on the same mix: one request of each kind decoded alone
-    # (and checked against its served result), weighted by the mix fractions
-    frac = {"tsp500": 0.4, "tsp1000": 0.4, "tsp10000": 0.1, "atsp1000": 0.1}
-    per_kind, equal = {}, True
-    for kind in kinds:
-        idx = next((r for r, k in enumerate(mix) if k == kind), None)
-        if idx is None:
-            continue
-        t0 = time.perf_counter()
-        tour, L = ctx.decode(reqs[idx])
-        per_kind[kind] = time.perf_counter() - t0
-        equal &= bool(np.array_equal(tour, results[idx][0]) and L == results[idx][1])
+    print("bench: serve plain decodes", file=sys.stderr, flush=True)
+    per_kind, alone, equal = {}, {}, True
+    for kind in SERVE_KINDS:
+        idx = [r for r, k in enumerate(mix) if k == kind][:plain_per_kind]
+        ts = []
+        for r in idx:
+            t0 = time.perf_counter()
+            tour, L = ctx.decode(reqs[r])
+            ts.append(time.perf_counter() - t0)
+            equal &= bool(np.array_equal(tour, results[r][0]) and L == results[r][1])
+        if ts:
+            alone[kind] = ts
     assert equal, "served and plain tours differ"
     ctx.close()
-    mean_plain_s = sum(frac[k] * t for k, t in per_kind.items()) / sum(frac[k] for k in per_kind)
+    for kind in SERVE_KINDS:
+        ls = [lat[r] for r, k in enumerate(mix) if k == kind]
+        if ls:
+            per_kind[kind] = {"requests": len(ls), "served_p50_ms": 1000 * percentile(ls, 0.5),
+                              "served_p99_ms": 1000 * percentile(ls, 0.99),
+                              "alone_mean_ms": 1000 * float(np.mean(alone[kind])) if kind in alone else None,
+                              "alone_decodes": len(alone.get(kind, []))}
+    mean_plain_s = sum(SERVE_FRAC[k] * float(np.mean(t)) for k, t in alone.items()) / \
+        sum(SERVE_FRAC[k] for k in alone)
     plain_dps = 1.0 / mean_plain_s
-    plain_lat = list(per_kind.values())
-    out = base_line(args, "ant-steps/s, served decode (Poisson mix)", ant_steps / wall, 1000.0 * wall,
-                    {"workload": f"serve: {count} requests, 40/40/10/10 TSP500/TSP1000/TSP10000/ATSP1000, "
-                                 f"100 iterations each, Poisson arrivals at {rate:.2f}/s",
-                     "budget_gb": args.serve_budget_gb, "max_slots": args.slots})
+    return {"workload": f"serve: {count} requests, 40/40/10/10 TSP500/TSP1000/TSP10000/ATSP1000, "
+                        f"100 iterations each, Poisson arrivals at {rate:.2f}/s",
+            "budget_gb": budget_gb, "max_slots": slots, "wall_s": wall, "ant_steps_per_s": ant_steps / wall,
+            "decodes_per_s": count / wall,
+            "latency_ms": {"p50": 1000 * percentile(lat, 0.5), "p99": 1000 * percentile(lat, 0.99)},
+            "per_kind": per_kind,
+            "plain": {"decodes_per_s": plain_dps, "decodes_per_kind": plain_per_kind,
+                      "note": "requests of each kind decoded alone, mean time weighted by the mix"},
+            "served_vs_plain": (count / wall) / plain_dps, "equal_gap": equal,
+            "saturated_decodes_per_s": sat, "arrival_rate_per_s": rate, "server": cnt}
+
+
+def run_serve(args, hac, wl, cpu):
+    mix, specs = serve_specs(args.requests)
+    reqs = generate(specs)
+    sub = sub_serve(hac, wl, mix, reqs, args.serve_budget_gb, args.slots)
+    ant_steps_s = sub.pop("ant_steps_per_s")
+    out = base_line(args, "ant-steps/s, served decode (Poisson mix)", ant_steps_s, 1000.0 * sub["wall_s"],
+                    {"workload": sub.pop("workload"), "budget_gb": sub.pop("budget_gb"),
+                     "max_slots": sub.pop("max_slots")})
     out["steps"] = 1
-    out.update({"decodes_per_s": count / wall, "latency_ms": {"p50": 1000 * percentile(lat, 0.5),
-                                                             "p99": 1000 * percentile(lat, 0.99)},
-                "plain": {"decodes_per_s": plain_dps, "seconds_per_kind": per_kind,
-                          "note": "one request per kind decoded alone, weighted by the mix"},
-                "served_vs_plain": (count / wall) / plain_dps, "equal_gap": equal,
-                "saturated_decodes_per_s": sat, "arrival_rate_per_s": rate,
-                "server": cnt, "cpu_baseline": cpu})
+    out.update(sub)
+    out["cpu_baseline"] = cpu
     return out
 
 
@@ -359,9 +498,8 @@ def run_paper(args, hac, wl):
     ctx = hac.Context(0)
     db = hac.DeviceBatch(insts)
     print(f"paper{n} ls={ls}: batched decode of {count} instances", file=sys.stderr, flush=True)
-    wall, times, cms, launches = timed_batches(ctx, db, args.steps, args.warmup)
+    wall, times, st = timed_batches(ctx, db, args.steps, args.warmup)
     batched = db.results()
-    st = ctx.stats()
     print(f"paper{n} ls={ls}: batched {wall:.1f} s; plain decodes", file=sys.stderr, flush=True)
     lat, psteps, equal = plain_sample(ctx, insts, max(1, min(args.plain_sample, count)), batched)
     assert equal, "plain and batched tours differ"
@@ -383,7 +521,8 @@ def run_paper(args, hac, wl):
         "batched_vs_plain": (count * args.steps / wall) / (len(lat) / sum(lat)),
         "equal_gap": equal,
         "mean_length": mean_len,
-        "roofline": roofline(insts, cms, launches),
+        "roofline": roofline(insts, st["construct_ms"], st["construct_launches"]),
+        "kernels": {k: v for k, v in kernel_lines(insts, st).items() if k != "construct"},
         "paper_context": None if ctx_paper is None else dict(
             ctx_paper, hardware="8 CPU cores (model unstated)", note="different instances and heatmaps; "
             "context only"),
@@ -457,10 +596,12 @@ def main():
     ap.add_argument("--instances", type=int, default=None, help="paper workload: instances in the batch")
     ap.add_argument("--iterations", type=int, default=None, help="override the workload's iteration count")
     ap.add_argument("--plain-sample", type=int, default=16)
-    ap.add_argument("--cpu-sample", type=int, default=16)
-    ap.add_argument("--cpu-iterations", type=int, default=300)
+    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--cpu-iterations", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--requests", type=int, default=240)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batch64: leave out the tsp10k and serve sub-objects")
+    ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=None,
@@ -490,18 +631,32 @@ def main():
         run = {"paper": run_paper, "ablation": run_ablation, "diagnostics": run_diagnostics}[args.workload]
         print(json.dumps(run(args, hac, wl)))
         return
+    # inputs are generated and the CPU leg runs first, on the host cores,
+    # before this process initialises the GPU
+    extras = args.workload == "batch64" and not args.no_extras
+    t_gen = time.perf_counter()
     if args.workload == "batch64":
-        insts = wl.batch64(64, iterations=it or 500)
+        insts = generate([("batch64", x, it or 500) for x in range(64)])
     elif args.workload == "tsp100":
         insts = [wl.tsp100(iterations=it or 100)]
     elif args.workload == "tsp500":
         insts = [wl.tsp500(iterations=it or 1000)]
     elif args.workload == "tsp10k":
-        insts = wl.tsp10k(8, iterations=it or 200)
+        insts = generate([("tsp10k", x, it or 200) for x in range(8)])
     else:
-        insts = [wl.serve_request("tsp500", 0)]
-    # the CPU leg runs first, before this process initialises the GPU
-    cpu = None if args.no_cpu else cpu_baseline(insts, args.cpu_sample, args.cpu_iterations)
+        insts = None
+    if extras:
+        tsp10k_insts = generate([("tsp10k", x, 200) for x in range(8)])
+        mix, specs = serve_specs(args.requests)
+        serve_reqs = generate(specs)
+    print(f"bench: inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    if args.workload == "serve":
+        mix, specs = serve_specs(args.requests)
+        cpu_insts = generate(specs[:args.cpu_sample])
+    else:
+        cpu_insts = insts
+    cpu = None if args.no_cpu else cpu_baseline(cpu_insts, args.cpu_sample, args.cpu_iterations)
+    print("bench: CPU baseline done", file=sys.stderr, flush=True)
 
     import paper_2601_19041_amd as hac
 
@@ -509,6 +664,9 @@ def main():
         out = run_batched(args, hac, insts, cpu, "64 TSP instances, n 500-1000",
                           "batch64: 64 TSP instances, n uniform on [500,1000], top-10 SoftDist heatmaps, "
                           "k=10, 50 ants, 500 iterations, no local search", args.plain_sample, "batch64")
+        if extras:
+            out["tsp10k"] = sub_tsp10k(hac, tsp10k_insts)
+            out["serve"] = sub_serve(hac, wl, mix, serve_reqs, args.serve_budget_gb, args.slots)
     elif args.workload == "tsp10k":
         out = run_batched(args, hac, insts, cpu, "8 TSP instances, n 10000, 2-opt",
                           "tsp10k: 8 TSP instances, n=10000, top-20 heatmaps, k=20, 100 ants, 200 iterations, "

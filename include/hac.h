@@ -42,7 +42,7 @@ typedef int32_t hac_status;
 #define HAC_OK 0
 #define HAC_EINVAL (-1)       /* malformed instance, heatmap or parameters   */
 #define HAC_ENOMEM (-2)       /* device memory or budget cannot hold it      */
-#define HAC_EDEVICE (-3)      /* a HIP runtime call failed                   */
+#define HAC_EDEVICE (-3)      /* a HIP call or a kernel's own check failed   */
 #define HAC_EUNSUPPORTED (-4) /* valid for the method, not for this library  */
 #define HAC_EBUSY (-5)        /* a served request is not finished yet        */
 #define HAC_ECANCELLED (-6)   /* a served request was cancelled              */
@@ -134,6 +134,13 @@ typedef struct hac_stats {
                                   /* coordinates                            */
   int32_t ants_per_wave;          /* 1-4 ants per wave, 16 lanes each       */
   int32_t byte_marks;             /* 1: visited marks are bytes, 0: bits    */
+  /* with timing enabled, as construct_ms / construct_launches: summed      */
+  /* HIP-event times and launch counts of the 2-opt kernel (local search)   */
+  /* and of the end-of-iteration kernel (control + pheromone update)        */
+  double local_search_ms;
+  int64_t local_search_launches;
+  double update_ms;
+  int64_t update_launches;
 } hac_stats;
 
 /* Fills the paper's settings (Section IV-C): m = 32, I = 5000, k = 20,
@@ -160,8 +167,10 @@ hac_status hac_create(hac_ctx** out, int32_t device, void* stream, uint64_t hbm_
 void hac_destroy(hac_ctx* ctx);
 /* Detail text of the last failure on this context ("" if none). */
 const char* hac_last_error(const hac_ctx* ctx);
-/* 1 enables per-kernel HIP-event timing of the construction kernel (it
- * adds a few microseconds per iteration); 0 disables it (default). */
+/* 1 enables per-kernel HIP-event timing of the construction, 2-opt and
+ * end-of-iteration kernels (hac_stats); the iterations then run as
+ * separate launches instead of a replayed graph, which adds a few
+ * microseconds per iteration.  0 disables it (default). */
 hac_status hac_set_timing(hac_ctx* ctx, int32_t enable);
 
 /* Decodes one instance (the plain path: one instance per launch

@@ -77,7 +77,9 @@ class hac_stats(ctypes.Structure):
                 ("r_hat", ctypes.c_double), ("l_nn", ctypes.c_double),
                 ("ants_per_block", ctypes.c_int32), ("lds_staged", ctypes.c_int32),
                 ("ants_per_wave", ctypes.c_int32),
-                ("byte_marks", ctypes.c_int32)]
+                ("byte_marks", ctypes.c_int32),
+                ("local_search_ms", ctypes.c_double), ("local_search_launches", ctypes.c_int64),
+                ("update_ms", ctypes.c_double), ("update_launches", ctypes.c_int64)]
 
 
 # every symbol include/hac.h declares

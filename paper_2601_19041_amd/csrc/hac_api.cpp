@@ -1038,8 +1038,8 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   const double prep_ms = ms_since(t0);
   const auto t1 = Clock::now();
 
-  double construct_ms = 0.0;
-  int64_t launches = 0;
+  double construct_ms = 0.0, ls_ms = 0.0, update_ms = 0.0;
+  int64_t launches = 0, ls_launches = 0, update_launches = 0;
   LaunchShape used{0, 0, 0, 0, 0};
   if (m > 0) {
     bool any_ls = false;
@@ -1057,6 +1057,12 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       shape = tune_shape(hs, d_descs, s, c->scratch, &ok);
       if (!ok) return set_err(c, HAC_EDEVICE, "autotuner launch failed");
       CTX_HIP(launch_init(d_descs, m, s));  // undo the tuner's fallback counts
+    }
+    if (const char* f = std::getenv("HAC_FORCE_DEVICE_ERROR")) {
+      // test hook: flags instance f's error word as a failing kernel check
+      // would, so that the error path can be exercised without one
+      const int32_t x = std::atoi(f);
+      if (x >= 0 && x < m) CTX_HIP(hipMemsetAsync(&hs[x].d.st->err, 0xff, sizeof(uint32_t), s));
     }
     used = shape;
     std::vector<BlockMap> map = build_block_map(hs, shape.ants_per_block);
@@ -1077,27 +1083,40 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       return launch_iter_end(d_descs, m, s);
     };
     if (c->timing) {
-      // per-iteration launches with HIP events around each construction
-      while ((int)c->events.size() < 2 * max_iter) {
+      // per-iteration launches with HIP events around each kernel: e[4 it]
+      // .. e[4 it + 3] bracket construction, 2-opt and the update
+      while ((int)c->events.size() < 4 * max_iter) {
         hipEvent_t e;
         CTX_HIP(hipEventCreate(&e));
         c->events.push_back(e);
       }
       for (int32_t it = 0; it < max_iter; ++it) {
-        CTX_HIP(hipEventRecord(c->events[2 * it], s));
+        hipEvent_t* ev = &c->events[4 * it];
+        CTX_HIP(hipEventRecord(ev[0], s));
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
                                       shape.bytes, shape.kmax, lds, s));
-        CTX_HIP(hipEventRecord(c->events[2 * it + 1], s));
+        CTX_HIP(hipEventRecord(ev[1], s));
         if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, s));
+        CTX_HIP(hipEventRecord(ev[2], s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
+        CTX_HIP(hipEventRecord(ev[3], s));
       }
       CTX_HIP(hipStreamSynchronize(s));
       for (int32_t it = 0; it < max_iter; ++it) {
+        hipEvent_t* ev = &c->events[4 * it];
         float ms = 0;
-        CTX_HIP(hipEventElapsedTime(&ms, c->events[2 * it], c->events[2 * it + 1]));
+        CTX_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
         construct_ms += ms;
+        if (any_ls) {
+          CTX_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+          ls_ms += ms;
+        }
+        CTX_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        update_ms += ms;
       }
       launches = max_iter;
+      ls_launches = any_ls ? max_iter : 0;
+      update_launches = max_iter;
     } else if (max_iter > 0) {
       // a graph of G iterations replayed; surplus iterations are no-ops
       const int32_t G = std::min<int32_t>(max_iter, 16);
@@ -1141,6 +1160,10 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     CTX_HIP(stage_copies(c->stage, items, at, blob.data(), blob.size(), true, s));
     CTX_HIP(hipStreamSynchronize(s));
     for (int32_t y = 0; y < m; ++y) std::memcpy(&sts[y], blob.data() + at[y], sizeof(State));
+    for (int32_t y = 0; y < m; ++y)
+      if (sts[y].err || std::isnan(lens[y]))
+        return set_err(c, HAC_EDEVICE, "instance " + std::to_string(which[y]) +
+                                           ": a construction step broke its pick contract on the device");
     if (!outputs_on_device)
       for (int32_t y = 0; y < m; ++y)
         CTX_HIP(hipMemcpyAsync(tours_out[which[y]], out_ptrs[y], 4 * (size_t)hs[y].lay.n,
@@ -1173,6 +1196,10 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   st.total_ms = ms_since(t0);
   st.construct_ms = construct_ms;
   st.construct_launches = launches;
+  st.local_search_ms = ls_ms;
+  st.local_search_launches = ls_launches;
+  st.update_ms = update_ms;
+  st.update_launches = update_launches;
   st.ants_per_block = used.ants_per_block;
   st.lds_staged = used.staged;
   st.ants_per_wave = used.rows_per_wave;

@@ -20,6 +20,10 @@ struct State {
   float tmax_f, tmin_f; // their FP32 casts, used by the update
   double min_gain;              // 2-opt gain threshold, 1e-9 L_nn / n
   unsigned long long fallbacks;  // nearest-unvisited steps so far
+  // nonzero once a kernel found its own contract broken (the construction
+  // step picked other than exactly one slot of an open row); the instance
+  // then stops, and the host reports HAC_EDEVICE
+  uint32_t err;
 };
 
 // Uniform grid over the coordinates of a coordinate instance with
@@ -81,6 +85,19 @@ struct InstDesc {
   double* tr_lgb;             // [iterations] or null
   int32_t* tr_elite;          // [iterations] or null
 };
+
+// The pick contract of a construction step, over a wave's four 16-lane rows
+// at once: `hits` has a lane's bit set when one of its slots passed the
+// prefix test, `exh` when its row has no open slot.  An open row must have
+// exactly one hit and an exhausted row none.  Scalar bit arithmetic on the
+// two wave masks (16-bit fields): X gives an exhausted row one bit, then no
+// field of X may be zero (the borrow test) and none may hold two bits.
+// Returns nonzero when the contract is broken.
+__host__ __device__ inline uint64_t pick_contract_broken(uint64_t hits, uint64_t exh) {
+  constexpr uint64_t L = 0x0001000100010001ull, H = 0x8000800080008000ull;
+  const uint64_t X = hits | (exh & L);
+  return (hits & exh) | ((X - L) & ~X & H) | (X & (X - L));
+}
 
 // One entry per construction block: instance and first ant (inst < 0: idle)
 struct BlockMap {

@@ -850,6 +850,7 @@ __global__ void __launch_bounds__(256) init_kernel(const InstDesc* insts) {
     st->restarts = 0;
     st->ib = 0;
     st->fallbacks = 0;
+    st->err = 0;
     s_tmax = (float)tmax;
   }
   __syncthreads();
@@ -1169,6 +1170,7 @@ struct AntRows {
   bool live;
   int cur;       // the row's current node (same in all its lanes)
   uint32_t fallbacks;
+  uint32_t* err;  // the instance's error word (State::err)
 
   __device__ __forceinline__ uint64_t entry(uint32_t a) const {
     if constexpr (STAGED == 1) {
@@ -1260,6 +1262,11 @@ struct AntRows {
       }
       hit |= h;
     }
+    // the pick contract, checked on scalar masks beside the OR butterflies
+    const bool exhausted = sh >= 256;
+    const uint64_t exh_mask = __builtin_amdgcn_ballot_w64(exhausted);
+    uint64_t broken = pick_contract_broken(__builtin_amdgcn_ballot_w64(hit), exh_mask);
+    asm volatile("" : "+s"(broken));  // evaluated here, in the slots between the DPP levels
     int j = (int)row_reduce(pick, OpOr());
     // the next row's byte offset, alongside j.  At most one lane of a row
     // holds a nonzero offset, so after three levels one half of the row holds
@@ -1282,8 +1289,15 @@ struct AntRows {
       else
         vis_g[wi] = wv;
     }
-    const bool exhausted = sh >= 256;
-    if (__builtin_amdgcn_ballot_w64(exhausted)) {
+    if (__builtin_expect(broken != 0, 0)) {
+      // never taken when the arithmetic above holds; if it does not, the
+      // instance is flagged and the row continues from an in-range node, so
+      // that no address is formed from a wrong prefix
+      if (lane_id() == 0) atomicOr(err, 1u);
+      j = (int)min((uint32_t)j, (uint32_t)(n - 1));
+      set_row(__umul24((uint32_t)j, k8));
+    }
+    if (exh_mask) {
       j = fallback(exhausted, j, gl);
       if (exhausted) set_row(__umul24((uint32_t)j, k8));
     }
@@ -1363,7 +1377,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   if (bm.inst < 0) return;
   const InstDesc I = insts[bm.inst];  // by value: the fields stay in registers
   const int t = I.st->t;
-  if (t > I.iterations) return;
+  if (t > I.iterations || I.st->err) return;
   extern __shared__ uint32_t lds[];
   const int n = I.n, k = I.k, lane = lane_id(), wave = threadIdx.x / WAVE;
   const int rpw = rows_per_wave;  // rows of a wave that carry ants (the others shadow row 0)
@@ -1470,6 +1484,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   A.set_row(__umul24((uint32_t)start, A.k8));
   if (A.u == 0 && A.live) A.mark(start);
   A.fallbacks = 0;
+  A.err = &I.st->err;
   A.left = n - 1;
   int tb = start;     // lane (s mod 16) holds T[s] of the current block of 16 steps
   int carry = start;  // T[s0 - 1]
@@ -1544,7 +1559,7 @@ __device__ void iteration_best_wave(const InstDesc& D, int& ib, double& lib) {
 template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
-  if (!D.local_search || D.st->t > D.iterations) return;
+  if (!D.local_search || D.st->t > D.iterations || D.st->err) return;
   const int n = D.n;
   if (D.local_search == 2) {
     for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
@@ -1599,7 +1614,7 @@ __global__ void __launch_bounds__(1024) iter_end_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   State* st = D.st;
   const int t = st->t;
-  if (t > D.iterations) return;
+  if (t > D.iterations || st->err) return;
   const int n = D.n, k = D.k, tid = threadIdx.x, nthr = blockDim.x;
   __shared__ double s_key[32];
   __shared__ int s_idx[32];
@@ -1793,6 +1808,12 @@ __global__ void __launch_bounds__(64) finish_kernel(const InstDesc* insts, int32
                                                     double* out_lens) {
   const InstDesc& D = insts[blockIdx.x];
   const int n = D.n, lane = lane_id();
+  if (D.st->err) {
+    // a broken kernel contract: no tour is written, and the length is NaN,
+    // which the host turns into HAC_EDEVICE
+    if (lane == 0) out_lens[blockIdx.x] = __builtin_nan("");
+    return;
+  }
   const int32_t* tg = D.t_gb;
   int r0 = 0x7fffffff;
   for (int s = lane; s < n; s += WAVE)

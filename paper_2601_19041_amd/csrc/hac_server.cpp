@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -160,7 +161,6 @@ struct hac_server {
   uint64_t next_ticket = 1;
   int64_t admitted = 0, completed = 0;
   int32_t peak_slots = 0;
-  std::string err;
 };
 
 namespace {
@@ -191,10 +191,12 @@ void fail_active(hac_server* S, Lane& LN, hac_status code) {
   S->cv_loop.notify_all();
 }
 
+// A failed HIP call fails the lane's requests with HAC_EDEVICE; the call
+// that failed is not reported further.
 bool hip_ok(hac_server* S, hipError_t e, const char* what) {
-  if (e == hipSuccess) return true;
-  S->err = std::string(what) + ": " + hipGetErrorString(e);
-  return false;
+  (void)S;
+  (void)what;
+  return e == hipSuccess;
 }
 
 void serve_lane(hac_server* S, Lane* lane_ptr) {
@@ -297,7 +299,6 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
       if (ok) {
         std::string why;
         ps = prepare_instances(hs, d_new, s, &why);
-        if (ps != HAC_OK) S->err = why;
       }
       std::lock_guard<std::mutex> g(S->mu);
       for (size_t x = 0; x < fresh.size(); ++x) {
@@ -347,7 +348,6 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
         // construction only reads the search state, so timing it here
         // leaves every instance's trajectory unchanged
         shape = tune_shape(hs, d_descs, s, LN.scratch, &ok);
-        if (!ok) S->err = "autotuner launch failed";
       }
       if (ok) {
         map = build_block_map(hs, shape.ants_per_block);
@@ -414,7 +414,10 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
       Slot& sl = LN.active[x];
       const bool fin = std::find(finished.begin(), finished.end(), x) != finished.end();
       if (fin || sl.req->cancel || S->stop) {
-        if (fin && !sl.req->cancel) {
+        if (fin && !sl.req->cancel && std::isnan(lens[x])) {
+          // the instance stopped on a broken kernel contract (no tour written)
+          finish_request(S, sl.req, FAILED, HAC_EDEVICE);
+        } else if (fin && !sl.req->cancel) {
           sl.req->length = lens[x];
           finish_request(S, sl.req, DONE, HAC_OK);
         } else {

@@ -94,8 +94,10 @@ def uniform_coords(n: int, rng: np.random.Generator) -> np.ndarray:
 
 
 def _pairwise(coords: np.ndarray, rows: np.ndarray) -> np.ndarray:
-    d = coords[rows, None, :] - coords[None, :, :]
-    return np.sqrt((d * d).sum(-1))
+    # sqrt(dx*dx + dy*dy), the same FP64 operations as a sum over the axis
+    dx = coords[rows, 0][:, None] - coords[None, :, 0]
+    dy = coords[rows, 1][:, None] - coords[None, :, 1]
+    return np.sqrt(dx * dx + dy * dy)
 
 
 def _topk_rows(dist_rows: np.ndarray, rows: np.ndarray, topk: int) -> np.ndarray:
@@ -294,30 +296,34 @@ def tsp500(instance: int = 0, seed: Optional[int] = None, iterations: int = 1000
                     seed=seed if seed is not None else 1 + instance, name=f"tsp500#{instance}")
 
 
+def batch64_instance(x: int, iterations: int = 500) -> Instance:
+    """Instance x of the 64-instance batch (see batch64)."""
+    rng = _rng(WL_BATCH64, x)
+    n = 500 + int(rng.integers(0, 501))
+    xy = uniform_coords(n, rng)
+    heat = softdist_heatmap(xy, 10)
+    return Instance(n, "coords", True, xy, None, heat, ants=50, iterations=iterations,
+                    k=10, seed=1 + x, name=f"batch64#{x}")
+
+
 def batch64(count: int = 64, iterations: int = 500) -> List[Instance]:
     """64 instances, n uniform on [500, 1000], top-10 heatmap, k=10, 50 ants, 500 iterations."""
-    out = []
-    for x in range(count):
-        rng = _rng(WL_BATCH64, x)
-        n = 500 + int(rng.integers(0, 501))
-        xy = uniform_coords(n, rng)
-        heat = softdist_heatmap(xy, 10)
-        out.append(Instance(n, "coords", True, xy, None, heat, ants=50, iterations=iterations,
-                            k=10, seed=1 + x, name=f"batch64#{x}"))
-    return out
+    return [batch64_instance(x, iterations) for x in range(count)]
+
+
+def tsp10k_instance(x: int, iterations: int = 200, n: int = 10000) -> Instance:
+    """Instance x of the 10 000-node batch (see tsp10k)."""
+    rng = _rng(WL_TSP10K, x)
+    xy = uniform_coords(n, rng)
+    heat = softdist_heatmap(xy, 20)
+    return Instance(n, "coords", True, xy, None, heat, ants=100, iterations=iterations,
+                    k=20, local_search=1, k_ls=20, seed=1 + x, name=f"tsp10k#{x}")
 
 
 def tsp10k(count: int = 8, iterations: int = 200, n: int = 10000) -> List[Instance]:
     """8 instances of n=10000, top-20 heatmap, k=20, 100 ants, 200 iterations,
     neighbour-list 2-opt (20 neighbours) on each iteration-best tour."""
-    out = []
-    for x in range(count):
-        rng = _rng(WL_TSP10K, x)
-        xy = uniform_coords(n, rng)
-        heat = softdist_heatmap(xy, 20)
-        out.append(Instance(n, "coords", True, xy, None, heat, ants=100, iterations=iterations,
-                            k=20, local_search=1, k_ls=20, seed=1 + x, name=f"tsp10k#{x}"))
-    return out
+    return [tsp10k_instance(x, iterations, n) for x in range(count)]
 
 
 def paper_budget(n: int, count: int = 1, local_search: int = 0, iterations: int = 5000,

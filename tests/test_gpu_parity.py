@@ -307,3 +307,23 @@ def test_heatmap_diagnostics_rejects_bad_tours(ctx):
         with pytest.raises(hac.HacError) as e:
             ctx.diagnostics(inst, bad)
         assert e.value.status == hac.HAC_EINVAL
+
+
+def test_device_error_word_reported(ctx, monkeypatch):
+    """When a kernel's own check flags an instance (forced here from the
+    host through the error word, so no kernel misbehaves), every kernel of
+    that instance stops, the call returns HAC_EDEVICE and the outputs stay
+    untouched; the context then decodes normally again."""
+    import paper_2601_19041_amd as hac
+    inst = wl.tsp100(iterations=6)
+    other = wl.random_instance(60, seed=3, ants=6, iterations=6)
+    print("case forced device error word", flush=True)
+    monkeypatch.setenv("HAC_FORCE_DEVICE_ERROR", "0")
+    tour, L = ctx.decode(inst, raise_on_error=False)
+    assert ctx.status == hac.HAC_EDEVICE and "pick contract" in ctx.last_error()
+    assert not tour.any() and L == 0.0
+    with pytest.raises(hac.HacError) as e:
+        ctx.decode_batch([other, inst])
+    assert e.value.status == hac.HAC_EDEVICE
+    monkeypatch.delenv("HAC_FORCE_DEVICE_ERROR")
+    _same(ctx.decode(inst), oracle.decode(inst), "after the error")
