@@ -141,6 +141,9 @@ typedef struct hac_stats {
   int64_t local_search_launches;
   double update_ms;
   int64_t update_launches;
+  int32_t geo_mode;  /* construction: how an exhausted row consults its     */
+                     /* geometric list before a scan: 0 not at all, 1 int32 */
+                     /* lists loaded every step, 2 uint16 lists a step ahead */
 } hac_stats;
 
 /* Fills the paper's settings (Section IV-C): m = 32, I = 5000, k = 20,

@@ -79,7 +79,8 @@ class hac_stats(ctypes.Structure):
                 ("ants_per_wave", ctypes.c_int32),
                 ("byte_marks", ctypes.c_int32),
                 ("local_search_ms", ctypes.c_double), ("local_search_launches", ctypes.c_int64),
-                ("update_ms", ctypes.c_double), ("update_launches", ctypes.c_int64)]
+                ("update_ms", ctypes.c_double), ("update_launches", ctypes.c_int64),
+                ("geo_mode", ctypes.c_int32)]
 
 
 # every symbol include/hac.h declares

@@ -157,6 +157,7 @@ size_t Layout::bytes() const {
   b += align256(4 * (nn + 1)) + align256(4 * (size_t)nnz) + align256(4 * (size_t)nnz);
   b += align256(4 * nk) + align256(8 * nk + 16) + 3 * align256(4 * nk + 16);
   b += align256(4 * nn * (size_t)kg);
+  b += n <= 65535 ? align256(128 * nn) : 0;
   b += align256(4 * nn * (size_t)ants) + align256(8 * (size_t)ants);
   b += 6 * align256(4 * nn);
   b += ls ? align256(12 * nn * (size_t)ls_tours) : 0;
@@ -185,6 +186,7 @@ void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve) {
   d.tau = (float*)carve(4 * nk + 16);
   d.w = (float*)carve(4 * nk + 16);
   d.geo = (int32_t*)carve(4 * nn * (size_t)L.kg);
+  d.geo16 = L.n <= 65535 ? (uint16_t*)carve(128 * nn) : nullptr;
   d.tours = (int32_t*)carve(4 * nn * (size_t)L.ants);
   d.lens = (double*)carve(8 * (size_t)L.ants);
   d.t_gb = (int32_t*)carve(4 * nn);
@@ -547,9 +549,12 @@ static void tune_cache_load() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char key[256];
-  int a, st, rpw;
-  while (std::fscanf(f, "%255s %d %d %d", key, &a, &st, &rpw) == 4)
-    g_tune_cache[key] = LaunchShape{a, st, 0, rpw};
+  int a, st, rpw, geo;
+  while (std::fscanf(f, "%255s %d %d %d %d", key, &a, &st, &rpw, &geo) == 5) {
+    LaunchShape sh{a, st, 0, rpw, 0};
+    sh.geo = geo;
+    g_tune_cache[key] = sh;
+  }
   std::fclose(f);
 }
 
@@ -559,8 +564,8 @@ static void tune_cache_store() {
   FILE* f = std::fopen(path, "w");
   if (!f) return;
   for (auto& kv : g_tune_cache)
-    std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged,
-                 kv.second.rows_per_wave);
+    std::fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.ants_per_block, kv.second.staged,
+                 kv.second.rows_per_wave, kv.second.geo);
   std::fclose(f);
 }
 
@@ -580,6 +585,17 @@ static bool shape_fits(const std::vector<HostInst>& hs, LaunchShape sh) {
       return false;
   }
   return true;
+}
+
+std::vector<int32_t> geo_modes(const std::vector<HostInst>& hs, int32_t staged) {
+  bool all16 = true;
+  for (auto& h : hs) all16 &= h.lay.n <= 65535;
+  if (const char* f = std::getenv("HAC_GEO_MODE")) {
+    const int m = std::atoi(f);
+    if (m == 0 || m == 1 || (m == 2 && all16)) return {m};
+  }
+  if (staged) return {1};
+  return {0, all16 ? 2 : 1};
 }
 
 int32_t batch_max_k(const std::vector<HostInst>& hs) {
@@ -608,7 +624,7 @@ static std::string shape_key(const std::vector<HostInst>& hs) {
   while ((1 << nb) < max_n) nb++;
   int ab = 0;
   while ((1ll << ab) < ants) ab++;
-  return "gfx950/n" + std::to_string(nb) + "/k" + std::to_string(k) + "/a" + std::to_string(ab) +
+  return "gfx950v2/n" + std::to_string(nb) + "/k" + std::to_string(k) + "/a" + std::to_string(ab) +
          (hs[0].lay.coords ? "/euc" : "/mat");
 }
 
@@ -627,6 +643,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
       if (const char* bits = std::getenv("HAC_BIT_MARKS")) {
         if (bits[0] == '1') sh.bytes = 0;  // pins bit marks (shows both give the same tours)
       }
+      sh.geo = geo_modes(hs, sh.staged)[0];
       if (sh.ants_per_block <= 16 * sh.rows_per_wave && shape_fits(hs, sh)) return sh;
     }
   }
@@ -638,6 +655,9 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     if (it != g_tune_cache.end()) {
       LaunchShape sh = with_marks(hs, {it->second.ants_per_block, it->second.staged, kmax,
                                        it->second.rows_per_wave, 0});
+      sh.geo = it->second.geo;
+      const std::vector<int32_t> gm = geo_modes(hs, sh.staged);
+      if (std::find(gm.begin(), gm.end(), sh.geo) == gm.end()) sh.geo = gm[0];
       if (shape_fits(hs, sh)) return sh;
     }
   }
@@ -653,10 +673,15 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
   for (int rpw : {4, 2, 1})
     for (int waves : {1, 2, 4, 8, 16})
       for (int st : forms) {
-        const LaunchShape sh = with_marks(hs, {rpw * waves, st, kmax, rpw, 0});
-        if (shape_fits(hs, sh)) cands.push_back(sh);
+        LaunchShape sh = with_marks(hs, {rpw * waves, st, kmax, rpw, 0});
+        if (!shape_fits(hs, sh)) continue;
+        for (int32_t g : geo_modes(hs, st)) {
+          sh.geo = g;
+          cands.push_back(sh);
+        }
       }
   LaunchShape best{4, 0, kmax, 4, 0};
+  best.geo = geo_modes(hs, 0)[0];
   float best_ms = 1e30f;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -681,7 +706,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);
       (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block,
-                             sh.rows_per_wave, sh.staged, sh.bytes, sh.kmax, shape_lds(hs, sh), s);
+                             sh.rows_per_wave, sh.staged, sh.bytes, sh.kmax, shape_lds(hs, sh), sh.geo, s);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) {
         *ok = false;
@@ -1074,7 +1099,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     const int32_t blocks = (int32_t)map.size();
     auto one_iteration = [&]() -> hipError_t {
       hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
-                                      shape.bytes, shape.kmax, lds, s);
+                                      shape.bytes, shape.kmax, lds, shape.geo, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
         e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, s);
@@ -1094,7 +1119,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
         hipEvent_t* ev = &c->events[4 * it];
         CTX_HIP(hipEventRecord(ev[0], s));
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
-                                      shape.bytes, shape.kmax, lds, s));
+                                      shape.bytes, shape.kmax, lds, shape.geo, s));
         CTX_HIP(hipEventRecord(ev[1], s));
         if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, s));
         CTX_HIP(hipEventRecord(ev[2], s));
@@ -1163,7 +1188,8 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     for (int32_t y = 0; y < m; ++y)
       if (sts[y].err || std::isnan(lens[y]))
         return set_err(c, HAC_EDEVICE, "instance " + std::to_string(which[y]) +
-                                           ": a construction step broke its pick contract on the device");
+                                           ": an ant's tour failed its permutation check on the device "
+                                           "(a construction step broke its pick contract)");
     if (!outputs_on_device)
       for (int32_t y = 0; y < m; ++y)
         CTX_HIP(hipMemcpyAsync(tours_out[which[y]], out_ptrs[y], 4 * (size_t)hs[y].lay.n,
@@ -1204,6 +1230,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   st.lds_staged = used.staged;
   st.ants_per_wave = used.rows_per_wave;
   st.byte_marks = used.bytes;
+  st.geo_mode = used.geo;
   for (int32_t y = 0; y < m; ++y) {
     st.ant_steps += (int64_t)hs[y].p.ants * (hs[y].lay.n - 1) * hs[y].p.iterations;
     st.fallback_steps += (int64_t)sts[y].fallbacks;

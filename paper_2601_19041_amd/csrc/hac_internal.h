@@ -64,6 +64,9 @@ struct InstDesc {
   float* tau;                 // [n][k]
   float* w;                   // [n][k]  tau * S
   int32_t* geo;               // [n][kg] geometric nearest neighbours
+  uint16_t* geo16;            // [n][64] the same lists as uint16, rows padded to 64
+                              // entries (n <= 65535, else null): one 8-byte load
+                              // per lane reads four entries
   int32_t* tours;             // [ants][n]
   double* lens;               // [ants]
   int32_t* t_gb;              // [n]
@@ -86,17 +89,15 @@ struct InstDesc {
   int32_t* tr_elite;          // [iterations] or null
 };
 
-// The pick contract of a construction step, over a wave's four 16-lane rows
-// at once: `hits` has a lane's bit set when one of its slots passed the
-// prefix test, `exh` when its row has no open slot.  An open row must have
-// exactly one hit and an exhausted row none.  Scalar bit arithmetic on the
-// two wave masks (16-bit fields): X gives an exhausted row one bit, then no
-// field of X may be zero (the borrow test) and none may hold two bits.
-// Returns nonzero when the contract is broken.
-__host__ __device__ inline uint64_t pick_contract_broken(uint64_t hits, uint64_t exh) {
-  constexpr uint64_t L = 0x0001000100010001ull, H = 0x8000800080008000ull;
-  const uint64_t X = hits | (exh & L);
-  return (hits & exh) | ((X - L) & ~X & H) | (X & (X - L));
+// A tour of n nodes is a permutation of 0..n-1 only if the sum of its
+// entries is n(n-1)/2 and the sum of their squares (n-1)n(2n-1)/6; here
+// both modulo 2^32.  A construction step that took a wrong node (a duplicate
+// in place of a missing node) changes both; the construction kernel checks
+// them for every ant's tour.  The closed forms are evaluated exactly in 64
+// bits (n <= 10^6) before the reduction.
+__host__ __device__ inline bool tour_checksums_ok(int32_t n, uint32_t sum, uint32_t sum_sq) {
+  const uint64_t N = (uint64_t)n;
+  return sum == (uint32_t)(N * (N - 1) / 2) && sum_sq == (uint32_t)((N - 1) * N * (2 * N - 1) / 6);
 }
 
 // One entry per construction block: instance and first ant (inst < 0: idle)
@@ -128,9 +129,13 @@ hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 // builds the coordinate grid of every instance that has one
 hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s);
+// geo_mode: how an exhausted row consults its geometric list before a
+// scan: 0 not at all, 1 int32 lists loaded at the top of each step, 2
+// uint16 lists loaded one step ahead (every instance has geo16)
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
-                            int32_t bytes, int32_t max_k, size_t lds_bytes, hipStream_t s);
+                            int32_t bytes, int32_t max_k, size_t lds_bytes, int32_t geo_mode,
+                            hipStream_t s);
 // tours_per_inst: blocks per instance (the largest ant count among instances
 // that search every ant's tour, else 1)
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,

@@ -322,6 +322,7 @@ __global__ void __launch_bounds__(256) candidates_kernel(const InstDesc* insts) 
   if (lane < s) out[rank_s] = sup.id;
   if (lane < need) out[rank_f] = fill.id;
   if (lane < kg) D.geo[(int64_t)i * kg + lane] = geo.id;
+  if (D.geo16) D.geo16[(int64_t)i * 64 + lane] = (uint16_t)(lane < kg ? geo.id : 0);
   // each node's nearest neighbour, for the host's lower bound on a tour;
   // the successor array holds it until the first update overwrites it
   if (lane == 0) D.succ[i] = geo.id;
@@ -1144,6 +1145,9 @@ struct AntRows {
   const double2* xy_lds;
   GDist D;
   const HAC_AS1 int32_t* geo;
+  const HAC_AS1 uint64_t* geo16;  // uint16 lists, 16 x 8 bytes (64 entries) per node
+  int geo_mode;                   // 0 no list check, 1 int32 lists, 2 uint16 lists a step ahead
+  uint64_t glr;                   // mode 2: entries 4u .. 4u + 3 of the current node's list
   uint32_t* vis_wave;  // visited marks of the wave's live rows, vis_words apart
   uint32_t* vis_g;     // this row's marks (row 0's for an idle row, which never writes)
   int vis_words;       // BYTES: one byte per node, else one bit
@@ -1170,7 +1174,7 @@ struct AntRows {
   bool live;
   int cur;       // the row's current node (same in all its lanes)
   uint32_t fallbacks;
-  uint32_t* err;  // the instance's error word (State::err)
+  uint32_t row_max;     // STAGED 0: byte offset of the last table row
 
   __device__ __forceinline__ uint64_t entry(uint32_t a) const {
     if constexpr (STAGED == 1) {
@@ -1197,12 +1201,15 @@ struct AntRows {
 #pragma unroll
     for (int s = 0; s < S; ++s) e[s] = entry(ra[s]);
     __builtin_amdgcn_sched_barrier(0);  // the table read goes first: it heads the step's chain
-    // the geometric list of the current node, needed only if the row is
-    // exhausted: loaded now so that its latency hides behind the step
-    const uint32_t go = __umul24((uint32_t)cur, (uint32_t)kg);
-    int gl[4];  // entries 4u .. 4u + 3 of the list
+    // mode 1: the int32 geometric list of the current node, needed only if
+    // the row is exhausted, loaded now so that its latency hides behind the
+    // step (mode 2 loaded the uint16 list at the end of the previous step)
+    int gl[4] = {0, 0, 0, 0};  // entries 4u .. 4u + 3 of the list
+    if (geo_mode == 1) {
+      const uint32_t go = __umul24((uint32_t)cur, (uint32_t)kg);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) gl[q] = geo[go + (uint32_t)min(4 * u + q, kg - 1)];
+      for (int q = 0; q < 4; ++q) gl[q] = geo[go + (uint32_t)min(4 * u + q, kg - 1)];
+    }
     int c[S];
     uint32_t wb[S], mk[S], vw[S], bit[S];
     // t = 150 - (biased exponent), plus 512 once the slot's node is visited
@@ -1262,11 +1269,13 @@ struct AntRows {
       }
       hit |= h;
     }
-    // the pick contract, checked on scalar masks beside the OR butterflies
+    // Exactly one slot of an open row passes the test.  Whatever happens,
+    // the node and a global table row stay in range below, so a broken
+    // pick gives an in-range wrong choice, never a wild address; it marks
+    // a node the ant does not take, so its tour is no permutation, which
+    // the tour checksums at the end of the launch report.
     const bool exhausted = sh >= 256;
     const uint64_t exh_mask = __builtin_amdgcn_ballot_w64(exhausted);
-    uint64_t broken = pick_contract_broken(__builtin_amdgcn_ballot_w64(hit), exh_mask);
-    asm volatile("" : "+s"(broken));  // evaluated here, in the slots between the DPP levels
     int j = (int)row_reduce(pick, OpOr());
     // the next row's byte offset, alongside j.  At most one lane of a row
     // holds a nonzero offset, so after three levels one half of the row holds
@@ -1276,10 +1285,12 @@ struct AntRows {
     ro |= dpp_all<0xB1>(ro);
     ro |= dpp_all<0x4E>(ro);
     ro |= dpp_all<0x141>(ro);
+    uint32_t rrow = ro + dpp_all<0x140>(ro);
+    if constexpr (STAGED == 0) rrow = min(rrow, row_max);  // LDS reads out of range cannot fault
     if constexpr (S == 1) {
-      ra[0] = ro + dpp_all<0x140>(ro) + lane_off[0];
+      ra[0] = rrow + lane_off[0];
     } else {
-      set_row(ro + dpp_all<0x140>(ro));
+      set_row(rrow);
     }
     // the lane of the chosen slot marks it (only this row writes its marks;
     // a bitset word is rewritten with the value it has just read)
@@ -1289,25 +1300,26 @@ struct AntRows {
       else
         vis_g[wi] = wv;
     }
-    if (__builtin_expect(broken != 0, 0)) {
-      // never taken when the arithmetic above holds; if it does not, the
-      // instance is flagged and the row continues from an in-range node, so
-      // that no address is formed from a wrong prefix
-      if (lane_id() == 0) atomicOr(err, 1u);
-      j = (int)min((uint32_t)j, (uint32_t)(n - 1));
-      set_row(__umul24((uint32_t)j, k8));
-    }
+    j = (int)min((uint32_t)j, (uint32_t)(n - 1));
     if (exh_mask) {
       j = fallback(exhausted, j, gl);
       if (exhausted) set_row(__umul24((uint32_t)j, k8));
     }
+    // mode 2: the next node's list, a whole step ahead of its use
+    if (geo_mode == 2) glr = geo16[(uint32_t)j * 16u + (uint32_t)u];
     --left;
     return j;
   }
 
-  __device__ __forceinline__ int fallback(bool exhausted, int j, const int (&gl)[4]) {
+  __device__ __forceinline__ int fallback(bool exhausted, int j, int (&gl)[4]) {
     int jg = -1;
-    if (exhausted) {  // whole rows: the geometric list, four entries per lane
+    if (geo_mode == 2) {
+      gl[0] = (int)(glr & 0xffffu);
+      gl[1] = (int)((glr >> 16) & 0xffffu);
+      gl[2] = (int)((glr >> 32) & 0xffffu);
+      gl[3] = (int)(glr >> 48);
+    }
+    if (exhausted && geo_mode != 0) {  // whole rows: the geometric list, four entries per lane
       bool o[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) o[q] = (4 * u + q < kg) & !visited(vis_g, gl[q]);  // ids are valid in every lane
@@ -1372,7 +1384,7 @@ template <int STAGED, int S, bool BYTES>
 __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
                                                          int ants_per_block, int rows_per_wave,
-                                                         int lds_bytes) {
+                                                         int lds_bytes, int geo_mode) {
   const BlockMap bm = map[blockIdx.x];
   if (bm.inst < 0) return;
   const InstDesc I = insts[bm.inst];  // by value: the fields stay in registers
@@ -1455,6 +1467,8 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   A.D = GDist(I);
   A.grid = grid_view(I);
   A.geo = as_global(I.geo);
+  A.geo16 = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.geo16));
+  A.geo_mode = geo_mode;
   A.vis_words = vis_words;
   A.vis_wave = lds + wave * rpw * vis_words;
   A.vis_g = A.vis_wave + (A.live ? A.g : 0) * vis_words;
@@ -1482,13 +1496,15 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   rnd = dpp_zero<0x101>(rnd);  // row_shl:1, step 1's draw to lane 0
   A.cur = start;
   A.set_row(__umul24((uint32_t)start, A.k8));
+  if (geo_mode == 2) A.glr = A.geo16[(uint32_t)start * 16u + (uint32_t)A.u];
   if (A.u == 0 && A.live) A.mark(start);
   A.fallbacks = 0;
-  A.err = &I.st->err;
+  A.row_max = (uint32_t)(n - 1) * A.k8;
   A.left = n - 1;
   int tb = start;     // lane (s mod 16) holds T[s] of the current block of 16 steps
   int carry = start;  // T[s0 - 1]
   double len = 0.0;
+  uint32_t csum = 0, csq = 0;  // sum and sum of squares (mod 2^32) of this lane's tour entries
   int q0 = 1;
   for (int s0 = 0; s0 < n; s0 += 16) {
     if (s0 > 0) {
@@ -1504,6 +1520,10 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
     }
     // write T[s0 .. s0+cnt-1] and add their incoming edges in step order
     if (A.live && A.u < cnt) my_tour[s0 + A.u] = tb;
+    if (A.u < cnt) {
+      csum += (uint32_t)tb;
+      csq += __umul24((uint32_t)tb, (uint32_t)tb);  // node ids are below 2^24
+    }
     int prev = (int)dpp_zero<0x111>((uint32_t)tb);  // T[s - 1] from the lane below
     if (A.u == 0) prev = carry;
     double dl = 0.0;
@@ -1526,6 +1546,11 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   } else {
     len += A.D.len(carry, start);
   }
+  // the tour must be a permutation of 0..n-1: both checksums of the row
+  // against their closed forms
+  csum = row_reduce(csum, OpAdd());
+  csq = row_reduce(csq, OpAdd());
+  if (A.live && A.u == 0 && !tour_checksums_ok(n, csum, csq)) atomicOr(&I.st->err, 1u);
   if (A.live && A.u == 0) {
     I.lens[ant] = len;
     if (A.fallbacks) atomicAdd(&I.st->fallbacks, (unsigned long long)A.fallbacks);
@@ -2041,14 +2066,16 @@ int32_t construct_group_lanes(int32_t max_k) { (void)max_k; return 16; }
 
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
-                            int32_t bytes, int32_t max_k, size_t lds_bytes, hipStream_t s) {
+                            int32_t bytes, int32_t max_k, size_t lds_bytes, int32_t geo_mode,
+                            hipStream_t s) {
+  if (geo_mode < 0 || geo_mode > 2) return hipErrorInvalidValue;
   if (rows_per_wave < 1 || rows_per_wave > 4) return hipErrorInvalidValue;
   const int waves = (ants_per_block + rows_per_wave - 1) / rows_per_wave;
   const dim3 grid(blocks), block(waves * WAVE);
   const int S = max_k <= 16 ? 1 : (max_k <= 32 ? 2 : 4);
 #define HAC_LAUNCH(ST, SL, BY)                                                                 \
   hipLaunchKernelGGL((construct_kernel<ST, SL, BY>), grid, block, lds_bytes, s, d_insts, d_map, \
-                     ants_per_block, rows_per_wave, (int)lds_bytes)
+                     ants_per_block, rows_per_wave, (int)lds_bytes, (int)geo_mode)
 #define HAC_LAUNCH_S(ST, BY)             \
   {                                      \
     if (S == 1) HAC_LAUNCH(ST, 1, BY);   \

@@ -72,6 +72,7 @@ struct LaunchShape {
   int32_t kmax;
   int32_t rows_per_wave;
   int32_t bytes;  // visited marks: one byte per node (when they fit every instance) or one bit
+  int32_t geo = 1;  // geometric-list mode of the construction kernel (launch_construct)
 };
 
 // One decode batch: everything from uploaded inputs to results.
@@ -89,6 +90,13 @@ struct Engine {
 hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_params* p,
                     std::string* why);
 int32_t degree_target_of(const hac_instance* inst, const hac_params* p);
+
+// The geometric-list modes the tuner tries for a staging form: with the
+// table in LDS, 1 (int32 lists loaded at each step); with the table in
+// global memory, 0 (no list check) and 2 (uint16 lists loaded a step ahead,
+// when every instance has them; else 1).  HAC_GEO_MODE (0, 1 or 2) pins
+// the mode where it applies.
+std::vector<int32_t> geo_modes(const std::vector<HostInst>& hs, int32_t staged);
 
 // Builds the XCD-aware construction block map.
 std::vector<BlockMap> build_block_map(const std::vector<HostInst>& hs, int32_t ants_per_block);

@@ -4,11 +4,15 @@ The construction kernel picks the next node of every ant with integer
 arithmetic over 16-lane rows: quantised weights q, a row prefix scan, the
 draw r = floor(U * sum q / 2^32), and the test r - exclusive < q, which must
 pass in exactly one slot of an open row and in none of an exhausted row.
-The kernel checks this on the device (pick_contract_broken) and stops the
-instance with HAC_EDEVICE when it fails, instead of forming an address from
-a wrong prefix.  These tests pin, without a GPU:
-  * the device check itself, compiled for the host from the same header,
-    against a per-row count on random and edge-case masks;
+On the device, the chosen node and a global table row are clamped into
+range, so a broken pick can only give an in-range wrong choice; it marks a
+node the ant does not take, so the ant's tour is not a permutation, and the
+kernel checks every tour's entry sum and sum of squares against their
+closed forms modulo 2^32 (tour_checksums_ok), stopping the instance with HAC_EDEVICE.
+These tests pin, without a GPU:
+  * the checksum test itself, compiled for the host from the same header:
+    it accepts permutations and rejects a duplicate in place of a missing
+    node, also two such changes whose plain sums cancel;
   * a lane-level model of the step's arithmetic, with the DPP row
     operations spelled out (row shifts fill with zero), in two forms of
     the exclusive prefix: the kernel's (P - acc + a - q) and the form of a
@@ -39,55 +43,25 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CHECK_CPP = r"""
 #include "hac_internal.h"
 #include <cstdio>
+#include <vector>
 int main() {
-  unsigned long long h, e;
-  while (std::scanf("%llx %llx", &h, &e) == 2)
-    std::printf("%d\n", hac::pick_contract_broken(h, e) != 0 ? 1 : 0);
+  int n;
+  while (std::scanf("%d", &n) == 1) {
+    unsigned s = 0, q = 0;  // modulo 2^32, as the kernel sums them
+    for (int i = 0; i < n; ++i) {
+      unsigned v;
+      std::scanf("%u", &v);
+      s += v;
+      q += v * v;
+    }
+    std::printf("%d\n", hac::tour_checksums_ok(n, s, q) ? 1 : 0);
+  }
   return 0;
 }
 """
 
 
-def _brute_broken(hits, exh):
-    for g in range(4):
-        fh = (hits >> (16 * g)) & 0xFFFF
-        fe = (exh >> (16 * g)) & 0xFFFF
-        n = bin(fh).count("1")
-        if (fe and n != 0) or (not fe and n != 1):
-            return 1
-    return 0
-
-
-def _masks(rng, count):
-    out = []
-    for _ in range(count):
-        hits = exh = 0
-        for g in range(4):
-            ex = rng.random() < 0.3
-            if ex:
-                exh |= 0xFFFF << (16 * g)
-                f = 0 if rng.random() < 0.7 else int(rng.integers(1, 1 << 16))
-            else:
-                u = rng.random()
-                if u < 0.6:
-                    f = 1 << int(rng.integers(0, 16))
-                elif u < 0.75:
-                    f = 0
-                else:
-                    f = int(rng.integers(1, 1 << 16))
-            hits |= f << (16 * g)
-        out.append((hits, exh))
-    # edge cases: every single-bit position, the top bit of each field, all
-    # rows exhausted, all bits set
-    for b in range(64):
-        out.append((1 << b, 0))
-        out.append((1 << b, 0xFFFF << (16 * (b // 16))))
-    out += [(0, 0), (0, (1 << 64) - 1), ((1 << 64) - 1, 0), (0x8000800080008000, 0),
-            (0x0001000100010001, 0), (0x0003000100010001, 0), (0x8000800080000000, 0xFFFF)]
-    return out
-
-
-def test_device_check_against_a_per_row_count(tmp_path):
+def test_tour_checksums(tmp_path):
     src = tmp_path / "check.cpp"
     src.write_text(CHECK_CPP)
     exe = tmp_path / "check"
@@ -95,14 +69,30 @@ def test_device_check_against_a_per_row_count(tmp_path):
     subprocess.check_call([HIPCC, "-x", "c++", "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__", "-I", CSRC,
                            "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"), str(src),
                            "-o", str(exe)], stderr=subprocess.DEVNULL)
-    rng = np.random.default_rng(7)
-    cases = _masks(rng, 20000)
-    inp = "".join(f"{h:x} {e:x}\n" for h, e in cases)
+    rng = np.random.default_rng(11)
+    cases, want = [], []
+    for n in (1, 2, 3, 5, 64, 100, 1000, 65536, 1000000):
+        t = rng.permutation(n)
+        cases.append(t)
+        want.append(1)
+        if n >= 3:
+            bad = t.copy()
+            bad[rng.integers(n)] = bad[rng.integers(n)] if n > 1 else bad[0]
+            if len(set(bad.tolist())) < n:
+                cases.append(bad)
+                want.append(0)
+            # a duplicate of a and a missing b, plus a duplicate of c and a
+            # missing d with a + c = b + d: the plain sum cancels
+            if n >= 100:
+                two = t.copy()
+                pos = {int(v): i for i, v in enumerate(two)}
+                two[pos[10]] = 9   # 9 twice, 10 missing
+                two[pos[20]] = 21  # 21 twice, 20 missing
+                cases.append(two)
+                want.append(0)
+    inp = "".join(f"{len(c)} " + " ".join(map(str, c.tolist())) + "\n" for c in cases)
     out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout.split()
-    got = [int(x) for x in out]
-    want = [_brute_broken(h, e) for h, e in cases]
-    assert got == want
-    assert 0 < sum(want) < len(want)
+    assert [int(x) for x in out] == want
 
 
 # ---- lane-level model of one step (16-lane rows, S slots per lane) ----
