@@ -192,6 +192,30 @@ hac_status hac_decode_dev(hac_ctx* ctx, const hac_instance* inst_dev, const hac_
                           const hac_params* p, uint64_t seed, int32_t* tour_out_dev,
                           double* length_out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decode as hac_decode, with the same arguments, result and errors, but
+ * every device buffer it uses (the instance's inputs, candidate lists,
+ * pheromone and weights, ant tours, search state and launch tables) is
+ * carved from one array of HAC_NOALLOC_BYTES that the library holds on each
+ * GPU for the life of the process; the call allocates nothing and frees
+ * nothing.  The launch shape is the tuner's cached choice for the
+ * instance's shape class, else a fixed one (no timing launches), and the
+ * iterations run as plain launches.  HAC_ENOMEM, with the byte count in
+ * hac_last_error, if the instance needs more than the array holds (a
+ * 10 000-node instance with 100 ants and 2-opt needs about 15 MB).
+ * Calls on one GPU share its array, which keeps the last call's contents:
+ * every buffer is written before it is read, and calls that would overlap
+ * on one GPU (several threads or contexts) are serialised by a lock per
+ * device, since they would otherwise race on the array.  The context's
+ * stream and timing setting are used as by hac_decode (timing is ignored);
+ * hac_debug_state and hac_debug_trace after such a call read the shared
+ * array. */
+#define HAC_NOALLOC_BYTES ((uint64_t)64 << 20)
+hac_status hac_decode_noalloc(hac_ctx* ctx, const hac_instance* inst, const hac_csr* heat,
+                              const hac_params* p, uint64_t seed, int32_t* tour_out,
+                              double* length_out);
+
 /* Decodes `count` independent instances of any sizes together (the
  * batched path): all instances' ants are constructed in shared launches,
  * with launch shapes chosen by the autotuner.  params[i], seeds[i] and

@@ -85,7 +85,7 @@ class hac_stats(ctypes.Structure):
 
 # every symbol include/hac.h declares
 EXPORTS = ["hac_params_default", "hac_strerror", "hac_validate", "hac_create", "hac_destroy",
-           "hac_last_error", "hac_set_timing", "hac_decode", "hac_decode_dev", "hac_decode_batch",
+           "hac_last_error", "hac_set_timing", "hac_decode", "hac_decode_noalloc", "hac_decode_dev", "hac_decode_batch",
            "hac_decode_batch_dev",
            "hac_last_stats", "hac_debug_state", "hac_debug_trace", "hac_footprint",
            "hac_server_create", "hac_server_submit", "hac_server_poll", "hac_server_wait",
@@ -126,6 +126,8 @@ def lib():
         L.hac_set_timing.restype = i32
         L.hac_decode.argtypes = [vp, PI, PC, PP, u64, vp, vp]
         L.hac_decode.restype = i32
+        L.hac_decode_noalloc.argtypes = [vp, PI, PC, PP, u64, vp, vp]
+        L.hac_decode_noalloc.restype = i32
         L.hac_decode_dev.argtypes = [vp, PI, PC, PP, u64, vp, vp]
         L.hac_decode_dev.restype = i32
         L.hac_decode_batch.argtypes = [vp, i32, PI, PC, PP, vp, vp, vp]
@@ -257,6 +259,19 @@ class Context:
                               ctypes.byref(m.s_params), m.seed, tour.ctypes.data, ctypes.byref(L))
         if raise_on_error:
             self._check(st, "hac_decode")
+        else:
+            self.status = st
+        return tour, L.value
+
+    def decode_noalloc(self, inst, raise_on_error: bool = True, **over) -> Tuple[np.ndarray, float]:
+        """The allocation-free variant of decode (hac_decode_noalloc)."""
+        m = Marshalled(inst, **over)
+        tour = np.zeros(inst.n, dtype=np.int32)
+        L = ctypes.c_double()
+        st = lib().hac_decode_noalloc(self._h, ctypes.byref(m.s_inst), ctypes.byref(m.s_csr),
+                                      ctypes.byref(m.s_params), m.seed, tour.ctypes.data, ctypes.byref(L))
+        if raise_on_error:
+            self._check(st, "hac_decode_noalloc")
         else:
             self.status = st
         return tour, L.value

@@ -628,6 +628,36 @@ static std::string shape_key(const std::vector<HostInst>& hs) {
          (hs[0].lay.coords ? "/euc" : "/mat");
 }
 
+// A launch shape chosen without timing anything (the allocation-free path):
+// the tuner's cached choice for the batch's shape class if there is one,
+// else the first that fits of 16 ants per block with 8-byte LDS entries,
+// the two packed LDS forms, and one ant per wave with the table in global
+// memory.  Results do not depend on the shape.
+LaunchShape default_shape(const std::vector<HostInst>& hs) {
+  const int32_t kmax = batch_max_k(hs);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tune_cache.find(shape_key(hs));
+    if (it != g_tune_cache.end()) {
+      LaunchShape sh = with_marks(hs, {it->second.ants_per_block, it->second.staged, kmax,
+                                       it->second.rows_per_wave, 0});
+      sh.geo = geo_modes(hs, sh.staged)[0];
+      if (shape_fits(hs, sh)) return sh;
+    }
+  }
+  for (int st : {1, 2, 3}) {
+    LaunchShape sh = with_marks(hs, {16, st, kmax, 4, 0});
+    if (shape_fits(hs, sh)) {
+      sh.geo = geo_modes(hs, st)[0];
+      return sh;
+    }
+  }
+  LaunchShape sh = with_marks(hs, {4, 0, kmax, 1, 0});
+  sh.geo = geo_modes(hs, 0)[0];
+  return sh;
+}
+
 LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs, hipStream_t s,
                        DeviceArena& scratch, bool* ok) {
   *ok = true;
@@ -809,6 +839,8 @@ hac_status hac_create(hac_ctx** out, int32_t device, void* stream, uint64_t hbm_
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return HAC_EDEVICE;
   if (device < 0 || device >= ndev) return HAC_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return HAC_EDEVICE;
+  // the allocation-free entry point's array on this device (once per device)
+  if (noalloc_scratch_init(device) != hipSuccess) return HAC_EDEVICE;
   hac_ctx* c = new hac_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes;
@@ -950,9 +982,13 @@ hac_status mirror_inputs(hac_ctx* c, int32_t count, const hac_instance* insts, c
   return HAC_OK;
 }
 
+// noalloc: every device buffer comes from the device's static scratch array
+// (no hipMalloc, no graph, no events, no tuning launches); only for host
+// inputs and outputs
 hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, const hac_csr* csrs_in,
                      const hac_params* params, const uint64_t* seeds, int32_t* const* tours_out,
-                     double* lengths_out, bool outputs_on_device, bool inputs_on_device) {
+                     double* lengths_out, bool outputs_on_device, bool inputs_on_device,
+                     bool noalloc = false) {
   const auto t0 = Clock::now();
   c->err.clear();
   c->stats = hac_stats{};
@@ -1004,22 +1040,42 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
                  align256(sizeof(int32_t*) * (size_t)std::max(m, 1)) + align256(8 * (size_t)std::max(m, 1));
   for (auto& h : hs) total += h.lay.bytes() + (outputs_on_device ? 0 : align256(4 * (size_t)h.lay.n));
   if (c->budget && total > c->budget) return set_err(c, HAC_ENOMEM, "batch exceeds the context budget");
-  if (m > 0) {
+  // device memory: the context's arena, or the static scratch array
+  char* nb = nullptr;
+  size_t nb_used = 0;
+  if (noalloc) {
+    // the block map follows the slots: at most one block per ant, and a
+    // round of eight entries (one per XCD) per block at worst
+    size_t ants = 0;
+    for (auto& h : hs) ants += (size_t)h.p.ants;
+    total += align256(sizeof(BlockMap) * 8 * ants);
+    if (total > kNoAllocBytes)
+      return set_err(c, HAC_ENOMEM, "the decode needs " + std::to_string(total) + " bytes of device memory; "
+                                    "the allocation-free scratch holds " + std::to_string(kNoAllocBytes));
+    nb = (char*)noalloc_scratch(c->device);
+    if (!nb) return set_err(c, HAC_EDEVICE, "allocation-free scratch not set up on this device");
+  } else if (m > 0) {
     hipError_t e = c->arena.reserve(total);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
       return set_err(c, HAC_ENOMEM, "device memory");
     CTX_HIP(e);
   }
-  InstDesc* d_descs = m ? (InstDesc*)c->arena.carve(sizeof(InstDesc) * m) : nullptr;
-  int32_t** d_out_ptrs = m ? (int32_t**)c->arena.carve(sizeof(int32_t*) * m) : nullptr;
-  double* d_out_lens = m ? (double*)c->arena.carve(8 * (size_t)m) : nullptr;
+  auto carve = [&](size_t b) -> void* {
+    if (!noalloc) return c->arena.carve(b);
+    void* p = nb + nb_used;
+    nb_used += align256(b);
+    return p;
+  };
+  InstDesc* d_descs = m ? (InstDesc*)carve(sizeof(InstDesc) * m) : nullptr;
+  int32_t** d_out_ptrs = m ? (int32_t**)carve(sizeof(int32_t*) * m) : nullptr;
+  double* d_out_lens = m ? (double*)carve(8 * (size_t)m) : nullptr;
   std::vector<int32_t*> out_ptrs(m);
   std::vector<CopyItem> up;  // device-resident inputs, gathered in one launch
   for (int32_t y = 0; y < m; ++y) {
     HostInst& h = hs[y];
-    assign_slot(h, [&](size_t b) { return c->arena.carve(b); });
+    assign_slot(h, carve);
     fill_desc_scalars(h);
-    out_ptrs[y] = outputs_on_device ? tours_out[which[y]] : (int32_t*)c->arena.carve(4 * (size_t)h.lay.n);
+    out_ptrs[y] = outputs_on_device ? tours_out[which[y]] : (int32_t*)carve(4 * (size_t)h.lay.n);
     if (h.from_device) {
       // the caller's device arrays, gathered into the slot below
       const Layout& L = h.lay;
@@ -1057,7 +1113,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     CTX_HIP(hipMemcpyAsync(d_descs, descs.data(), sizeof(InstDesc) * m, hipMemcpyHostToDevice, s));
     CTX_HIP(hipMemcpyAsync(d_out_ptrs, out_ptrs.data(), sizeof(int32_t*) * m, hipMemcpyHostToDevice, s));
     std::string err;
-    hac_status ps = prepare_instances(hs, d_descs, s, &err, &c->stage);
+    hac_status ps = prepare_instances(hs, d_descs, s, &err, noalloc ? nullptr : &c->stage);
     if (ps != HAC_OK) return set_err(c, ps, err);
   }
   const double prep_ms = ms_since(t0);
@@ -1077,7 +1133,9 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       if (!h.lay.coords) all_coords = 0;
     }
     LaunchShape shape{4, 0, 16, 4, 0};
-    if (max_iter > 0) {
+    if (noalloc) {
+      shape = default_shape(hs);
+    } else if (max_iter > 0) {
       bool ok = true;
       shape = tune_shape(hs, d_descs, s, c->scratch, &ok);
       if (!ok) return set_err(c, HAC_EDEVICE, "autotuner launch failed");
@@ -1091,9 +1149,17 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     }
     used = shape;
     std::vector<BlockMap> map = build_block_map(hs, shape.ants_per_block);
-    c->scratch.reset();
-    CTX_HIP(c->scratch.reserve(map.size() * sizeof(BlockMap)));
-    BlockMap* d_map = (BlockMap*)c->scratch.carve(map.size() * sizeof(BlockMap));
+    BlockMap* d_map;
+    if (noalloc) {
+      size_t ants = 0;
+      for (auto& h : hs) ants += (size_t)h.p.ants;
+      if (map.size() > 8 * ants) return set_err(c, HAC_EDEVICE, "block map larger than its reserve");
+      d_map = (BlockMap*)carve(map.size() * sizeof(BlockMap));
+    } else {
+      c->scratch.reset();
+      CTX_HIP(c->scratch.reserve(map.size() * sizeof(BlockMap)));
+      d_map = (BlockMap*)c->scratch.carve(map.size() * sizeof(BlockMap));
+    }
     CTX_HIP(hipMemcpyAsync(d_map, map.data(), map.size() * sizeof(BlockMap), hipMemcpyHostToDevice, s));
     const size_t lds = shape_lds(hs, shape);
     const int32_t blocks = (int32_t)map.size();
@@ -1107,7 +1173,12 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       }
       return launch_iter_end(d_descs, m, s);
     };
-    if (c->timing) {
+    if (noalloc) {
+      // plain launches: no graph, no events
+      for (int32_t it = 0; it < max_iter; ++it) CTX_HIP(one_iteration());
+      CTX_HIP(hipStreamSynchronize(s));
+      launches = max_iter;
+    } else if (c->timing) {
       // per-iteration launches with HIP events around each kernel: e[4 it]
       // .. e[4 it + 3] bracket construction, 2-opt and the update
       while ((int)c->events.size() < 4 * max_iter) {
@@ -1182,7 +1253,12 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       at.push_back((size_t)y * align256(sizeof(State)));
     }
     std::vector<char> blob((size_t)m * align256(sizeof(State)));
-    CTX_HIP(stage_copies(c->stage, items, at, blob.data(), blob.size(), true, s));
+    if (noalloc) {
+      for (int32_t y = 0; y < m; ++y)
+        CTX_HIP(hipMemcpyAsync(blob.data() + at[y], hs[y].d.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    } else {
+      CTX_HIP(stage_copies(c->stage, items, at, blob.data(), blob.size(), true, s));
+    }
     CTX_HIP(hipStreamSynchronize(s));
     for (int32_t y = 0; y < m; ++y) std::memcpy(&sts[y], blob.data() + at[y], sizeof(State));
     for (int32_t y = 0; y < m; ++y)
@@ -1256,6 +1332,16 @@ hac_status hac_decode(hac_ctx* c, const hac_instance* inst, const hac_csr* heat,
   if (!c) return HAC_EINVAL;
   int32_t* tours[1] = {tour_out};
   return run_batch(c, 1, inst, heat, p, &seed, tours, length_out, false, false);
+}
+
+hac_status hac_decode_noalloc(hac_ctx* c, const hac_instance* inst, const hac_csr* heat, const hac_params* p,
+                              uint64_t seed, int32_t* tour_out, double* length_out) {
+  if (!c) return HAC_EINVAL;
+  std::mutex* lock = noalloc_call_lock(c->device);
+  if (!lock) return HAC_EINVAL;
+  std::lock_guard<std::mutex> g(*lock);
+  int32_t* tours[1] = {tour_out};
+  return run_batch(c, 1, inst, heat, p, &seed, tours, length_out, false, false, true);
 }
 
 hac_status hac_decode_batch(hac_ctx* c, int32_t count, const hac_instance* insts, const hac_csr* heats,

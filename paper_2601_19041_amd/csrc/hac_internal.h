@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace hac {
 
 // Device-resident search state of one instance (Alg. 1 bookkeeping).
@@ -113,6 +115,17 @@ struct CopyItem {
   void* dst;
   uint64_t bytes;
 };
+
+// ---- the allocation-free entry point (defined in hac_kernels.hip) ----
+// bytes of the per-device scratch array every hac_decode_noalloc carves
+static constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+// takes the array's device address on `device` (which must be current);
+// once per device, later calls return at once
+hipError_t noalloc_scratch_init(int32_t device);
+// the address taken by noalloc_scratch_init, or null
+void* noalloc_scratch(int32_t device);
+// serialises allocation-free decodes on one device (they share its array)
+std::mutex* noalloc_call_lock(int32_t device);
 
 // ---- launchers (defined in hac_kernels.hip) ----
 // all items of a list (device memory) in one launch; max_bytes bounds the

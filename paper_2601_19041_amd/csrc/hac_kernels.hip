@@ -18,9 +18,17 @@
 #include <stdint.h>
 
 #include <cstdlib>
+#include <mutex>
 #include <type_traits>
 
 #include "hac_internal.h"
+
+// Device memory of the allocation-free entry point (hac_decode_noalloc):
+// every buffer of such a decode is carved from this array, which each GPU
+// the library runs on holds for the life of the process.  In host code its
+// name is a host-side stand-in, not a device address: the address comes
+// from hipGetSymbolAddress, taken once per device (noalloc_scratch_init).
+static __device__ __align__(256) unsigned char scratch[hac::kNoAllocBytes];
 
 namespace hac {
 
@@ -2138,6 +2146,35 @@ hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const*
   hipLaunchKernelGGL(finish_kernel, dim3(count), dim3(WAVE), 0, s, d_insts, d_out_tours,
                      d_out_lens);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// the allocation-free entry point's scratch array, per device
+// ------------------------------------------------------------------------
+static constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_init_mu;
+static void* g_noalloc_ptr[kMaxDevices];
+static std::mutex g_noalloc_call_mu[kMaxDevices];
+
+hipError_t noalloc_scratch_init(int32_t device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_noalloc_init_mu);
+  if (g_noalloc_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_noalloc_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* noalloc_scratch(int32_t device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_noalloc_init_mu);
+  return g_noalloc_ptr[device];
+}
+
+std::mutex* noalloc_call_lock(int32_t device) {
+  return (device >= 0 && device < kMaxDevices) ? &g_noalloc_call_mu[device] : nullptr;
 }
 
 }  // namespace hac

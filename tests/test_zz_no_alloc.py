@@ -1,0 +1,70 @@
+"""The allocation-free entry point (hac_decode_noalloc) against hac_decode.
+
+hac_decode_noalloc carves every device buffer of a decode from one static
+array per GPU instead of allocating.  Through the C ABI, two calls in a row
+(the second with a smaller input, so the array still holds the first call's
+data) must return exactly what hac_decode returns for the same inputs, and
+so must a call with 2-opt and one on an asymmetric matrix.  An instance
+larger than the array is refused with HAC_ENOMEM and the outputs are left
+untouched.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2601_19041_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hac():
+    import paper_2601_19041_amd as hac
+    return hac
+
+
+@pytest.fixture(scope="module")
+def ctx(hac):
+    c = hac.Context(0)
+    yield c
+    c.close()
+
+
+def _same(a, b, what):
+    assert np.array_equal(a[0], b[0]), f"{what}: tours differ at {np.flatnonzero(a[0] != b[0])[:5]}"
+    assert a[1] == b[1], (what, a[1], b[1])
+
+
+def test_noalloc_equals_decode_twice_then_smaller(ctx):
+    big = wl.tsp500(iterations=300)
+    small = wl.tsp100(iterations=60)
+    print("case no-alloc tsp500 then tsp100", flush=True)
+    got_big = ctx.decode_noalloc(big)
+    got_small = ctx.decode_noalloc(small)
+    _same(got_big, ctx.decode(big), "tsp500")
+    _same(got_small, ctx.decode(small), "tsp100 after tsp500")
+
+
+def test_noalloc_two_opt_and_atsp(ctx):
+    ls = wl.random_instance(300, seed=8, ants=12, iterations=25, local_search=1, k_ls=10)
+    atsp = wl.serve_request("atsp1000", 3, iterations=10)
+    print("case no-alloc 2-opt n=300, ATSP n=1000", flush=True)
+    for inst in (ls, atsp):
+        _same(ctx.decode_noalloc(inst), ctx.decode(inst), inst.name)
+
+
+def test_noalloc_refuses_what_does_not_fit(ctx, hac):
+    n = 3000  # an 8-byte distance matrix of 72 MB alone exceeds the 64 MiB array
+    rng = np.random.default_rng(5)
+    xy = rng.random((n, 2))
+    d = np.sqrt(((xy[:, None, :] - xy[None, :, :]) ** 2).sum(-1))
+    d = np.ascontiguousarray(np.minimum(d, d.T))
+    inst = wl.Instance(n, "matrix", True, None, d, wl.empty_heatmap(n), ants=4, iterations=2, k=8,
+                       name="mat3000")
+    print("case no-alloc too large", flush=True)
+    tour, L = ctx.decode_noalloc(inst, raise_on_error=False)
+    assert ctx.status == hac.HAC_ENOMEM and "allocation-free" in ctx.last_error()
+    assert not tour.any() and L == 0.0
+    # the context still decodes (allocating) and without allocating
+    small = wl.tsp100(iterations=20)
+    _same(ctx.decode_noalloc(small), ctx.decode(small), "after the refusal")
