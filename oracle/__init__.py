@@ -95,6 +95,11 @@ def lib():
         L.orc_tour_length.argtypes = [P, vp]
         L.orc_tour_length.restype = ctypes.c_double
         L.orc_two_opt.argtypes = [P, vp, ctypes.c_int32, ctypes.c_double, vp]
+        L.orc_nearest_in_lists.argtypes = [P, ctypes.c_int32, vp]
+        L.orc_nearest_in_lists.restype = ctypes.c_int32
+        L.orc_two_opt_directed.argtypes = [P, vp, vp, ctypes.c_int32, ctypes.c_double, vp]
+        L.orc_directed_move.argtypes = [P, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
+        L.orc_directed_move.restype = ctypes.c_double
         L.orc_decode.argtypes = [P, vp, vp, ctypes.POINTER(Trace)]
         L.orc_decode.restype = ctypes.c_int32
         L.orc_diagnostics.argtypes = [P, vp, vp, vp]
@@ -217,6 +222,33 @@ def two_opt(inst, nl: np.ndarray, tour, min_gain: float) -> np.ndarray:
     t = np.array(tour, dtype=np.int32)
     lib().orc_two_opt(p.ref, _ptr(nl), nl.shape[1], min_gain, _ptr(t))
     return t
+
+
+def nearest_in_lists(inst, kk: int) -> np.ndarray:
+    p = OracleProblem(inst)
+    kk = min(kk, p.n - 1)
+    out = np.zeros((p.n, kk), dtype=np.int32)
+    lib().orc_nearest_in_lists(p.ref, kk, _ptr(out))
+    return out
+
+
+def two_opt_directed(inst, nl_out: np.ndarray, nl_in: np.ndarray, tour, min_gain: float) -> np.ndarray:
+    p = OracleProblem(inst)
+    a = np.ascontiguousarray(nl_out, dtype=np.int32)
+    b = np.ascontiguousarray(nl_in, dtype=np.int32)
+    t = np.array(tour, dtype=np.int32)
+    lib().orc_two_opt_directed(p.ref, _ptr(a), _ptr(b), a.shape[1], min_gain, _ptr(t))
+    return t
+
+
+def directed_move(inst, tour, a: int, c: int, direction: int):
+    """(gain, tour after the move) of one directed 2-opt move; gain is NaN
+    for a degenerate move."""
+    p = OracleProblem(inst)
+    t = np.ascontiguousarray(tour, dtype=np.int32)
+    out = np.zeros_like(t)
+    g = lib().orc_directed_move(p.ref, _ptr(t), a, c, direction, _ptr(out))
+    return g, out
 
 
 def decode(inst, trace: bool = False, state: bool = False, **over):

@@ -203,6 +203,23 @@ int32_t orc_nearest_lists(const orc_problem* p, int32_t kk, int32_t* out) {
   return kk;
 }
 
+/* Incoming neighbour lists (matrix instances, for the directed 2-opt): for
+ * node i the kk nodes j with the smallest d(j, i), ties to the lower index. */
+int32_t orc_nearest_in_lists(const orc_problem* p, int32_t kk, int32_t* out) {
+  int32_t n = p->n;
+  if (kk > n - 1) kk = n - 1;
+  if (kk < 1) return 0;
+  topk_t t = {kk, 0, (double*)malloc(sizeof(double) * kk), (int32_t*)malloc(4 * kk)};
+  for (int32_t i = 0; i < n; i++) {
+    t.size = 0;
+    for (int32_t j = 0; j < n; j++)
+      if (j != i) topk_offer(&t, dist(p, j, i), j);
+    for (int32_t q = 0; q < kk; q++) out[(int64_t)i * kk + q] = t.id[q];
+  }
+  free(t.key); free(t.id);
+  return kk;
+}
+
 static int cmp_desc(const void* a, const void* b) {
   double x = *(const double*)a, y = *(const double*)b;
   return (x < y) - (x > y);
@@ -518,6 +535,160 @@ void orc_two_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min
   free(pos); free(queue); free(inq);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Section III-D for the ATSP: directed 2-opt.  Reading of "a directed 2-opt */
+/* based on the Jonker-Volgenant reduction": that reduction makes each city  */
+/* a pair of nodes joined by an edge every tour keeps; a 2-opt move on the   */
+/* reduced graph that keeps the pairs joined reverses a path and swaps each  */
+/* pair's roles, which on the directed tour is the 2-opt move whose reversed */
+/* path is priced in its new direction.  Moves:                              */
+/*   successor side: b = succ(a), c from a's outgoing list, e = succ(c);     */
+/*     (a->b), (c->e) become (a->c), (b->e), the path b..c reversed;         */
+/*   predecessor side: b = pred(a), c from a's incoming list, e = pred(c);   */
+/*     (b->a), (e->c) become (c->a), (e->b), the path c..b reversed.         */
+/* gain = (removed edges + F) - (added edges + B), F and B the reversed      */
+/* path's cost in its old and new direction, from prefix sums of the         */
+/* directed edge lengths in tour order.  Queue, side order, list stop rule,  */
+/* threshold and re-queueing as in the symmetric 2-opt; the reversed part is */
+/* always the path itself (its complement would give the opposite tour).    */
+/* A run applies at most 64 n moves: every move shortens the tour by more    */
+/* than the threshold, so this bound only guards against a broken gain.     */
+/* ------------------------------------------------------------------------ */
+
+/* pf[q] = sum of d(T[t], T[t+1]) for t < q, pb[q] the same edges reversed,
+ * q = 0..n, the closing edge last (eq. (1)'s order) */
+static void directed_prefix(const orc_problem* p, const int32_t* tour, double* pf, double* pb) {
+  int32_t n = p->n;
+  pf[0] = 0.0;
+  pb[0] = 0.0;
+  for (int32_t q = 0; q < n; q++) {
+    int32_t x = tour[q], y = tour[(q + 1) % n];
+    pf[q + 1] = pf[q] + dist(p, x, y);
+    pb[q + 1] = pb[q] + dist(p, y, x);
+  }
+}
+
+/* cost of the path from position i to position j (cyclic, forward) */
+static double path_cost(const double* pre, int32_t n, int32_t i, int32_t j) {
+  return i <= j ? pre[j] - pre[i] : (pre[n] - pre[i]) + pre[j];
+}
+
+/* reverse the tour positions i..j (cyclic) */
+static void reverse_positions(int32_t n, int32_t* tour, int32_t* pos, int32_t i, int32_t j) {
+  int32_t len = ((j - i + n) % n) + 1;
+  for (int32_t s = 0; s < len / 2; s++) {
+    int32_t ti = tour[i], tj = tour[j];
+    tour[i] = tj;
+    tour[j] = ti;
+    pos[tj] = i;
+    pos[ti] = j;
+    i = (i + 1) % n;
+    j = (j - 1 + n) % n;
+  }
+}
+
+/* gain of the directed move at a with list node c (dir 0: successor side,
+ * 1: predecessor side), or NAN when the move is degenerate; *pi, *pj get
+ * the positions of the path to reverse */
+static double directed_gain(const orc_problem* p, const int32_t* tour, const int32_t* pos,
+                            const double* pf, const double* pb, int32_t a, int32_t c, int dir,
+                            int32_t* pi, int32_t* pj) {
+  int32_t n = p->n;
+  if (dir == 0) {
+    int32_t b = tour[(pos[a] + 1) % n], e = tour[(pos[c] + 1) % n];
+    if (e == a || c == b || c == a) return NAN;
+    int32_t i = pos[b], j = pos[c];
+    double F = path_cost(pf, n, i, j), B = path_cost(pb, n, i, j);
+    *pi = i;
+    *pj = j;
+    return ((dist(p, a, b) + dist(p, c, e)) + F) - ((dist(p, a, c) + dist(p, b, e)) + B);
+  }
+  int32_t b = tour[(pos[a] - 1 + n) % n], e = tour[(pos[c] - 1 + n) % n];
+  if (e == a || c == b || c == a) return NAN;
+  int32_t i = pos[c], j = pos[b];
+  double F = path_cost(pf, n, i, j), B = path_cost(pb, n, i, j);
+  *pi = i;
+  *pj = j;
+  return ((dist(p, b, a) + dist(p, e, c)) + F) - ((dist(p, c, a) + dist(p, e, b)) + B);
+}
+
+void orc_two_opt_directed(const orc_problem* p, const int32_t* nl_out, const int32_t* nl_in, int32_t kk,
+                          double min_gain, int32_t* tour) {
+  int32_t n = p->n;
+  if (n < 5 || kk < 1) return;
+  int32_t* pos = (int32_t*)malloc(4 * (size_t)n);
+  int32_t* queue = (int32_t*)malloc(4 * (size_t)n);
+  uint8_t* inq = (uint8_t*)malloc((size_t)n);
+  double* pf = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+  double* pb = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+  for (int32_t s = 0; s < n; s++) { pos[tour[s]] = s; queue[s] = tour[s]; inq[s] = 1; }
+  directed_prefix(p, tour, pf, pb);
+  int32_t head = 0, count = n;
+  int64_t moves = 0, max_moves = 64 * (int64_t)n;
+#define DPUSH(x)                         \
+  do {                                   \
+    if (!inq[x]) {                       \
+      queue[(head + count) % n] = (x);   \
+      count++;                           \
+      inq[x] = 1;                        \
+    }                                    \
+  } while (0)
+  while (count > 0 && moves < max_moves) {
+    int32_t a = queue[head];
+    head = (head + 1) % n;
+    count--;
+    inq[a] = 0;
+    int improved = 1;
+    while (improved && moves < max_moves) {
+      improved = 0;
+      for (int dir = 0; dir < 2 && !improved; dir++) {
+        int32_t b = dir == 0 ? tour[(pos[a] + 1) % n] : tour[(pos[a] - 1 + n) % n];
+        double dab = dir == 0 ? dist(p, a, b) : dist(p, b, a);
+        const int32_t* nl = dir == 0 ? nl_out : nl_in;
+        for (int32_t q = 0; q < kk; q++) {
+          int32_t c = nl[(int64_t)a * kk + q];
+          double dac = dir == 0 ? dist(p, a, c) : dist(p, c, a);
+          double g1 = dab - dac;
+          if (g1 <= 0.0) break;
+          int32_t i, j;
+          double gain = directed_gain(p, tour, pos, pf, pb, a, c, dir, &i, &j);
+          if (isnan(gain)) continue;
+          if (gain > min_gain) {
+            int32_t e = dir == 0 ? tour[(pos[c] + 1) % n] : tour[(pos[c] - 1 + n) % n];
+            reverse_positions(n, tour, pos, i, j);
+            directed_prefix(p, tour, pf, pb);
+            moves++;
+            DPUSH(a); DPUSH(b); DPUSH(c); DPUSH(e);
+            improved = 1;
+            break;
+          }
+        }
+      }
+    }
+  }
+#undef DPUSH
+  free(pos); free(queue); free(inq); free(pf); free(pb);
+}
+
+/* One directed move (test hook): the gain the directed 2-opt computes for
+ * the move at node a with list node c on `tour` (dir 0 successor side, 1
+ * predecessor side), and the tour after the move in `out`; NAN (out
+ * unchanged) for a degenerate move. */
+double orc_directed_move(const orc_problem* p, const int32_t* tour, int32_t a, int32_t c, int32_t dir,
+                         int32_t* out) {
+  int32_t n = p->n;
+  int32_t* pos = (int32_t*)malloc(4 * (size_t)n);
+  double* pf = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+  double* pb = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+  for (int32_t s = 0; s < n; s++) { out[s] = tour[s]; pos[tour[s]] = s; }
+  directed_prefix(p, tour, pf, pb);
+  int32_t i = 0, j = 0;
+  double gain = directed_gain(p, tour, pos, pf, pb, a, c, dir, &i, &j);
+  if (!isnan(gain)) reverse_positions(n, out, pos, i, j);
+  free(pos); free(pf); free(pb);
+  return gain;
+}
+
 /* Eq. (5)/(6): bounds from a tour length */
 static void tau_bounds(const orc_problem* p, int32_t k_eff, double len, double* tmax,
                        double* tmin) {
@@ -549,7 +720,6 @@ static int valid_problem(const orc_problem* p) {
   if (p->alpha != 1.0) return 0;
   if (p->local_search < 0 || p->local_search > 2) return 0;
   if (!isfinite(p->kappa_fixed)) return 0;
-  if (p->kind == ORC_MATRIX && !p->symmetric && p->local_search) return 0;
   if (p->row_ptr[0] != 0) return 0;
   for (int32_t i = 0; i < p->n; i++) {
     if (p->row_ptr[i + 1] < p->row_ptr[i]) return 0;
@@ -655,10 +825,21 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
 
   int32_t k_ls = p->k_ls < n - 1 ? p->k_ls : n - 1;
   int32_t* nl = NULL;
+  int32_t* nl_in = NULL; /* the ATSP's incoming lists, for the directed 2-opt */
   if (p->local_search) {
     nl = (int32_t*)malloc(4 * (int64_t)n * (k_ls > 0 ? k_ls : 1));
     orc_nearest_lists(p, k_ls, nl);
+    if (!sym) {
+      nl_in = (int32_t*)malloc(4 * (int64_t)n * (k_ls > 0 ? k_ls : 1));
+      orc_nearest_in_lists(p, k_ls, nl_in);
+    }
   }
+  /* Section III-D: 2-opt for symmetric instances, directed 2-opt for the ATSP */
+#define LOCAL_SEARCH(t)                                                  \
+  do {                                                                   \
+    if (sym) orc_two_opt(p, nl, k_ls, min_gain, (t));                    \
+    else orc_two_opt_directed(p, nl, nl_in, k_ls, min_gain, (t));        \
+  } while (0)
 
   int32_t* t_nn = (int32_t*)malloc(4 * (size_t)n);
   double l_nn_raw = orc_nn_tour(p, t_nn);
@@ -666,7 +847,7 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
   /* reading: the 2-opt gain threshold is 1e-9 of the mean NN-tour edge */
   double min_gain = 1e-9 * l_nn_raw / (double)n;
   if (p->local_search) {
-    orc_two_opt(p, nl, k_ls, min_gain, t_nn);
+    LOCAL_SEARCH(t_nn);
     l_nn = orc_tour_length(p, t_nn);
   }
 
@@ -690,7 +871,7 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
     }
     if (!(lb > 0.0) || (double)(float)(1.0 / (p->rho * lb)) * (double)hmax >= (double)FLT_MAX / 2 ||
         (double)tmin_f * (double)hmin < (double)FLT_MIN * 2) {
-      free(cand); free(heur); free(nl); free(t_nn);
+      free(cand); free(heur); free(nl); free(nl_in); free(t_nn);
       return -2;
     }
   }
@@ -723,7 +904,7 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
       /* Alg. 1 applies the local search to every constructed tour
          (local_search = 2); the iteration best is then taken among the
          improved tours */
-      if (p->local_search == 2) orc_two_opt(p, nl, k_ls, min_gain, ta);
+      if (p->local_search == 2) LOCAL_SEARCH(ta);
       lens[a] = orc_tour_length(p, ta);
     }
     /* iteration best: the first ant with the smallest length */
@@ -733,7 +914,7 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
     memcpy(t_ib, tours + (int64_t)ib * n, 4 * (size_t)n);
     double l_ib = lens[ib];
     if (p->local_search == 1) {
-      orc_two_opt(p, nl, k_ls, min_gain, t_ib);
+      LOCAL_SEARCH(t_ib);
       l_ib = orc_tour_length(p, t_ib);
     }
     /* restart-best (strictly better replaces) */
@@ -846,7 +1027,8 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
     if (tr->ant_len) memcpy(tr->ant_len, lens, sizeof(double) * p->ants);
     if (tr->nn_tour) memcpy(tr->nn_tour, t_nn, 4 * (size_t)n);
   }
-  free(cand); free(heur); free(nl); free(t_nn); free(tau); free(w); free(t_gb); free(t_rb);
+#undef LOCAL_SEARCH
+  free(cand); free(heur); free(nl); free(nl_in); free(t_nn); free(tau); free(w); free(t_gb); free(t_rb);
   free(t_ib); free(tours); free(lens); free(succ); free(pred); free(vis);
   return 0;
 }

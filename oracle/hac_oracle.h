@@ -28,7 +28,8 @@ typedef struct {
   const int32_t* col;
   const float* val;
   /* MMAS / HeatACO parameters (Section IV-C).  local_search: 0 none, 1 2-opt
-     on the iteration best, 2 2-opt on every ant's tour (Alg. 1) */
+     on the iteration best, 2 2-opt on every ant's tour (Alg. 1); for the
+     ATSP the directed 2-opt */
   int32_t ants, iterations, k, k_ls, local_search;
   double alpha, beta, rho, p_best, c_cap, theta_h, eps, xi_bf, lambda_bf, clip;
   int32_t degree_target, bf_period, restart_stall, ugb_max, baseline_scope;
@@ -89,6 +90,20 @@ double orc_tour_length(const orc_problem* p, const int32_t* tour);
 /* First-improvement neighbour-list 2-opt with a don't-look queue. */
 void orc_two_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min_gain,
                  int32_t* tour);
+
+/* Incoming neighbour lists of size kk: for node i the nodes j with the
+ * smallest d(j, i) (the directed 2-opt's predecessor side) */
+int32_t orc_nearest_in_lists(const orc_problem* p, int32_t kk, int32_t* out);
+/* Directed 2-opt for the ATSP (Section III-D): first improvement over the
+ * outgoing (successor side) and incoming (predecessor side) lists with a
+ * don't-look queue; each move reverses a path and prices it in its new
+ * direction. */
+void orc_two_opt_directed(const orc_problem* p, const int32_t* nl_out, const int32_t* nl_in, int32_t kk,
+                          double min_gain, int32_t* tour);
+/* One directed 2-opt move (test hook): its gain as the directed 2-opt
+ * computes it, and the tour after it in out; NAN for a degenerate move. */
+double orc_directed_move(const orc_problem* p, const int32_t* tour, int32_t a, int32_t c, int32_t dir,
+                         int32_t* out);
 
 /* Whole decode (Alg. 1).  tour_out [n] canonical, len_out.  0 on success. */
 int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc_trace* tr);

@@ -4,7 +4,7 @@ Each mutant plants one plausible mistake in a copy of oracle/hac_oracle.c:
 a dropped term, a wrong sign or operator, an off-by-one index, a flipped
 comparison or tie rule.  The copy is built with the oracle's own gcc flags,
 and the pin tests (tests/test_oracle_pins.py, tests/test_oracle_reduction.py,
-tests/test_oracle_elite.py) run against it in a subprocess (HAC_ORACLE_LIB).  At least one pin must fail
+tests/test_oracle_elite.py, tests/test_oracle_directed.py) run against it in a subprocess (HAC_ORACLE_LIB).  At least one pin must fail
 for every mutant.  The oracle source itself is never changed; every mutant
 keeps the oracle terminating.
 """
@@ -136,6 +136,22 @@ MUTANTS = [
     ("restart resets the first row only",
      "for (int64_t x = 0; x < nk; x++) { tau[x] = tmax_f; w[x] = tau[x] * heur[x]; }\n        rb_valid = 0;",
      "for (int64_t x = 0; x < k_eff; x++) { tau[x] = tmax_f; w[x] = tau[x] * heur[x]; }\n        rb_valid = 0;"),
+    ("directed 2-opt: reversed path priced in its old direction",
+     "return ((dist(p, a, b) + dist(p, c, e)) + F) - ((dist(p, a, c) + dist(p, b, e)) + B);",
+     "return ((dist(p, a, b) + dist(p, c, e)) + F) - ((dist(p, a, c) + dist(p, b, e)) + F);"),
+    ("directed 2-opt: the complement reversed instead of the path",
+     "            reverse_positions(n, tour, pos, i, j);\n            directed_prefix(p, tour, pf, pb);",
+     "            reverse_positions(n, tour, pos, (j + 1) % n, (i - 1 + n) % n);\n"
+     "            directed_prefix(p, tour, pf, pb);"),
+    ("directed 2-opt: predecessor side searches the outgoing list",
+     "const int32_t* nl = dir == 0 ? nl_out : nl_in;", "const int32_t* nl = nl_out;"),
+    ("directed 2-opt: path costs not updated after a move",
+     "            reverse_positions(n, tour, pos, i, j);\n            directed_prefix(p, tour, pf, pb);",
+     "            reverse_positions(n, tour, pos, i, j);"),
+    ("directed 2-opt: predecessor-side stop rule on the outgoing distance",
+     "double dac = dir == 0 ? dist(p, a, c) : dist(p, c, a);", "double dac = dist(p, a, c);"),
+    ("incoming lists ordered by outgoing distance",
+     "if (j != i) topk_offer(&t, dist(p, j, i), j);", "if (j != i) topk_offer(&t, dist(p, i, j), j);"),
 ]
 
 # Mutants of the elite schedule and the restart (Section III-B).  Each must
@@ -174,13 +190,14 @@ def _build(tmp, x, old, new):
     return so
 
 
-PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_reduction.py", "tests/test_oracle_elite.py"]
+PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_reduction.py", "tests/test_oracle_elite.py",
+             "tests/test_oracle_directed.py"]
 
 
 def _pins_fail(so, files=tuple(PIN_FILES)):
     env = dict(os.environ, HAC_ORACLE_LIB=so)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
-                        *files], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+                        *files], cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     return r.returncode, r.stdout[-600:]
 
 
