@@ -126,8 +126,6 @@ hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_para
   if (p->alpha != 1.0) return fail(HAC_EUNSUPPORTED, "only alpha = 1 is supported");
   if (p->k > HAC_MAX_K) return fail(HAC_EUNSUPPORTED, "k above HAC_MAX_K");
   if (p->local_search && p->k_ls > HAC_MAX_KLS) return fail(HAC_EUNSUPPORTED, "k_ls above HAC_MAX_KLS");
-  if (p->local_search && inst->kind == HAC_MATRIX && !inst->symmetric)
-    return fail(HAC_EUNSUPPORTED, "2-opt needs a symmetric instance");
   return HAC_OK;
 }
 
@@ -144,6 +142,7 @@ Layout make_layout(const hac_instance* inst, const hac_csr* csr, const hac_param
   L.iterations = p->iterations;
   L.coords = inst->kind == HAC_COORDS_EUC2D;
   L.ls = p->local_search != 0;
+  L.directed = L.ls && inst->kind == HAC_MATRIX && !inst->symmetric;
   L.ls_tours = p->local_search == 2 ? p->ants : 1;
   L.nnz = csr->nnz;
   L.gside = (L.coords && L.n >= kGridMinN) ? grid_side(L.n) : 0;
@@ -160,7 +159,8 @@ size_t Layout::bytes() const {
   b += n <= 65535 ? align256(128 * nn) : 0;
   b += align256(4 * nn * (size_t)ants) + align256(8 * (size_t)ants);
   b += 6 * align256(4 * nn);
-  b += ls ? align256(12 * nn * (size_t)ls_tours) : 0;
+  b += ls ? align256((directed ? dir_work_stride(n) : 12 * nn) * (size_t)ls_tours) : 0;
+  b += directed ? align256(4 * nn * (size_t)kls) : 0;
   if (gside > 0) {
     const size_t cells = (size_t)gside * gside;
     b += align256(4 * (cells + 1)) + align256(4 * cells) + align256(4 * nn) + align256(16 * nn) +
@@ -195,7 +195,8 @@ void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve) {
   d.nn_tour = (int32_t*)carve(4 * nn);
   d.succ = (int32_t*)carve(4 * nn);
   d.pred = (int32_t*)carve(4 * nn);
-  d.ls_work = L.ls ? (int32_t*)carve(12 * nn * (size_t)L.ls_tours) : nullptr;
+  d.ls_work = L.ls ? (int32_t*)carve((L.directed ? dir_work_stride(L.n) : 12 * nn) * (size_t)L.ls_tours) : nullptr;
+  d.nl_in = L.directed ? (int32_t*)carve(4 * nn * (size_t)L.kls) : nullptr;
   d.gside = L.gside;
   if (L.gside > 0) {
     const size_t cells = (size_t)L.gside * L.gside;
@@ -450,12 +451,13 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   HAC_HIP(launch_grid(d_descs, count, s));
   HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
   bool any_ls = false;
-  int32_t all_coords = 1;
+  int32_t all_coords = 1, max_n_dir = 0;
   for (auto& h : hs) {
     any_ls |= h.p.local_search != 0;
-    if (!h.lay.coords) all_coords = 0;
+    if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n);
+    else if (h.p.local_search && !h.lay.coords) all_coords = 0;
   }
-  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n, all_coords, s));
+  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n, all_coords, max_n_dir, s));
   std::vector<State> sts(count);
   if (stage) {
     // after the weights' scatter on the same stream: the staging arena is reused
@@ -1124,13 +1126,14 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   LaunchShape used{0, 0, 0, 0, 0};
   if (m > 0) {
     bool any_ls = false;
-    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1;
+    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0;
     for (auto& h : hs) {
       any_ls |= h.p.local_search != 0;
       if (h.p.local_search == 2) ls_tours = std::max(ls_tours, h.p.ants);
       max_iter = std::max(max_iter, h.p.iterations);
       max_n = std::max(max_n, h.lay.n);
-      if (!h.lay.coords) all_coords = 0;
+      if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n);
+      else if (h.p.local_search && !h.lay.coords) all_coords = 0;
     }
     LaunchShape shape{4, 0, 16, 4, 0};
     if (noalloc) {
@@ -1168,7 +1171,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
                                       shape.bytes, shape.kmax, lds, shape.geo, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
-        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, s);
+        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, s);
         if (e != hipSuccess) return e;
       }
       return launch_iter_end(d_descs, m, s);
@@ -1192,7 +1195,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
                                       shape.bytes, shape.kmax, lds, shape.geo, s));
         CTX_HIP(hipEventRecord(ev[1], s));
-        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, s));
+        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, s));
         CTX_HIP(hipEventRecord(ev[2], s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
         CTX_HIP(hipEventRecord(ev[3], s));

@@ -78,7 +78,9 @@ struct InstDesc {
   int32_t* succ;              // [n]
   int32_t* pred;              // [n]
   int32_t* ls_work;           // [3n] pos, queue, in-queue for 2-opt ([ants][3n] when
-                              // every ant's tour is searched)
+                              // every ant's tour is searched; dir_work_stride(n) bytes
+                              // per tour for the directed 2-opt's arrays)
+  int32_t* nl_in;             // [n][kls] incoming lists (ATSP with local search), else null
   int32_t gside;              // grid cells per side (0: no grid)
   int32_t* g_start;           // [side^2 + 1] first slot of each cell
   int32_t* g_cur;             // [side^2] build cursors
@@ -101,6 +103,14 @@ __host__ __device__ inline bool tour_checksums_ok(int32_t n, uint32_t sum, uint3
   const uint64_t N = (uint64_t)n;
   return sum == (uint32_t)(N * (N - 1) / 2) && sum_sq == (uint32_t)((N - 1) * N * (2 * N - 1) / 6);
 }
+
+// Bytes of the directed 2-opt's arrays for n nodes (edge lengths and prefix
+// sums in both directions, tour, positions, queue, in-queue flags), and the
+// 256-byte-aligned stride of one tour's part of the work area.
+__host__ __device__ inline size_t dir_work_bytes(int32_t n) {
+  return (size_t)8 * (4 * (size_t)n + 2) + (size_t)12 * n + (((size_t)n + 7) & ~(size_t)7);
+}
+__host__ __device__ inline size_t dir_work_stride(int32_t n) { return (dir_work_bytes(n) + 255) & ~(size_t)255; }
 
 // One entry per construction block: instance and first ant (inst < 0: idle)
 struct BlockMap {
@@ -137,8 +147,11 @@ hipError_t launch_candidates(const InstDesc* d_insts, int32_t count, int32_t max
 hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
 // 2-opt launches: all_coords = 1 when every instance of the batch has
 // coordinates (the FP32-filtered LDS mode needs them)
+// max_n_dir: largest ATSP instance with local search (0: none); such
+// instances take the directed 2-opt (and their incoming lists are built
+// first), the others the symmetric one
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
-                             hipStream_t s);
+                             int32_t max_n_dir, hipStream_t s);
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 // builds the coordinate grid of every instance that has one
 hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s);
@@ -152,7 +165,8 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
 // tours_per_inst: blocks per instance (the largest ant count among instances
 // that search every ant's tour, else 1)
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
-                               int32_t all_coords, int32_t tours_per_inst, hipStream_t s);
+                               int32_t all_coords, int32_t tours_per_inst, int32_t max_n_dir,
+                               hipStream_t s);
 hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const* d_out_tours,
                          double* d_out_lens, hipStream_t s);

@@ -817,7 +817,7 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
 template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) two_opt_nn_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
-  if (!D.local_search) return;
+  if (!D.local_search || !D.sym) return;  // the ATSP takes the directed 2-opt
   two_opt_tour<MODE>(D, D.nn_tour, D.st->min_gain, D.ls_work);
   if (threadIdx.x < WAVE) {
     const double len = tour_length_wave(D, D.nn_tour);
@@ -1592,7 +1592,7 @@ __device__ void iteration_best_wave(const InstDesc& D, int& ib, double& lib) {
 template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
-  if (!D.local_search || D.st->t > D.iterations || D.st->err) return;
+  if (!D.local_search || !D.sym || D.st->t > D.iterations || D.st->err) return;
   const int n = D.n;
   if (D.local_search == 2) {
     for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
@@ -1627,6 +1627,263 @@ __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const Ins
       D.st->ib = ib;
       D.st->l_ib = len;
     }
+  }
+}
+
+// ------------------------------------------------------------------------
+// Directed 2-opt for the ATSP (Section III-D), one wave per tour.
+//
+// A move reverses the tour path between its two inner nodes and prices it in
+// its new direction: on the successor side of node a (b = succ a, c from a's
+// outgoing list, e = succ c) the edges (a->b), (c->e) become (a->c), (b->e)
+// and the path b..c is reversed; on the predecessor side (b = pred a, c from
+// a's incoming list, e = pred c) (b->a), (e->c) become (c->a), (e->b) and
+// the path c..b is reversed.  gain = (removed edges + F) - (added edges + B)
+// with F and B the path's cost in its old and new direction, from prefix
+// sums of the directed edge lengths in tour order (pf, pb), which one lane
+// adds up in tour order after each move, from the first position whose edge
+// changed, so that they are the sums of a full recomputation.  The queue,
+// the side order, the list stop rule, the threshold, the re-queueing of the
+// end nodes and the re-examination of a are those of the symmetric 2-opt;
+// the reversed part is always the path itself, and a search applies at most
+// 64 n moves.  The 64 lanes evaluate a's moves at once: lanes 0..31 the
+// successor side in list order, 32..63 the predecessor side; the first
+// improving move in that order is the sequential one.
+// ------------------------------------------------------------------------
+struct DirWork {
+  double* ef;   // [n] d(T[q], T[q+1]) (the closing edge at n - 1)
+  double* eb;   // [n] d(T[q+1], T[q])
+  double* pf;   // [n + 1] prefix sums of ef
+  double* pb;   // [n + 1] prefix sums of eb
+  int32_t* tour;
+  int32_t* pos;
+  int32_t* queue;
+  uint8_t* inq;
+};
+
+__device__ __forceinline__ DirWork dir_work_at(char* base, int n) {
+  DirWork w;
+  w.ef = reinterpret_cast<double*>(base);
+  w.eb = w.ef + n;
+  w.pf = w.eb + n;
+  w.pb = w.pf + (n + 1);
+  w.tour = reinterpret_cast<int32_t*>(w.pb + (n + 1));
+  w.pos = w.tour + n;
+  w.queue = w.pos + n;
+  w.inq = reinterpret_cast<uint8_t*>(w.queue + n);
+  return w;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+}
+
+// edge lengths from position q0 on, then the prefix sums from q0 (one lane,
+// in tour order; the sums before q0 do not change)
+__device__ void dir_prefix(const HAC_AS1 double* d, int n, const DirWork& w, int q0) {
+  const int lane = lane_id();
+  for (int q = q0 + lane; q < n; q += WAVE) {
+    const int x = w.tour[q], y = w.tour[q + 1 == n ? 0 : q + 1];
+    w.ef[q] = d[(int64_t)x * n + y];
+    w.eb[q] = d[(int64_t)y * n + x];
+  }
+  wave_sync();
+  if (lane == 0) {
+    double f = w.pf[q0], b = w.pb[q0];
+    for (int q = q0; q < n; ++q) {
+      f = f + w.ef[q];
+      b = b + w.eb[q];
+      w.pf[q + 1] = f;
+      w.pb[q + 1] = b;
+    }
+  }
+  wave_sync();
+}
+
+__device__ __forceinline__ double dir_path_cost(const double* pre, int n, int i, int j) {
+  return i <= j ? pre[j] - pre[i] : (pre[n] - pre[i]) + pre[j];
+}
+
+__device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain, const DirWork& w) {
+  const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id();
+  if (n < 5 || kls < 1) return;
+  const HAC_AS1 double* d = as_global(D.dist);
+  const HAC_AS1 int32_t* out_l = as_global(D.geo);   // outgoing lists: d(a, .) order
+  const HAC_AS1 int32_t* in_l = as_global(D.nl_in);  // incoming lists: d(., a) order
+  for (int s = lane; s < n; s += WAVE) {
+    const int v = tour_g[s];
+    w.tour[s] = v;
+    w.queue[s] = v;
+  }
+  wave_sync();
+  for (int s = lane; s < n; s += WAVE) {
+    w.pos[w.tour[s]] = s;
+    w.inq[w.tour[s]] = 1;
+  }
+  if (lane == 0) {
+    w.pf[0] = 0.0;
+    w.pb[0] = 0.0;
+  }
+  wave_sync();
+  dir_prefix(d, n, w, 0);
+  const int64_t max_moves = 64 * (int64_t)n;
+  int64_t moves = 0;
+  int head = 0, count = n, pend = -1;
+  const bool pred_side = lane >= 32;
+  const int q = lane & 31;
+  const bool in_list = q < kls;
+  while (moves < max_moves) {
+    int a = pend;
+    if (a < 0) {
+      if (count == 0) break;
+      a = w.queue[head];
+      head = head + 1 == n ? 0 : head + 1;
+      --count;
+      if (lane == 0) w.inq[a] = 0;
+      wave_sync();
+    }
+    const int pa = w.pos[a];
+    const int b = pred_side ? w.tour[pa == 0 ? n - 1 : pa - 1] : w.tour[pa + 1 == n ? 0 : pa + 1];
+    const int c = pred_side ? in_l[(int64_t)a * kls + (in_list ? q : 0)] : out_l[(int64_t)a * kg + (in_list ? q : 0)];
+    const double dab = pred_side ? d[(int64_t)b * n + a] : d[(int64_t)a * n + b];
+    const double dac = pred_side ? d[(int64_t)c * n + a] : d[(int64_t)a * n + c];
+    const bool g1pos = dab - dac > 0.0;
+    // a side stops at its first list entry that cannot gain
+    const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !g1pos);
+    const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
+    const int lim = pred_side ? (stop_p ? (int)__builtin_ctzll(stop_p) : 32)
+                              : (stop_s ? (int)__builtin_ctzll(stop_s) : 32);
+    const bool ok = in_list && q < lim;
+    const int pc = w.pos[c];
+    const int e = pred_side ? w.tour[pc == 0 ? n - 1 : pc - 1] : w.tour[pc + 1 == n ? 0 : pc + 1];
+    const bool degenerate = e == a || c == b || c == a;
+    int i = 0, j = 0;
+    bool imp = false;
+    if (ok && !degenerate) {
+      i = pred_side ? pc : w.pos[b];
+      j = pred_side ? w.pos[b] : pc;
+      const double F = dir_path_cost(w.pf, n, i, j), B = dir_path_cost(w.pb, n, i, j);
+      double gain;
+      if (pred_side)
+        gain = ((dab + d[(int64_t)e * n + c]) + F) - ((dac + d[(int64_t)e * n + b]) + B);
+      else
+        gain = ((dab + d[(int64_t)c * n + e]) + F) - ((dac + d[(int64_t)b * n + e]) + B);
+      imp = gain > min_gain;
+    }
+    const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
+    if (!mi) {
+      pend = -1;
+      continue;
+    }
+    const int l = (int)__builtin_ctzll(mi);
+    const int mb = rd_lane(b, l), mc = rd_lane(c, l), me = rd_lane(e, l);
+    const int mi_ = rd_lane(i, l), mj = rd_lane(j, l);
+    // reverse the positions mi_..mj (cyclic)
+    const int len = ((mj - mi_ + n) % n) + 1;
+    for (int s = lane; s < len / 2; s += WAVE) {
+      int x = mi_ + s;
+      if (x >= n) x -= n;
+      int y = mj - s;
+      if (y < 0) y += n;
+      const int tx = w.tour[x], ty = w.tour[y];
+      w.tour[x] = ty;
+      w.tour[y] = tx;
+      w.pos[ty] = x;
+      w.pos[tx] = y;
+    }
+    wave_sync();
+    // the end nodes join the queue tail in the order a, b, c, e if absent
+    if (lane == 0) {
+      const int ends[4] = {a, mb, mc, me};
+      for (int z = 0; z < 4; ++z) {
+        const int x = ends[z];
+        if (!w.inq[x]) {
+          int slot = head + count;
+          if (slot >= n) slot -= n;
+          w.queue[slot] = x;
+          ++count;
+          w.inq[x] = 1;
+        }
+      }
+    }
+    count = rd_lane(count, 0);
+    wave_sync();
+    dir_prefix(d, n, w, (mi_ <= mj && mi_ >= 1) ? mi_ - 1 : 0);
+    ++moves;
+    pend = a;
+  }
+  for (int s = lane; s < n; s += WAVE) tour_g[s] = w.tour[s];
+  wave_sync();
+}
+
+// the directed 2-opt's working arrays: in LDS when the launch gave room for
+// them (lds_ok), else in the tour's part of the work area
+__device__ __forceinline__ DirWork dir_work_for(const InstDesc& D, int lds_ok, int tour_index) {
+  extern __shared__ __align__(16) char dir_lds[];
+  return dir_work_at(lds_ok ? dir_lds
+                            : reinterpret_cast<char*>(D.ls_work) + (int64_t)tour_index * dir_work_stride(D.n),
+                     D.n);
+}
+
+// incoming lists: for node i the kls nodes j with the smallest d(j, i),
+// ties to the lower index (one wave per node; blockIdx.y is the instance)
+__global__ void __launch_bounds__(256) in_lists_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.y];
+  if (!D.local_search || D.sym) return;
+  const int n = D.n, kls = D.kls, lane = lane_id();
+  const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+  if (i >= n) return;
+  const HAC_AS1 double* d = as_global(D.dist);
+  WaveTopK t;
+  topk_init(t, kls);
+  for (int j0 = 0; j0 < n; j0 += WAVE) {
+    const int j = j0 + lane;
+    const bool valid = j < n && j != i;
+    topk_offer(t, valid ? d[(int64_t)j * n + i] : 0.0, j, valid);
+  }
+  if (lane < kls) D.nl_in[(int64_t)i * kls + lane] = t.id;
+}
+
+__global__ void __launch_bounds__(WAVE) directed_two_opt_nn_kernel(const InstDesc* insts, int lds_ok) {
+  const InstDesc& D = insts[blockIdx.x];
+  if (!D.local_search || D.sym) return;
+  dir_two_opt(D, D.nn_tour, D.st->min_gain, dir_work_for(D, lds_ok, 0));
+  const double len = tour_length_wave(D, D.nn_tour);
+  if (threadIdx.x == 0) {
+    D.st->l_gb = len;
+    D.st->l_ib = len;
+  }
+}
+
+// local_search = 1: block (i, 0) improves a copy of the iteration best;
+// local_search = 2: block (i, y) improves ant tours y, y + gridDim.y, ...
+__global__ void __launch_bounds__(WAVE) directed_local_search_kernel(const InstDesc* insts, int lds_ok) {
+  const InstDesc& D = insts[blockIdx.x];
+  if (!D.local_search || D.sym || D.st->t > D.iterations || D.st->err) return;
+  const int n = D.n;
+  if (D.local_search == 2) {
+    for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
+      int32_t* tour = D.tours + (int64_t)a * n;
+      dir_two_opt(D, tour, D.st->min_gain, dir_work_for(D, lds_ok, a));
+      const double len = tour_length_wave(D, tour);
+      if (threadIdx.x == 0) D.lens[a] = len;
+      wave_sync();
+    }
+    return;
+  }
+  if (blockIdx.y != 0) return;
+  int ib;
+  double lib;
+  iteration_best_wave(D, ib, lib);
+  const int32_t* src = D.tours + (int64_t)ib * n;
+  for (int s = threadIdx.x; s < n; s += WAVE) D.t_ib[s] = src[s];
+  wave_sync();
+  dir_two_opt(D, D.t_ib, D.st->min_gain, dir_work_for(D, lds_ok, 0));
+  const double len = tour_length_wave(D, D.t_ib);
+  if (threadIdx.x == 0) {
+    D.st->ib = ib;
+    D.st->l_ib = len;
   }
 }
 
@@ -1930,8 +2187,36 @@ static int ls_mode(int32_t max_n, int32_t all_coords) {
   return 0;
 }
 
+// LDS for the directed 2-opt of the largest ATSP instance, or 0 when its
+// arrays go to the work area in global memory
+static size_t dir_lds_bytes(int32_t max_n_dir) {
+  if (const char* f = std::getenv("HAC_LS_MODE"))
+    if (f[0] == '0') return 0;  // pins the work area to global memory (as for the symmetric 2-opt)
+  const size_t need = dir_work_bytes(max_n_dir);
+  return need <= (size_t)max_lds_bytes() - 1024 ? need : 0;
+}
+
+static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_t max_n_dir, int32_t tpi,
+                                  bool nn, hipStream_t s) {
+  const size_t lds = dir_lds_bytes(max_n_dir);
+  if (nn)
+    hipLaunchKernelGGL(directed_two_opt_nn_kernel, dim3(count), dim3(WAVE), lds, s, d_insts, lds ? 1 : 0);
+  else
+    hipLaunchKernelGGL(directed_local_search_kernel, dim3(count, std::max(tpi, 1)), dim3(WAVE), lds, s, d_insts,
+                       lds ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
-                             hipStream_t s) {
+                             int32_t max_n_dir, hipStream_t s) {
+  if (max_n_dir > 0) {
+    const int waves = 4;
+    hipLaunchKernelGGL(in_lists_kernel, dim3((max_n_dir + waves - 1) / waves, count), dim3(waves * WAVE), 0, s,
+                       d_insts);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_directed(d_insts, count, max_n_dir, 1, true, s);
+    if (e != hipSuccess) return e;
+  }
   const int mode = ls_mode(max_n, all_coords);
   const dim3 grid(count), block(LS_WAVES * WAVE);
   if (mode == 2)
@@ -2122,7 +2407,12 @@ static int ls_block_waves(int32_t max_n, int mode, int64_t tours) {
 }
 
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
-                               int32_t all_coords, int32_t tours_per_inst, hipStream_t s) {
+                               int32_t all_coords, int32_t tours_per_inst, int32_t max_n_dir,
+                               hipStream_t s) {
+  if (max_n_dir > 0) {
+    const hipError_t e = launch_directed(d_insts, count, max_n_dir, tours_per_inst, false, s);
+    if (e != hipSuccess) return e;
+  }
   const int mode = ls_mode(max_n, all_coords);
   const int tpi = std::max(tours_per_inst, 1);
   const int waves = tpi > 1 ? ls_block_waves(max_n, mode, (int64_t)count * tpi) : LS_WAVES;

@@ -33,6 +33,7 @@ class DeviceArena {
 struct Layout {
   int32_t n, k, kg, kls, ants, iterations;
   bool coords, ls;
+  bool directed;     // the ATSP with local search: directed 2-opt (incoming lists, larger work area)
   int32_t ls_tours;  // tours with their own 2-opt work area (ants when every ant is searched)
   int32_t gside;  // coordinate grid cells per side (0: none)
   int64_t nnz;

@@ -35,7 +35,7 @@ def sweep_cases(count: int = 96, seed: int = 2601):
         topk = int(rng.integers(2, 16))
         ants = int(rng.integers(1, 7 if large else 25))
         iterations = int(rng.integers(1, 4 if large else 26))
-        ls = 0 if kind == "atsp" else int(rng.choice([0, 0, 1, 2]))
+        ls = int(rng.choice([0, 0, 1, 2]))  # the ATSP takes the directed 2-opt
         k_ls = int(rng.integers(1, 25))
         heat = "empty" if rng.random() < 0.1 else "softdist"
         grid = None

@@ -73,7 +73,7 @@ def test_validate_host_only(hac):
     assert hac.validate(inst, local_search=1, k_ls=40) == hac.HAC_EUNSUPPORTED
     at = wl.random_instance(20, seed=4, kind="matrix", symmetric=False)
     assert hac.validate(at) == hac.HAC_OK
-    assert hac.validate(at, local_search=1) == hac.HAC_EUNSUPPORTED
+    assert hac.validate(at, local_search=1) == hac.HAC_OK  # the directed 2-opt
     sm = wl.random_instance(20, seed=4, kind="matrix", symmetric=True)
     sm.dist = sm.dist.copy()
     sm.dist[1, 2] += 1e-3
