@@ -421,6 +421,7 @@ def sub_serve(hac, wl, mix, reqs, budget_gb, slots, plain_per_kind=4):
         results.append((tour, L))
     wall = time.perf_counter() - t_start
     cnt = srv.counters()
+    lanes = srv.lane_stats()
     srv.close()
     ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in reqs)
     print("bench: serve plain decodes", file=sys.stderr, flush=True)
@@ -456,7 +457,8 @@ def sub_serve(hac, wl, mix, reqs, budget_gb, slots, plain_per_kind=4):
             "plain": {"decodes_per_s": plain_dps, "decodes_per_kind": plain_per_kind,
                       "note": "requests of each kind decoded alone, mean time weighted by the mix"},
             "served_vs_plain": (count / wall) / plain_dps, "equal_gap": equal,
-            "saturated_decodes_per_s": sat, "arrival_rate_per_s": rate, "server": cnt}
+            "saturated_decodes_per_s": sat, "arrival_rate_per_s": rate, "server": cnt,
+            "lanes": [{k: (round(v, 1) if isinstance(v, float) else v) for k, v in ln.items()} for ln in lanes]}
 
 
 def run_serve(args, hac, wl, cpu):

@@ -287,10 +287,14 @@ hac_status hac_debug_trace(hac_ctx* ctx, int32_t which, double* l_ib, double* l_
 
 /* ---- continuous-batching request loop ----------------------------------
  * A server owns a device memory budget and a number of instance slots.
- * Submitted requests are queued; a loop thread admits them while a slot is
- * free and the request's device footprint fits in the free budget, and
- * advances all admitted instances together, iteration by iteration, so
- * that requests arriving while others run join the running batch.  Each
+ * Submitted requests are queued by size class of n (below 768, below 4096,
+ * larger).  Each class has a loop thread and a stream of its own: it
+ * admits the class's requests while a slot is free (slots go to requests
+ * in arrival order across the classes) and the request's device footprint
+ * fits in the free budget, and advances the class's admitted instances
+ * together, iteration by iteration, so that requests arriving while others
+ * run join the running batch, and the classes run concurrently on the
+ * device.  Each
  * instance's pheromone, candidate lists and best tours stay on the device
  * from admission to completion.  Results equal hac_decode's. */
 
@@ -298,6 +302,10 @@ hac_status hac_debug_trace(hac_ctx* ctx, int32_t which, double* l_ib, double* l_
  * lists, heuristic, pheromone and weights, ant tours and best tours. */
 uint64_t hac_footprint(const hac_instance* inst, const hac_csr* heat, const hac_params* p);
 
+/* The server runs its smallest size class on ctx's stream and two streams
+ * of its own for the others; ctx must outlive it, and calls on ctx while
+ * the server runs share that stream.  HIP's default of four hardware
+ * queues per process then holds the three classes and the null stream. */
 hac_status hac_server_create(hac_ctx* ctx, uint64_t budget_bytes, int32_t max_slots,
                              hac_server** out);
 /* Queues a request.  Inputs are copied before return.  HAC_ENOMEM if the
@@ -317,6 +325,23 @@ hac_status hac_server_cancel(hac_server* srv, uint64_t ticket);
 /* Counters: requests admitted, completed, peak concurrent slots, peak bytes. */
 hac_status hac_server_counters(hac_server* srv, int64_t* admitted, int64_t* completed,
                                int32_t* peak_slots, uint64_t* peak_bytes);
+/* Per-lane figures of a server (lane 0, 1, 2: n below 768, below 4096,
+ * larger), counted since hac_server_create.  Wall-clock times of the
+ * lane's loop thread: prep_ms preparing admitted instances (uploads,
+ * candidate lists, fold, NN tour), round_ms running rounds of iterations
+ * up to their completion on the device, idle_ms waiting for work.
+ * instance_iterations sums the admitted instances over every iteration
+ * the lane ran. */
+typedef struct hac_lane_stats {
+  int32_t min_n, max_n;        /* the lane's size class, max_n exclusive (0: none) */
+  int64_t admitted, completed; /* requests                                  */
+  int64_t rounds, iterations, instance_iterations;
+  int32_t peak_active;         /* most instances held at once               */
+  double prep_ms, round_ms, idle_ms;
+} hac_lane_stats;
+#define HAC_SERVER_LANES 3
+/* HAC_EINVAL for a lane outside 0 .. HAC_SERVER_LANES - 1. */
+hac_status hac_server_lane_stats(hac_server* srv, int32_t lane, hac_lane_stats* out);
 /* Stops the loop (cancelling what is left) and frees the server. */
 void hac_server_destroy(hac_server* srv);
 

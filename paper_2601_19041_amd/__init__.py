@@ -68,6 +68,16 @@ class hac_diagnostics(ctypes.Structure):
                 ("evidence_on_tour", ctypes.c_int64)]
 
 
+class hac_lane_stats(ctypes.Structure):
+    _fields_ = [("min_n", ctypes.c_int32), ("max_n", ctypes.c_int32), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("rounds", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("instance_iterations", ctypes.c_int64), ("peak_active", ctypes.c_int32),
+                ("prep_ms", ctypes.c_double), ("round_ms", ctypes.c_double), ("idle_ms", ctypes.c_double)]
+
+
+SERVER_LANES = 3
+
+
 class hac_stats(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
                 ("search_ms", ctypes.c_double), ("construct_ms", ctypes.c_double),
@@ -89,7 +99,8 @@ EXPORTS = ["hac_params_default", "hac_strerror", "hac_validate", "hac_create", "
            "hac_decode_batch_dev",
            "hac_last_stats", "hac_debug_state", "hac_debug_trace", "hac_footprint",
            "hac_server_create", "hac_server_submit", "hac_server_poll", "hac_server_wait",
-           "hac_server_cancel", "hac_server_counters", "hac_server_destroy", "hac_heatmap_diagnostics"]
+           "hac_server_cancel", "hac_server_counters", "hac_server_lane_stats", "hac_server_destroy",
+           "hac_heatmap_diagnostics"]
 
 _lib = None
 
@@ -156,6 +167,8 @@ def lib():
             L.hac_server_cancel.restype = i32
             L.hac_server_counters.argtypes = [vp, vp, vp, vp, vp]
             L.hac_server_counters.restype = i32
+            L.hac_server_lane_stats.argtypes = [vp, i32, ctypes.POINTER(hac_lane_stats)]
+            L.hac_server_lane_stats.restype = i32
             L.hac_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
@@ -466,6 +479,17 @@ class Server:
         lib().hac_server_counters(self._h, ctypes.byref(a), ctypes.byref(c), ctypes.byref(ps),
                                   ctypes.byref(pb))
         return dict(admitted=a.value, completed=c.value, peak_slots=ps.value, peak_bytes=pb.value)
+
+    def lane_stats(self) -> list:
+        """Per-lane counters (hac_server_lane_stats), one dict per size class."""
+        out = []
+        for lane in range(SERVER_LANES):
+            st = hac_lane_stats()
+            code = lib().hac_server_lane_stats(self._h, lane, ctypes.byref(st))
+            if code != HAC_OK:
+                raise HacError(code, f"hac_server_lane_stats: {strerror(code)}")
+            out.append({name: getattr(st, name) for name, _ in hac_lane_stats._fields_})
+        return out
 
     def close(self):
         if self._h:

@@ -720,38 +720,57 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     *ok = false;
     return best;
   }
-  for (const LaunchShape& sh : cands) {
+  // shortest of `reps` launches of shape sh, each ant stopping after `cap`
+  // tour positions (construction only reads the state, so repeating it is
+  // harmless); negative on a failed call
+  auto time_shape = [&](const LaunchShape& sh, int32_t cap, int reps) -> float {
     std::vector<BlockMap> map = build_block_map(hs, sh.ants_per_block);
     scratch.reset();
-    if (scratch.reserve(map.size() * sizeof(BlockMap)) != hipSuccess) {
-      *ok = false;
-      break;
-    }
+    if (scratch.reserve(map.size() * sizeof(BlockMap)) != hipSuccess) return -1.0f;
     BlockMap* d_map = (BlockMap*)scratch.carve(map.size() * sizeof(BlockMap));
     if (hipMemcpyAsync(d_map, map.data(), map.size() * sizeof(BlockMap), hipMemcpyHostToDevice, s) !=
-        hipSuccess) {
-      *ok = false;
-      break;
-    }
-    // construction only reads the state, so repeating it is harmless
+        hipSuccess)
+      return -1.0f;
     float ms_min = 1e30f;
-    for (int rep = 0; rep < 2; ++rep) {
+    for (int rep = 0; rep < reps; ++rep) {
       (void)hipEventRecord(e0, s);
-      (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block,
-                             sh.rows_per_wave, sh.staged, sh.bytes, sh.kmax, shape_lds(hs, sh), sh.geo, s);
+      (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block, sh.rows_per_wave,
+                             sh.staged, sh.bytes, sh.kmax, shape_lds(hs, sh), sh.geo, s, cap);
       (void)hipEventRecord(e1, s);
-      if (hipEventSynchronize(e1) != hipSuccess) {
-        *ok = false;
-        break;
-      }
+      if (hipEventSynchronize(e1) != hipSuccess) return -1.0f;
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e0, e1);
       ms_min = std::min(ms_min, ms);
     }
-    if (!*ok) break;
-    if (ms_min < best_ms) {
-      best_ms = ms_min;
-      best = sh;
+    return ms_min;
+  };
+  // Successive halving for large instances: every candidate is timed once
+  // on the first eighth of the tours, and the four fastest are then timed on
+  // whole tours (a whole launch of a 10^4-node batch takes milliseconds, and
+  // a serving lane tunes whenever its batch changes class).  Smaller
+  // instances are timed whole, twice.
+  int32_t max_n = 0;
+  for (auto& h : hs) max_n = std::max(max_n, h.lay.n);
+  const int32_t prefix = std::max<int32_t>(512, max_n / 8);
+  const bool halve = prefix < max_n && cands.size() > 4;
+  std::vector<std::pair<float, size_t>> first;
+  for (size_t x = 0; x < cands.size() && *ok; ++x) {
+    const float ms = time_shape(cands[x], halve ? prefix : INT32_MAX, halve ? 1 : 2);
+    if (ms < 0.0f) *ok = false;
+    first.emplace_back(ms, x);
+  }
+  if (*ok && halve) {
+    std::sort(first.begin(), first.end());
+    first.resize(4);
+    for (auto& f : first) {
+      f.first = time_shape(cands[f.second], INT32_MAX, 1);
+      if (f.first < 0.0f) *ok = false;
+    }
+  }
+  for (auto& f : first) {
+    if (*ok && f.first < best_ms) {
+      best_ms = f.first;
+      best = cands[f.second];
     }
   }
   (void)hipEventDestroy(e0);
@@ -784,6 +803,8 @@ struct hac_ctx {
   std::vector<HostInst> last;  // descriptors of the last call (debug hooks)
   std::vector<hipEvent_t> events;
 };
+
+hipStream_t hac_context_stream(const hac_ctx* ctx) { return ctx->stream; }
 
 static hac_status set_err(hac_ctx* c, hac_status s, const std::string& m) {
   if (c) c->err = m;

@@ -1392,7 +1392,7 @@ template <int STAGED, int S, bool BYTES>
 __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
                                                          int ants_per_block, int rows_per_wave,
-                                                         int lds_bytes, int geo_mode) {
+                                                         int lds_bytes, int geo_mode, int step_cap) {
   const BlockMap bm = map[blockIdx.x];
   if (bm.inst < 0) return;
   const InstDesc I = insts[bm.inst];  // by value: the fields stay in registers
@@ -1514,12 +1514,14 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
   double len = 0.0;
   uint32_t csum = 0, csq = 0;  // sum and sum of squares (mod 2^32) of this lane's tour entries
   int q0 = 1;
-  for (int s0 = 0; s0 < n; s0 += 16) {
+  // a timing launch of the tuner stops after step_cap tour positions
+  const int n_pos = min(n, step_cap);
+  for (int s0 = 0; s0 < n_pos; s0 += 16) {
     if (s0 > 0) {
       rnd = philox_x0((uint32_t)(s0 + A.u), (uint32_t)ant, (uint32_t)t, 0u, k0, k1);
       q0 = 0;
     }
-    const int cnt = min(16, n - s0);
+    const int cnt = min(16, n_pos - s0);
     for (int q = q0; q < cnt; ++q) {
       const int j = A.step(row_bcast<0>(rnd));
       rnd = dpp_zero<0x101>(rnd);
@@ -1547,6 +1549,7 @@ __global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restr
     sum_row_in_order<0>(len, dl);  // adding 0.0 past the end leaves len unchanged
     carry = A.cur;
   }
+  if (n_pos < n) return;  // a partial tour: no length, no checks
   if (STAGED && xy_lds) {
     const double2 pa = xy_lds[carry], pb = xy_lds[start];
     const double dx = pa.x - pb.x, dy = pa.y - pb.y;
@@ -2360,15 +2363,15 @@ int32_t construct_group_lanes(int32_t max_k) { (void)max_k; return 16; }
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
                             int32_t bytes, int32_t max_k, size_t lds_bytes, int32_t geo_mode,
-                            hipStream_t s) {
-  if (geo_mode < 0 || geo_mode > 2) return hipErrorInvalidValue;
+                            hipStream_t s, int32_t step_cap) {
+  if (geo_mode < 0 || geo_mode > 2 || step_cap < 1) return hipErrorInvalidValue;
   if (rows_per_wave < 1 || rows_per_wave > 4) return hipErrorInvalidValue;
   const int waves = (ants_per_block + rows_per_wave - 1) / rows_per_wave;
   const dim3 grid(blocks), block(waves * WAVE);
   const int S = max_k <= 16 ? 1 : (max_k <= 32 ? 2 : 4);
 #define HAC_LAUNCH(ST, SL, BY)                                                                 \
   hipLaunchKernelGGL((construct_kernel<ST, SL, BY>), grid, block, lds_bytes, s, d_insts, d_map, \
-                     ants_per_block, rows_per_wave, (int)lds_bytes, (int)geo_mode)
+                     ants_per_block, rows_per_wave, (int)lds_bytes, (int)geo_mode, (int)step_cap)
 #define HAC_LAUNCH_S(ST, BY)             \
   {                                      \
     if (S == 1) HAC_LAUNCH(ST, 1, BY);   \

@@ -127,3 +127,10 @@ int32_t batch_max_k(const std::vector<HostInst>& hs);
 hipError_t upload_inputs(const HostInst& h, hipStream_t s);
 
 }  // namespace hac
+
+// The stream a context runs on (the request loop's first lane uses it).
+hipStream_t hac_context_stream(const hac_ctx* ctx);
+
+namespace hac {
+
+}  // namespace hac

@@ -1,12 +1,20 @@
 // Continuous-batching request loop.
 //
 // The server owns a device memory pool of `budget` bytes and admits at most
-// `max_slots` instances at a time.  Requests are split into size classes
-// (lanes); each lane has its own loop thread and HIP stream, so a large
-// instance's long iterations do not pace the small ones: their kernels run
-// concurrently on the device.  Between rounds of iterations a lane admits
-// queued requests of its class whose footprint fits a free block of the
-// shared pool (first fit, in arrival order), prepares them on the device,
+// `max_slots` instances at a time.  Requests are split into three size
+// classes by n (lanes: below 768, below 4096, and larger); each lane has
+// its own loop thread and HIP stream, so the iterations of one class do not
+// pace another's: their kernels run concurrently on the device.  Streams
+// that share a hardware queue run one after the other, and HIP gives a
+// process four queues by default, which the null stream and any other
+// context also draw on; so the first lane runs on the context's own stream
+// and only two streams are added.
+// Slots go to requests in arrival order across the lanes: a lane admits a
+// request only while the free slots exceed the requests of other lanes
+// queued before it, so that a lane whose rounds are short does not take
+// every slot a long-running lane frees.  Between rounds of iterations a lane
+// admits queued requests of its class whose footprint fits a free block of
+// the shared pool (first fit, in arrival order), prepares them on the device,
 // and then advances every instance it holds together: each round launches
 // the construction, local-search and end-of-iteration kernels once per
 // iteration over the lane's admitted set.  An instance whose iterations are
@@ -138,11 +146,18 @@ struct Lane {
   DeviceArena meta, mapa, scratch;  // descriptor arrays, block map, tuner scratch
   std::vector<Slot> active;
   std::thread loop;
+  hac_lane_stats st{};  // guarded by the server's mutex
 };
 
-// requests with at least this many nodes run in the large-instance lane
-static constexpr int32_t kLargeN = 4096;
-static constexpr int kLanes = 2;
+// lane l takes the requests with kLaneBound[l - 1] <= n < kLaneBound[l]
+static constexpr int kLanes = HAC_SERVER_LANES;
+static constexpr int32_t kLaneBound[kLanes - 1] = {768, 4096};
+
+static int lane_of(int32_t n) {
+  int l = 0;
+  while (l < kLanes - 1 && n >= kLaneBound[l]) ++l;
+  return l;
+}
 
 struct hac_server {
   hac_ctx* ctx = nullptr;
@@ -212,6 +227,9 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
   BlockMap* d_map = nullptr;
   std::vector<double> lens;
 
+  auto ms_since = [](Clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+  };
   for (;;) {
     // ---- admission ----
     std::vector<Slot> fresh;
@@ -223,9 +241,11 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
           quit = true;
           break;
         }
+        int32_t ahead = 0;  // other lanes' requests queued before this one
         for (auto it = S->queue.begin(); it != S->queue.end();) {
           auto& r = *it;
           if (r->lane != LN.id) {
+            ahead += !r->cancel;
             ++it;
             continue;
           }
@@ -236,7 +256,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
             S->cv_done.notify_all();
             continue;
           }
-          if (S->active_total + (int32_t)fresh.size() >= S->max_slots || S->stop) break;
+          if (S->active_total + (int32_t)fresh.size() + ahead >= S->max_slots || S->stop) break;
           int64_t off = S->pool.alloc(r->bytes);
           if (off < 0) {
             ++it;
@@ -253,11 +273,15 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
         if (!fresh.empty() || !LN.active.empty()) break;
         // nothing to run: sleep until a submission, release or stop
         const uint64_t seen = S->gen;
+        const Clock::time_point t_idle = Clock::now();
         S->cv_loop.wait(lk, [&] { return S->stop || S->gen != seen; });
+        LN.st.idle_ms += ms_since(t_idle);
       }
       if (quit) break;
       S->active_total += (int32_t)fresh.size();
+      LN.st.admitted += (int64_t)fresh.size();
     }
+    const Clock::time_point t_prep = Clock::now();
     // ---- preparation of the newly admitted instances ----
     if (!fresh.empty()) {
       std::vector<HostInst> hs(fresh.size());
@@ -315,12 +339,15 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
         dirty = true;
       }
       S->peak_slots = std::max(S->peak_slots, S->active_total);
+      LN.st.peak_active = std::max(LN.st.peak_active, (int32_t)LN.active.size());
+      LN.st.prep_ms += ms_since(t_prep);
       if (!ok || ps != HAC_OK) {
         S->cv_done.notify_all();
         S->cv_loop.notify_all();
       }
     }
     if (LN.active.empty()) continue;
+    const Clock::time_point t_round = Clock::now();
 
     // ---- a round of iterations over the admitted set ----
     const int32_t m = (int32_t)LN.active.size();
@@ -411,6 +438,10 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
     }
     // ---- retirement ----
     std::lock_guard<std::mutex> g(S->mu);
+    LN.st.round_ms += ms_since(t_round);
+    LN.st.rounds += 1;
+    LN.st.iterations += rounds;
+    LN.st.instance_iterations += (int64_t)rounds * m;
     std::vector<Slot> keep;
     for (int32_t x = 0; x < m; ++x) {
       Slot& sl = LN.active[x];
@@ -422,6 +453,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
         } else if (fin && !sl.req->cancel) {
           sl.req->length = lens[x];
           finish_request(S, sl.req, DONE, HAC_OK);
+          LN.st.completed += 1;
         } else {
           finish_request(S, sl.req, CANCELLED, HAC_ECANCELLED);
         }
@@ -488,15 +520,21 @@ hac_status hac_server_create(hac_ctx* ctx, uint64_t budget_bytes, int32_t max_sl
   S->max_slots = max_slots;
   for (int l = 0; l < kLanes; ++l) {
     S->lanes[l].id = l;
+    S->lanes[l].st.min_n = l == 0 ? 1 : kLaneBound[l - 1];
+    S->lanes[l].st.max_n = l == kLanes - 1 ? 0 : kLaneBound[l];
+    if (l == 0) {
+      S->lanes[0].stream = hac_context_stream(ctx);
+      continue;
+    }
     if (hipStreamCreateWithFlags(&S->lanes[l].stream, hipStreamNonBlocking) != hipSuccess) {
-      for (int q = 0; q < l; ++q) (void)hipStreamDestroy(S->lanes[q].stream);
+      for (int q = 1; q < l; ++q) (void)hipStreamDestroy(S->lanes[q].stream);
       delete S;
       return HAC_EDEVICE;
     }
   }
   hipError_t e = S->pool.init(budget_bytes);
   if (e != hipSuccess) {
-    for (int l = 0; l < kLanes; ++l) (void)hipStreamDestroy(S->lanes[l].stream);
+    for (int l = 1; l < kLanes; ++l) (void)hipStreamDestroy(S->lanes[l].stream);
     delete S;
     return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HAC_ENOMEM : HAC_EDEVICE;
   }
@@ -529,7 +567,7 @@ hac_status hac_server_submit(hac_server* S, const hac_instance* inst, const hac_
   r->csr.val = r->val.data();
   r->p = *p;
   r->seed = seed;
-  r->lane = n >= kLargeN ? 1 : 0;
+  r->lane = lane_of(n);
   r->bytes = footprint_of(inst, heat, p);
   r->t_submit = Clock::now();
   if (r->bytes > S->budget) return HAC_ENOMEM;
@@ -588,6 +626,13 @@ hac_status hac_server_counters(hac_server* S, int64_t* admitted, int64_t* comple
   return HAC_OK;
 }
 
+hac_status hac_server_lane_stats(hac_server* S, int32_t lane, hac_lane_stats* out) {
+  if (!S || !out || lane < 0 || lane >= kLanes) return HAC_EINVAL;
+  std::lock_guard<std::mutex> g(S->mu);
+  *out = S->lanes[lane].st;
+  return HAC_OK;
+}
+
 void hac_server_destroy(hac_server* S) {
   if (!S) return;
   {
@@ -602,7 +647,7 @@ void hac_server_destroy(hac_server* S) {
     if (ln.loop.joinable()) ln.loop.join();
   for (auto& ln : S->lanes) {
     (void)hipStreamSynchronize(ln.stream);
-    (void)hipStreamDestroy(ln.stream);
+    if (ln.id != 0) (void)hipStreamDestroy(ln.stream);  // lane 0 runs on the context's stream
   }
   delete S;
 }

@@ -38,6 +38,11 @@ def test_exports_every_declared_symbol(hac):
     assert sorted(hac.EXPORTS) == names
 
 
+def test_server_lane_count_matches_the_header(hac):
+    text = open(os.path.join(ROOT, "include", "hac.h")).read()
+    assert int(re.search(r"#define HAC_SERVER_LANES (\d+)", text).group(1)) == hac.SERVER_LANES
+
+
 def test_defaults_are_the_papers(hac):
     prm = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_parameters.json")))
     p = hac.params_default()

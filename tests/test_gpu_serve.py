@@ -35,6 +35,8 @@ def _mix():
     out.append(wl.random_instance(120, seed=301, k=10, ants=8, iterations=9, local_search=1, k_ls=10))
     # 2-opt on every ant's tour (its work area is per ant)
     out.append(wl.random_instance(140, seed=303, k=10, ants=6, iterations=8, local_search=2, k_ls=10))
+    # the next size class: another lane, running concurrently
+    out.append(wl.random_instance(800, seed=304, k=8, ants=6, iterations=6))
     out.append(wl.random_instance(1, seed=302))
     return out
 
@@ -61,6 +63,7 @@ def test_served_equals_alone_under_budget(ctx, hac):
     tickets = [srv.submit(x) for x in insts]
     res = [srv.wait(t) for t in tickets]
     cnt = srv.counters()
+    srv_lanes = srv.lane_stats()
     srv.close()
     for x in range(len(insts)):
         assert np.array_equal(res[x][0], alone[x][0]), x
@@ -69,6 +72,14 @@ def test_served_equals_alone_under_budget(ctx, hac):
     assert cnt["completed"] == len(insts)
     assert cnt["peak_slots"] <= 3
     assert 0 < cnt["peak_bytes"] <= budget
+    # every request with n > 1 ran in the lane of its size class
+    lanes = srv_lanes
+    for ln in lanes:
+        want = sum(1 for x in insts if x.n > 1 and x.n >= ln["min_n"] and (ln["max_n"] == 0 or x.n < ln["max_n"]))
+        assert ln["admitted"] == want and ln["completed"] == want, ln
+        assert ln["peak_active"] <= 3
+        if want:
+            assert ln["rounds"] > 0 and ln["instance_iterations"] >= ln["iterations"] > 0
 
 
 @pytest.mark.parametrize("order_seed", [0, 1])
