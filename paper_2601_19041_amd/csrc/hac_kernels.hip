@@ -537,29 +537,19 @@ struct LsMove {
   int imp, a, b, c, e, dir;
 };
 
-// FP32 copy of the coordinates in LDS, used to decide the 2-opt tests
-// without global loads.  M is the largest coordinate magnitude.  With u =
-// 2^-24, rounding the coordinates and computing a distance in FP32 (a
-// square root within a few ulp) is off by at most 17 u M from the FP64
-// value, so
+// Mode 2 decides the 2-opt tests from an FP32 copy of the coordinates in
+// LDS.  M is the largest coordinate magnitude.  With u = 2^-24, rounding
+// the coordinates and computing a distance in FP32 (a square root within a
+// few ulp) is off by at most 17 u M from the FP64 value, so
 //   d(a,b) - d(a,c)         is within E1 = 2^-18 M (>= 34 u M + rounding),
 //   (ab + ce) - (ac + be)   is within E2 = 2^-17 M (>= 68 u M + 17 u M).
 // A lane whose FP32 result lies inside the bound recomputes its test in
 // FP64 from global memory, so every decision is the FP64 one.
-struct LsFast {
-  const float2* xy;  // null: no FP32 copy
-  double e1, e2;
-  __device__ __forceinline__ float len(int i, int j) const {
-    const float dx = xy[i].x - xy[j].x, dy = xy[i].y - xy[j].y;
-    return __builtin_sqrtf(dx * dx + dy * dy);
-  }
-};
 
 // candidate moves of node a against the current tour (one wave)
 template <class IP>
 __device__ __forceinline__ LsMove ls_eval(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls,
-                                          int n, IP tour, IP pos, int a, double min_gain,
-                                          const LsFast& F) {
+                                          int n, IP tour, IP pos, int a, double min_gain) {
   const int lane = lane_id();
   const bool pred_dir = lane >= 32;
   const int q = lane & 31;
@@ -567,26 +557,8 @@ __device__ __forceinline__ LsMove ls_eval(const GDist& G, const HAC_AS1 int32_t*
   const int c = geo[(int64_t)a * kg + min(q, kls - 1)];
   const int pa = pos[a];
   const int b = pred_dir ? tour[pa == 0 ? n - 1 : pa - 1] : tour[pa + 1 == n ? 0 : pa + 1];
-  bool g1pos;  // d(a,b) - d(a,c) > 0, as computed in FP64
-  double dab = 0.0, dac = 0.0;
-  bool have64 = false;
-  if (F.xy) {
-    // c == b gives exactly 0 (no gain); otherwise only list entries whose
-    // FP32 difference lies inside the bound are decided in FP64
-    const double g1f = (double)(F.len(a, b) - F.len(a, c));
-    g1pos = c != b && g1f > F.e1;
-    if (in_list && c != b && !(g1f > F.e1) && !(g1f < -F.e1)) {
-      dab = G.len(a, b);
-      dac = G.len(a, c);
-      have64 = true;
-      g1pos = dab - dac > 0.0;
-    }
-  } else {
-    dab = G.len(a, b);
-    dac = G.len(a, c);
-    have64 = true;
-    g1pos = dab - dac > 0.0;
-  }
+  const double dab = G.len(a, b), dac = G.len(a, c);
+  const bool g1pos = dab - dac > 0.0;
   // a direction stops at the first list entry that cannot gain
   const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !g1pos);
   const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
@@ -596,21 +568,7 @@ __device__ __forceinline__ LsMove ls_eval(const GDist& G, const HAC_AS1 int32_t*
   const int pc = pos[c];
   const int e = pred_dir ? tour[pc == 0 ? n - 1 : pc - 1] : tour[pc + 1 == n ? 0 : pc + 1];
   const bool cand = ok && e != a && c != b;  // a move that may be taken
-  bool imp;
-  if (F.xy) {
-    const double gf = (double)((F.len(a, b) + F.len(c, e)) - (F.len(a, c) + F.len(b, e)));
-    imp = gf > min_gain + F.e2;
-    if (cand && !(gf > min_gain + F.e2) && !(gf < min_gain - F.e2)) {
-      if (!have64) {
-        dab = G.len(a, b);
-        dac = G.len(a, c);
-      }
-      imp = (dab + G.len(c, e)) - (dac + G.len(b, e)) > min_gain;
-    }
-  } else {
-    imp = (dab + G.len(c, e)) - (dac + G.len(b, e)) > min_gain;
-  }
-  imp = imp && cand;
+  const bool imp = cand && (dab + G.len(c, e)) - (dac + G.len(b, e)) > min_gain;
   const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
   LsMove m{0, a, 0, 0, 0, 0};
   if (mi) {
@@ -652,8 +610,7 @@ __device__ __forceinline__ void ls_reverse(int n, IP tour, IP pos, int i, int j)
 }
 
 template <class IP, class BP>
-__device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain,
-                              const LsFast& F) {
+__device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain) {
   __shared__ int sh_head, sh_count;
   __shared__ LsMove sh_mv[LS_WAVES];
   const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
@@ -689,7 +646,7 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
         if (slot >= n) slot -= n;
         node = queue[slot];
       }
-      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, node, min_gain, F);
+      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
       if (lane == 0) sh_mv[wave] = m;
     }
     __syncthreads();
@@ -748,10 +705,205 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
   }
 }
 
+// Mode 2 of the 2-opt keeps the FP32 coordinates in tour order (txy[p] is
+// the node at position p), so one position read gives a node's tour
+// neighbour and its coordinates together: after the neighbour-list load,
+// the evaluation of a move is two dependent LDS reads deep (pos[c], then
+// tour, txy at pc and pc +- 1) instead of five.  The evaluating wave also
+// works out the path to reverse (the shorter side), so a round needs one
+// barrier after the evaluations and one after the reversal; the queue
+// bookkeeping stays in wave 0, whose LDS operations are ordered.
+struct LsMoveXY {
+  int imp, a, b, c, e, i, j, half;
+};
+
+__device__ __forceinline__ float ls_len_xy(float2 p, float2 q) {
+  const float dx = p.x - q.x, dy = p.y - q.y;
+  return __builtin_sqrtf(dx * dx + dy * dy);
+}
+
+__device__ __forceinline__ LsMoveXY ls_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls,
+                                              int n, const uint16_t* tour, const uint16_t* pos,
+                                              const float2* txy, int a, double min_gain, double e1,
+                                              double e2) {
+  const int lane = lane_id();
+  const bool pred_dir = lane >= 32;
+  const int q = lane & 31;
+  const bool in_list = q < kls;
+  const int c = geo[(int64_t)a * kg + min(q, kls - 1)];
+  const int pa = pos[a];
+  const int pb = pred_dir ? (pa == 0 ? n - 1 : pa - 1) : (pa + 1 == n ? 0 : pa + 1);
+  const int b = tour[pb];
+  const float2 xa = txy[pa], xb = txy[pb];
+  const int pc = pos[c];
+  const int pe = pred_dir ? (pc == 0 ? n - 1 : pc - 1) : (pc + 1 == n ? 0 : pc + 1);
+  const int e = tour[pe];
+  const float2 xc = txy[pc], xe = txy[pe];
+  const float lab = ls_len_xy(xa, xb), lac = ls_len_xy(xa, xc);
+  // d(a,b) - d(a,c) > 0, as computed in FP64: c == b gives exactly 0, and
+  // only list entries whose FP32 difference lies inside the bound are
+  // decided in FP64
+  const double g1f = (double)(lab - lac);
+  bool g1pos = c != b && g1f > e1;
+  double dab = 0.0, dac = 0.0;
+  bool have64 = false;
+  if (in_list && c != b && !(g1f > e1) && !(g1f < -e1)) {
+    dab = G.len(a, b);
+    dac = G.len(a, c);
+    have64 = true;
+    g1pos = dab - dac > 0.0;
+  }
+  // a direction stops at the first list entry that cannot gain
+  const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !g1pos);
+  const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
+  const int lim_s = stop_s ? (int)__builtin_ctzll(stop_s) : 32;
+  const int lim_p = stop_p ? (int)__builtin_ctzll(stop_p) : 32;
+  const bool cand = in_list && q < (pred_dir ? lim_p : lim_s) && e != a && c != b;
+  const double gf = (double)((lab + ls_len_xy(xc, xe)) - (lac + ls_len_xy(xb, xe)));
+  bool imp = gf > min_gain + e2;
+  if (cand && !(gf > min_gain + e2) && !(gf < min_gain - e2)) {
+    if (!have64) {
+      dab = G.len(a, b);
+      dac = G.len(a, c);
+    }
+    imp = (dab + G.len(c, e)) - (dac + G.len(b, e)) > min_gain;
+  }
+  imp = imp && cand;
+  const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
+  LsMoveXY m{0, a, 0, 0, 0, 0, 0, 0};
+  if (mi) {
+    // the path b..c (successor side) or c..b (predecessor side), or its
+    // complement when that is shorter
+    int i = pred_dir ? pc : pb, j = pred_dir ? pb : pc;
+    int len = (j >= i ? j - i : j - i + n) + 1;
+    if (2 * len > n) {
+      const int ni = j + 1 == n ? 0 : j + 1, nj = i == 0 ? n - 1 : i - 1;
+      i = ni;
+      j = nj;
+      len = n - len;
+    }
+    const int l = (int)__builtin_ctzll(mi);
+    m.imp = 1;
+    m.b = rd_lane(b, l);
+    m.c = rd_lane(c, l);
+    m.e = rd_lane(e, l);
+    m.i = rd_lane(i, l);
+    m.j = rd_lane(j, l);
+    m.half = rd_lane(len, l) / 2;
+  }
+  return m;
+}
+
+template <class BP>
+__device__ __forceinline__ void two_opt_block_xy(const InstDesc& D, uint16_t* tour, uint16_t* pos, uint16_t* queue,
+                                                 BP inq, float2* txy, double min_gain, double e1, double e2) {
+  __shared__ int sh_head, sh_count;
+  __shared__ LsMoveXY sh_mv[LS_WAVES];
+  const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
+  const int nw = (int)(blockDim.x / WAVE);  // 1 .. LS_WAVES entries per batch
+  if (n < 5 || kls < 1) return;
+  const GDist G(D);
+  const HAC_AS1 int32_t* geo = as_global(D.geo);
+  for (int s = threadIdx.x; s < n; s += blockDim.x) {
+    const int v = tour[s];
+    pos[v] = (uint16_t)s;
+    queue[s] = (uint16_t)v;
+    inq[v] = 1;
+  }
+  if (threadIdx.x == 0) {
+    sh_head = 0;
+    sh_count = n;
+  }
+  __syncthreads();
+  // the node of the last applied move is examined again, in wave 0 of the
+  // next batch, ahead of the queue entries
+  int pend = -1;
+  for (;;) {
+    const int head = sh_head, count = sh_count;
+    const int re = pend >= 0 ? 1 : 0;
+    const int nq = min(nw - re, count);  // queue entries in this batch
+    const int nb = nq + re;
+    if (nb == 0) break;
+    if (wave < nb) {
+      int node = pend;
+      if (wave >= re) {
+        int slot = head + wave - re;
+        if (slot >= n) slot -= n;
+        node = queue[slot];
+      }
+      const LsMoveXY m = ls_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2);
+      if (lane == 0) sh_mv[wave] = m;
+    }
+    __syncthreads();
+    // the first improving result in batch order (one entry per lane)
+    const uint64_t fm = __builtin_amdgcn_ballot_w64(lane < nb && sh_mv[min(lane, LS_WAVES - 1)].imp);
+    const int f = fm ? (int)__builtin_ctzll(fm) : -1;
+    if (wave == 0) {
+      // queue entries consumed as a sequential scan would: all of them if
+      // no move improves, else those up to and including the improving one
+      const int used = f < 0 ? nq : max(0, f + 1 - re);
+      if (lane < used) {
+        int slot = head + lane;
+        if (slot >= n) slot -= n;
+        inq[queue[slot]] = 0;
+      }
+      int h = head + used;
+      if (h >= n) h -= n;
+      int cnt = count - used;
+      if (f >= 0) {
+        // the end nodes a, b, c, e (four distinct nodes) join the queue
+        // tail in that order if absent, one lane each
+        const bool mine = lane < 4;
+        int x = 0;
+        if (mine) {
+          const LsMoveXY& mv = sh_mv[f];
+          x = lane == 0 ? mv.a : (lane == 1 ? mv.b : (lane == 2 ? mv.c : mv.e));
+        }
+        const bool absent = mine && !inq[x];
+        const uint32_t am = (uint32_t)__builtin_amdgcn_ballot_w64(absent) & 0xfu;
+        if (absent) {
+          int slot = h + cnt + __builtin_popcount(am & ((1u << lane) - 1u));
+          if (slot >= n) slot -= n;
+          queue[slot] = (uint16_t)x;
+          inq[x] = 1;
+        }
+        cnt += __builtin_popcount(am);
+      }
+      if (lane == 0) {
+        sh_head = h;
+        sh_count = cnt;
+      }
+    }
+    if (f < 0) {
+      pend = -1;
+      __syncthreads();
+      continue;
+    }
+    // reverse positions i .. j (cyclic) of the tour and its coordinates
+    const int ri = sh_mv[f].i, rj = sh_mv[f].j, half = sh_mv[f].half;
+    pend = sh_mv[f].a;
+    for (int s2 = threadIdx.x; s2 < half; s2 += blockDim.x) {
+      int pi = ri + s2;
+      if (pi >= n) pi -= n;
+      int pj = rj - s2;
+      if (pj < 0) pj += n;
+      const int ti = tour[pi], tj = tour[pj];
+      const float2 xi = txy[pi], xj = txy[pj];
+      tour[pi] = (uint16_t)tj;
+      tour[pj] = (uint16_t)ti;
+      txy[pi] = xj;
+      txy[pj] = xi;
+      pos[tj] = (uint16_t)pi;
+      pos[ti] = (uint16_t)pj;
+    }
+    __syncthreads();
+  }
+}
+
 // Working arrays of the 2-opt, by mode:
 //   2: tour, pos and queue as uint16, in-queue flags as uint8 and an FP32
-//      copy of the coordinates, all in LDS (15 bytes per node, n < 65536,
-//      coordinate instances);
+//      copy of the coordinates in tour order, all in LDS (15 bytes per
+//      node, n < 65536, coordinate instances);
 //   1: tour, pos and queue as int32 and the flags in LDS (13 bytes per node);
 //   0: global memory (the tour in place, the rest in the work area).
 static __host__ __device__ inline size_t ls_lds_need(int n, int mode) {
@@ -765,21 +917,20 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
                                              int32_t* work) {
   extern __shared__ int32_t ls_lds[];
   const int n = D.n;
-  LsFast F{nullptr, 0.0, 0.0};
   if constexpr (MODE == 2) {
     uint16_t* tour = reinterpret_cast<uint16_t*>(ls_lds);
     uint16_t* pos = tour + n;
     uint16_t* queue = pos + n;
     uint8_t* inq = reinterpret_cast<uint8_t*>(ls_lds) + ((size_t)6 * n + 15) / 16 * 16;
-    float2* xyf = reinterpret_cast<float2*>(reinterpret_cast<uint8_t*>(inq) + ((size_t)n + 15) / 16 * 16);
+    float2* txy = reinterpret_cast<float2*>(reinterpret_cast<uint8_t*>(inq) + ((size_t)n + 15) / 16 * 16);
     __shared__ double sh_m[LS_WAVES];
     double mloc = 0.0;
     const HAC_AS1 double* xy = as_global(D.xy);
     for (int s = threadIdx.x; s < n; s += blockDim.x) {
-      tour[s] = (uint16_t)tour_g[s];
-      const double x = xy[2 * s], y = xy[2 * s + 1];
-      xyf[s] = make_float2((float)x, (float)y);
-      mloc = fmax(mloc, fmax(fabs(x), fabs(y)));
+      const int v = tour_g[s];
+      tour[s] = (uint16_t)v;
+      txy[s] = make_float2((float)xy[2 * v], (float)xy[2 * v + 1]);
+      mloc = fmax(mloc, fmax(fabs(xy[2 * s]), fabs(xy[2 * s + 1])));
     }
     // largest coordinate magnitude (for the FP32 error bounds)
     for (int off = 32; off >= 1; off >>= 1) mloc = fmax(mloc, __shfl_xor(mloc, off));
@@ -787,8 +938,7 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
     __syncthreads();
     double M = 0.0;
     for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) M = fmax(M, sh_m[w]);
-    F = LsFast{xyf, M * 0x1p-18, M * 0x1p-17};
-    two_opt_block(D, tour, pos, queue, inq, min_gain, F);
+    two_opt_block_xy(D, tour, pos, queue, inq, txy, min_gain, M * 0x1p-18, M * 0x1p-17);
     __syncthreads();
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
   } else if constexpr (MODE == 1) {
@@ -798,7 +948,7 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
     uint8_t* inq = reinterpret_cast<uint8_t*>(queue + n);
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour[s] = tour_g[s];
     __syncthreads();
-    two_opt_block(D, tour, pos, queue, inq, min_gain, F);
+    two_opt_block(D, tour, pos, queue, inq, min_gain);
     __syncthreads();
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
   } else {
@@ -806,7 +956,7 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
     HAC_AS1 int32_t* pos = as_global(work);
     HAC_AS1 int32_t* queue = pos + n;
     HAC_AS1 uint8_t* inq = reinterpret_cast<HAC_AS1 uint8_t*>(queue + n);
-    two_opt_block(D, tour, pos, queue, inq, min_gain, F);
+    two_opt_block(D, tour, pos, queue, inq, min_gain);
   }
   __threadfence_block();
   __syncthreads();
