@@ -717,9 +717,17 @@ struct LsMoveXY {
   int imp, a, b, c, e, i, j, half;
 };
 
+// the hardware square root (within 1 ulp, inside the bound's allowance)
+// instead of the correctly rounded library sequence
 __device__ __forceinline__ float ls_len_xy(float2 p, float2 q) {
   const float dx = p.x - q.x, dy = p.y - q.y;
-  return __builtin_sqrtf(dx * dx + dy * dy);
+  return __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
+}
+
+// position p + step (step = +-1) on a cycle of n, as selects rather than branches
+__device__ __forceinline__ int cyc_step(int p, int step, int n) {
+  const int r = p + step;
+  return r < 0 ? r + n : (r >= n ? r - n : r);
 }
 
 __device__ __forceinline__ LsMoveXY ls_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls,
@@ -731,12 +739,13 @@ __device__ __forceinline__ LsMoveXY ls_eval_xy(const GDist& G, const HAC_AS1 int
   const int q = lane & 31;
   const bool in_list = q < kls;
   const int c = geo[(int64_t)a * kg + min(q, kls - 1)];
+  const int step = pred_dir ? -1 : 1;
   const int pa = pos[a];
-  const int pb = pred_dir ? (pa == 0 ? n - 1 : pa - 1) : (pa + 1 == n ? 0 : pa + 1);
+  const int pb = cyc_step(pa, step, n);
   const int b = tour[pb];
   const float2 xa = txy[pa], xb = txy[pb];
   const int pc = pos[c];
-  const int pe = pred_dir ? (pc == 0 ? n - 1 : pc - 1) : (pc + 1 == n ? 0 : pc + 1);
+  const int pe = cyc_step(pc, step, n);
   const int e = tour[pe];
   const float2 xc = txy[pc], xe = txy[pe];
   const float lab = ls_len_xy(xa, xb), lac = ls_len_xy(xa, xc);
