@@ -712,7 +712,8 @@ __device__ __forceinline__ void two_opt_block(const InstDesc& D, IP tour, IP pos
 // tour, txy at pc and pc +- 1) instead of five.  The evaluating wave also
 // works out the path to reverse (the shorter side), so a round needs one
 // barrier after the evaluations and one after the reversal; the queue
-// bookkeeping stays in wave 0, whose LDS operations are ordered.
+// bookkeeping stays in one wave (its LDS operations are ordered), which
+// runs it while the other waves reverse the path.
 struct LsMoveXY {
   int imp, a, b, c, e, i, j, half;
 };
@@ -847,7 +848,10 @@ __device__ __forceinline__ void two_opt_block_xy(const InstDesc& D, uint16_t* to
     // the first improving result in batch order (one entry per lane)
     const uint64_t fm = __builtin_amdgcn_ballot_w64(lane < nb && sh_mv[min(lane, LS_WAVES - 1)].imp);
     const int f = fm ? (int)__builtin_ctzll(fm) : -1;
-    if (wave == 0) {
+    // the queue bookkeeping runs in the last wave, beside the reversal in
+    // the others (one wave does both when the block has one)
+    const int bw = nw - 1;
+    if (wave == bw) {
       // queue entries consumed as a sequential scan would: all of them if
       // no move improves, else those up to and including the improving one
       const int used = f < 0 ? nq : max(0, f + 1 - re);
@@ -891,7 +895,8 @@ __device__ __forceinline__ void two_opt_block_xy(const InstDesc& D, uint16_t* to
     // reverse positions i .. j (cyclic) of the tour and its coordinates
     const int ri = sh_mv[f].i, rj = sh_mv[f].j, half = sh_mv[f].half;
     pend = sh_mv[f].a;
-    for (int s2 = threadIdx.x; s2 < half; s2 += blockDim.x) {
+    const int rthreads = bw > 0 ? bw * WAVE : WAVE;
+    for (int s2 = (bw > 0 && wave == bw) ? half : (int)threadIdx.x; s2 < half; s2 += rthreads) {
       int pi = ri + s2;
       if (pi >= n) pi -= n;
       int pj = rj - s2;
