@@ -48,8 +48,11 @@ def test_noalloc_equals_decode_twice_then_smaller(ctx):
 def test_noalloc_two_opt_and_atsp(ctx):
     ls = wl.random_instance(300, seed=8, ants=12, iterations=25, local_search=1, k_ls=10)
     atsp = wl.serve_request("atsp1000", 3, iterations=10)
-    print("case no-alloc 2-opt n=300, ATSP n=1000", flush=True)
-    for inst in (ls, atsp):
+    # the directed 2-opt: incoming lists and its work area in the array too
+    atsp_ls = wl.random_instance(200, seed=9, kind="matrix", symmetric=False, ants=8, iterations=12,
+                                 local_search=2, k_ls=10)
+    print("case no-alloc 2-opt n=300, ATSP n=1000, ATSP n=200 with directed 2-opt", flush=True)
+    for inst in (ls, atsp, atsp_ls):
         _same(ctx.decode_noalloc(inst), ctx.decode(inst), inst.name)
 
 
