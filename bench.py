@@ -229,6 +229,12 @@ def kernel_line(name, bytes_per_launch, ms, launches):
             "algorithmic_bytes_per_launch": bytes_per_launch}
 
 
+def launch_shape(st) -> dict:
+    """The construction launch shape the decode used (the tuner's choice)."""
+    return {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
+            "ants_per_wave": st["ants_per_wave"], "byte_marks": st["byte_marks"], "geo_mode": st["geo_mode"]}
+
+
 def timing_pass(ctx, decode):
     """One decode with per-kernel HIP-event timing on: the per-launch
     durations of construction, 2-opt and update."""
@@ -303,8 +309,7 @@ def run_batched(args, hac, insts, cpu, name, desc, plain_count, traffic_key=None
                     {"workload": desc, "instances": count, "iterations": insts[0].iterations,
                      "ants": insts[0].ants, "k": insts[0].k, "inputs": "resident in HBM (hac_decode_batch_dev)",
                      "path": "iterations replayed from a captured hipGraph, kernel timing off",
-                     "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
-                                      "ants_per_wave": st["ants_per_wave"], "byte_marks": st["byte_marks"]}})
+                     "launch_shape": launch_shape(st)})
     out.update({
         "decodes_per_s": dps,
         "plain": {"decodes_per_s": plain_dps, "ant_steps_per_s": psteps / sum(lat), "sample": len(lat)},
@@ -343,7 +348,7 @@ def sub_tsp10k(hac, insts, plain_count=1):
     assert equal, "plain and batched tours differ (tsp10k)"
     dps, plain_dps = len(insts) / wall, len(lat) / sum(lat)
     ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
-    lines = kernel_lines(insts, st)
+    lines = kernel_lines(insts, st, "tsp10k")
     return {"workload": "tsp10k: 8 TSP instances, n=10000, top-20 heatmaps, k=20, 100 ants, 200 iterations, "
                         "neighbour-list 2-opt (20) on each iteration best",
             "steps": 1, "ms_per_step": 1000 * wall, "ant_steps_per_s": ant_steps / wall,
@@ -351,8 +356,7 @@ def sub_tsp10k(hac, insts, plain_count=1):
             "batched_vs_plain": dps / plain_dps, "equal_gap": equal,
             "latency_ms": {"batched": 1000 * wall, "plain_p50": 1000 * percentile(lat, 0.5)},
             "roofline": lines["construct"], "kernels": {k: v for k, v in lines.items() if k != "construct"},
-            "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
-                             "ants_per_wave": st["ants_per_wave"]}}
+            "launch_shape": launch_shape(st)}
 
 
 def run_plain(args, hac, inst, cpu, name, desc):
@@ -364,8 +368,7 @@ def run_plain(args, hac, inst, cpu, name, desc):
                     1000.0 * wall / args.steps,
                     {"workload": desc, "instances": 1, "iterations": inst.iterations, "ants": inst.ants,
                      "k": inst.k, "inputs": "resident in HBM",
-                     "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
-                                      "ants_per_wave": st["ants_per_wave"], "byte_marks": st["byte_marks"]}})
+                     "launch_shape": launch_shape(st)})
     out.update({"decodes_per_s": args.steps / wall,
                 "latency_ms": {"p50": 1000 * percentile(times, 0.5), "p99": 1000 * percentile(times, 0.99)},
                 "fallback_fraction": st["fallback_steps"] / max(1, st["ant_steps"]),
@@ -513,8 +516,7 @@ def run_paper(args, hac, wl):
                     ant_steps * args.steps / wall, 1000.0 * wall / args.steps,
                     {"workload": desc, "instances": count, "iterations": insts[0].iterations, "ants": 32,
                      "k": 20, "inputs": "resident in HBM (hac_decode_batch_dev)",
-                     "launch_shape": {"ants_per_block": st["ants_per_block"], "lds_staged": st["lds_staged"],
-                                      "ants_per_wave": st["ants_per_wave"], "byte_marks": st["byte_marks"]}})
+                     "launch_shape": launch_shape(st)})
     ctx_paper = PAPER_TIMES_S.get((n, ls))
     out.update({
         "decodes_per_s": count * args.steps / wall,
@@ -672,7 +674,7 @@ def main():
     elif args.workload == "tsp10k":
         out = run_batched(args, hac, insts, cpu, "8 TSP instances, n 10000, 2-opt",
                           "tsp10k: 8 TSP instances, n=10000, top-20 heatmaps, k=20, 100 ants, 200 iterations, "
-                          "neighbour-list 2-opt (20) on each iteration best", min(args.plain_sample, 1))
+                          "neighbour-list 2-opt (20) on each iteration best", min(args.plain_sample, 1), "tsp10k")
     elif args.workload == "serve":
         out = run_serve(args, hac, wl, cpu)
     else:
