@@ -745,10 +745,12 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     return ms_min;
   };
   // Successive halving for large instances: every candidate is timed once
-  // on the first eighth of the tours, and the four fastest are then timed on
-  // whole tours (a whole launch of a 10^4-node batch takes milliseconds, and
-  // a serving lane tunes whenever its batch changes class).  Smaller
-  // instances are timed whole, twice.
+  // on the first eighth of the tours, and the four fastest shapes are then
+  // timed on whole tours, each with every geometric-list mode it was tried
+  // with (a prefix has few exhausted rows, so it cannot rank the modes; a
+  // whole launch of a 10^4-node batch takes milliseconds, and a serving
+  // lane tunes whenever its batch changes class).  Smaller instances are
+  // timed whole, twice.
   int32_t max_n = 0;
   for (auto& h : hs) max_n = std::max(max_n, h.lay.n);
   const int32_t prefix = std::max<int32_t>(512, max_n / 8);
@@ -761,11 +763,27 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
   }
   if (*ok && halve) {
     std::sort(first.begin(), first.end());
-    first.resize(4);
+    auto same_shape = [&](size_t x, size_t y) {
+      const LaunchShape &a = cands[x], &b = cands[y];
+      return a.ants_per_block == b.ants_per_block && a.staged == b.staged && a.rows_per_wave == b.rows_per_wave &&
+             a.bytes == b.bytes;
+    };
+    std::vector<size_t> lead;  // the four fastest shapes
     for (auto& f : first) {
-      f.first = time_shape(cands[f.second], INT32_MAX, 1);
-      if (f.first < 0.0f) *ok = false;
+      bool seen = false;
+      for (size_t y : lead) seen |= same_shape(f.second, y);
+      if (!seen && lead.size() < 4) lead.push_back(f.second);
     }
+    std::vector<std::pair<float, size_t>> second;
+    for (size_t x = 0; x < cands.size() && *ok; ++x) {
+      bool in = false;
+      for (size_t y : lead) in |= same_shape(x, y);
+      if (!in) continue;
+      const float ms = time_shape(cands[x], INT32_MAX, 1);
+      if (ms < 0.0f) *ok = false;
+      second.emplace_back(ms, x);
+    }
+    first.swap(second);
   }
   for (auto& f : first) {
     if (*ok && f.first < best_ms) {
