@@ -216,9 +216,12 @@ def update_bytes(insts) -> int:
 def two_opt_bytes(insts) -> int:
     """Algorithmic bytes of one 2-opt launch over the tours it searches: read
     the tour (4 B), the coordinates (16 B) and the neighbour list (4 k_ls B)
-    of every node and write the tour (4 B)."""
+    of every node and write the tour (4 B).  The directed 2-opt (ATSP) reads
+    both directions of each tour edge (16 B) and an outgoing and an incoming
+    list (8 k_ls B) instead."""
     tours = lambda x: x.ants if x.local_search == 2 else (1 if x.local_search else 0)
-    return sum(tours(x) * x.n * (24 + 4 * min(x.k_ls, x.n - 1)) for x in insts)
+    lists = lambda x: (4 if x.symmetric else 8) * min(x.k_ls, x.n - 1)
+    return sum(tours(x) * x.n * (24 + lists(x)) for x in insts)
 
 
 def kernel_line(name, bytes_per_launch, ms, launches):
@@ -593,10 +596,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve", "paper", "ablation",
+    ap.add_argument("--workload", default="batch64", choices=["batch64", "tsp100", "tsp500", "tsp10k", "serve", "paper", "ablation", "atsp",
                              "diagnostics"])
     ap.add_argument("--paper-n", type=int, default=500, help="paper/ablation workload: instance size")
-    ap.add_argument("--ls", type=int, default=0, choices=[0, 2], help="paper workload: 2 = 2-opt on every ant")
+    ap.add_argument("--ls", type=int, default=0, choices=[0, 1, 2],
+                    help="paper workload: 2 = 2-opt on every ant; atsp workload: 1 (default there) or 2")
     ap.add_argument("--instances", type=int, default=None, help="paper workload: instances in the batch")
     ap.add_argument("--iterations", type=int, default=None, help="override the workload's iteration count")
     ap.add_argument("--plain-sample", type=int, default=16)
@@ -647,6 +651,10 @@ def main():
         insts = [wl.tsp500(iterations=it or 1000)]
     elif args.workload == "tsp10k":
         insts = generate([("tsp10k", x, it or 200) for x in range(8)])
+    elif args.workload == "atsp":
+        import dataclasses
+        insts = [dataclasses.replace(x, local_search=args.ls or 1, k_ls=20)
+                 for x in generate([("atsp1000", r, it or 100) for r in range(args.instances or 16)])]
     else:
         insts = None
     if extras:
@@ -675,6 +683,13 @@ def main():
         out = run_batched(args, hac, insts, cpu, "8 TSP instances, n 10000, 2-opt",
                           "tsp10k: 8 TSP instances, n=10000, top-20 heatmaps, k=20, 100 ants, 200 iterations, "
                           "neighbour-list 2-opt (20) on each iteration best", min(args.plain_sample, 1), "tsp10k")
+    elif args.workload == "atsp":
+        x = insts[0]
+        out = run_batched(args, hac, insts, cpu, f"{len(insts)} ATSP instances, n 1000, directed 2-opt",
+                          f"atsp: {len(insts)} ATSP instances (the served ATSP1000 kind), n=1000, directed top-20 "
+                          f"heatmaps, k=20, 50 ants, {x.iterations} iterations, directed 2-opt (20) on "
+                          + ("every ant" if x.local_search == 2 else "each iteration best"),
+                          min(args.plain_sample, 2))
     elif args.workload == "serve":
         out = run_serve(args, hac, wl, cpu)
     else:

@@ -548,23 +548,37 @@ void orc_two_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min
 /*     (b->a), (e->c) become (c->a), (e->b), the path c..b reversed.         */
 /* gain = (removed edges + F) - (added edges + B), F and B the reversed      */
 /* path's cost in its old and new direction, from prefix sums of the         */
-/* directed edge lengths in tour order.  Queue, side order, list stop rule,  */
+/* directed edge lengths in tour order, summed in blocks of 64 positions:    */
+/* in order within a block, and the block totals in order (reading: the      */
+/* paper does not say how path costs are kept; two levels let a search       */
+/* re-sum only the blocks a move changed).  Queue, side order, list stop rule,*/
 /* threshold and re-queueing as in the symmetric 2-opt; the reversed part is */
 /* always the path itself (its complement would give the opposite tour).    */
 /* A run applies at most 64 n moves: every move shortens the tour by more    */
 /* than the threshold, so this bound only guards against a broken gain.     */
 /* ------------------------------------------------------------------------ */
 
-/* pf[q] = sum of d(T[t], T[t+1]) for t < q, pb[q] the same edges reversed,
- * q = 0..n, the closing edge last (eq. (1)'s order) */
+/* pf[q] = the sum of e(t) = d(T[t], T[t+1]) over t < q, pb[q] the same
+ * edges reversed, q = 0..n, the closing edge last (eq. (1)'s order).  With
+ * block(q) = floor(q / 64): pf[q] = S[block(q)] + (the edges of q's block
+ * before q, added in order from 0.0), S[0] = 0 and S[b + 1] = S[b] + (block
+ * b's 64 edges added in order from 0.0). */
 static void directed_prefix(const orc_problem* p, const int32_t* tour, double* pf, double* pb) {
   int32_t n = p->n;
-  pf[0] = 0.0;
-  pb[0] = 0.0;
-  for (int32_t q = 0; q < n; q++) {
-    int32_t x = tour[q], y = tour[(q + 1) % n];
-    pf[q + 1] = pf[q] + dist(p, x, y);
-    pb[q + 1] = pb[q] + dist(p, y, x);
+  double sf = 0.0, sb = 0.0; /* S of the current block */
+  for (int32_t b0 = 0; b0 <= n; b0 += 64) {
+    double f = 0.0, r = 0.0; /* the block's edges so far */
+    for (int32_t q = b0; q < b0 + 64 && q <= n; q++) {
+      pf[q] = sf + f;
+      pb[q] = sb + r;
+      if (q < n) {
+        int32_t x = tour[q], y = tour[(q + 1) % n];
+        f += dist(p, x, y);
+        r += dist(p, y, x);
+      }
+    }
+    sf += f;
+    sb += r;
   }
 }
 

@@ -451,13 +451,14 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   HAC_HIP(launch_grid(d_descs, count, s));
   HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
   bool any_ls = false;
-  int32_t all_coords = 1, max_n_dir = 0;
+  int32_t all_coords = 1, max_n_dir = 0, max_n_sym = 0;  // largest directed / symmetric instance with 2-opt
   for (auto& h : hs) {
     any_ls |= h.p.local_search != 0;
     if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n);
-    else if (h.p.local_search && !h.lay.coords) all_coords = 0;
+    else if (h.p.local_search) max_n_sym = std::max(max_n_sym, h.lay.n);
+    if (h.p.local_search && !h.lay.directed && !h.lay.coords) all_coords = 0;
   }
-  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n, all_coords, max_n_dir, s));
+  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n_sym, all_coords, max_n_dir, s));
   std::vector<State> sts(count);
   if (stage) {
     // after the weights' scatter on the same stream: the staging arena is reused
@@ -1165,14 +1166,15 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   LaunchShape used{0, 0, 0, 0, 0};
   if (m > 0) {
     bool any_ls = false;
+    // max_n: the largest symmetric instance with 2-opt (0: none); max_n_dir: ATSP
     int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0;
     for (auto& h : hs) {
       any_ls |= h.p.local_search != 0;
       if (h.p.local_search == 2) ls_tours = std::max(ls_tours, h.p.ants);
       max_iter = std::max(max_iter, h.p.iterations);
-      max_n = std::max(max_n, h.lay.n);
       if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n);
-      else if (h.p.local_search && !h.lay.coords) all_coords = 0;
+      else if (h.p.local_search) max_n = std::max(max_n, h.lay.n);
+      if (h.p.local_search && !h.lay.directed && !h.lay.coords) all_coords = 0;
     }
     LaunchShape shape{4, 0, 16, 4, 0};
     if (noalloc) {

@@ -105,10 +105,12 @@ __host__ __device__ inline bool tour_checksums_ok(int32_t n, uint32_t sum, uint3
 }
 
 // Bytes of the directed 2-opt's arrays for n nodes (edge lengths and prefix
+// sums in both directions, block totals and block offsets of the prefix
 // sums in both directions, tour, positions, queue, in-queue flags), and the
 // 256-byte-aligned stride of one tour's part of the work area.
 __host__ __device__ inline size_t dir_work_bytes(int32_t n) {
-  return (size_t)8 * (4 * (size_t)n + 2) + (size_t)12 * n + (((size_t)n + 7) & ~(size_t)7);
+  return (size_t)8 * (4 * (size_t)n + 2) + (size_t)32 * ((size_t)n / 64 + 2) + (size_t)12 * n +
+         (((size_t)n + 7) & ~(size_t)7);
 }
 __host__ __device__ inline size_t dir_work_stride(int32_t n) { return (dir_work_bytes(n) + 255) & ~(size_t)255; }
 
@@ -145,11 +147,12 @@ hipError_t launch_copy_items(const CopyItem* d_items, int32_t count, uint64_t ma
 // neighbour, in the successor array)
 hipError_t launch_candidates(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
 hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n, hipStream_t s);
-// 2-opt launches: all_coords = 1 when every instance of the batch has
-// coordinates (the FP32-filtered LDS mode needs them)
-// max_n_dir: largest ATSP instance with local search (0: none); such
+// 2-opt launches: max_n is the largest symmetric instance with local search
+// (0: none, and the symmetric kernel is not launched); all_coords = 1 when
+// every such instance has coordinates (the FP32-filtered LDS mode needs
+// them); max_n_dir: largest ATSP instance with local search (0: none); such
 // instances take the directed 2-opt (and their incoming lists are built
-// first), the others the symmetric one
+// first)
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
                              int32_t max_n_dir, hipStream_t s);
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);

@@ -1822,6 +1822,10 @@ struct DirWork {
   double* eb;   // [n] d(T[q+1], T[q])
   double* pf;   // [n + 1] prefix sums of ef
   double* pb;   // [n + 1] prefix sums of eb
+  double* tf;   // [n / 64 + 1] totals of ef over blocks of 64 positions
+  double* tb;   // [n / 64 + 1] the same for eb
+  double* sf;   // [n / 64 + 1] block offsets: sf[0] = 0, sf[b + 1] = sf[b] + tf[b]
+  double* sb;   // [n / 64 + 1] the same for eb
   int32_t* tour;
   int32_t* pos;
   int32_t* queue;
@@ -1834,7 +1838,12 @@ __device__ __forceinline__ DirWork dir_work_at(char* base, int n) {
   w.eb = w.ef + n;
   w.pf = w.eb + n;
   w.pb = w.pf + (n + 1);
-  w.tour = reinterpret_cast<int32_t*>(w.pb + (n + 1));
+  const int nblk = n / 64 + 1;
+  w.tf = w.pb + (n + 1);
+  w.tb = w.tf + nblk;
+  w.sf = w.tb + nblk;
+  w.sb = w.sf + nblk;
+  w.tour = reinterpret_cast<int32_t*>(w.sb + (nblk + 1));
   w.pos = w.tour + n;
   w.queue = w.pos + n;
   w.inq = reinterpret_cast<uint8_t*>(w.queue + n);
@@ -1846,23 +1855,70 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// edge lengths from position q0 on, then the prefix sums from q0 (one lane,
-// in tour order; the sums before q0 do not change)
-__device__ void dir_prefix(const HAC_AS1 double* d, int n, const DirWork& w, int q0) {
+// Prefix sums in blocks of 64 positions (the oracle's definition):
+// pf[q] = sf[q / 64] + (the edges of q's block before q, added in order from
+// 0.0), sf[0] = 0, sf[b + 1] = sf[b] + tf[b], tf[b] the block's 64 edges
+// added in order from 0.0; pb alike.  After the edges lo .. hi changed, the
+// wave reloads them, re-adds the totals of their blocks (a lane per block),
+// then the block offsets from there (one lane), then every prefix from the
+// first changed block on (a lane per block): a dependent chain of about
+// 128 + n / 64 additions instead of n.  Within a block the loads run eight
+// ahead of the additions.
+__device__ __forceinline__ void dir_block_sums(const double* e, int q0, int q1, double& acc) {
+  int q = q0;
+  for (; q + 8 <= q1; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = e[q + t];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc += v[t];
+  }
+  for (; q < q1; ++q) acc += e[q];
+}
+
+__device__ void dir_prefix(const HAC_AS1 double* d, int n, const DirWork& w, int lo, int hi) {
   const int lane = lane_id();
-  for (int q = q0 + lane; q < n; q += WAVE) {
+  for (int q = lo + lane; q <= hi; q += WAVE) {
     const int x = w.tour[q], y = w.tour[q + 1 == n ? 0 : q + 1];
     w.ef[q] = d[(int64_t)x * n + y];
     w.eb[q] = d[(int64_t)y * n + x];
   }
   wave_sync();
+  const int blo = lo / 64, bhi = hi / 64, blast = n / 64;
+  for (int b = blo + lane; b <= bhi; b += WAVE) {
+    const int q0 = 64 * b, q1 = min(q0 + 64, n);
+    double f = 0.0, r = 0.0;
+    dir_block_sums(w.ef, q0, q1, f);
+    dir_block_sums(w.eb, q0, q1, r);
+    w.tf[b] = f;
+    w.tb[b] = r;
+  }
+  wave_sync();
   if (lane == 0) {
-    double f = w.pf[q0], b = w.pb[q0];
-    for (int q = q0; q < n; ++q) {
-      f = f + w.ef[q];
-      b = b + w.eb[q];
-      w.pf[q + 1] = f;
-      w.pb[q + 1] = b;
+    if (blo == 0) {
+      w.sf[0] = 0.0;
+      w.sb[0] = 0.0;
+    }
+    double f = w.sf[blo], r = w.sb[blo];
+    for (int b = blo; b < blast; ++b) {
+      f = f + w.tf[b];
+      r = r + w.tb[b];
+      w.sf[b + 1] = f;
+      w.sb[b + 1] = r;
+    }
+  }
+  wave_sync();
+  for (int b = blo + lane; b <= blast; b += WAVE) {
+    const int q0 = 64 * b, qe = min(q0 + 64, n + 1);
+    const double s1 = w.sf[b], s2 = w.sb[b];
+    double f = 0.0, r = 0.0;
+    for (int q = q0; q < qe; ++q) {
+      w.pf[q] = s1 + f;
+      w.pb[q] = s2 + r;
+      if (q < n) {
+        f += w.ef[q];
+        r += w.eb[q];
+      }
     }
   }
   wave_sync();
@@ -1888,12 +1944,7 @@ __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain,
     w.pos[w.tour[s]] = s;
     w.inq[w.tour[s]] = 1;
   }
-  if (lane == 0) {
-    w.pf[0] = 0.0;
-    w.pb[0] = 0.0;
-  }
-  wave_sync();
-  dir_prefix(d, n, w, 0);
+  dir_prefix(d, n, w, 0, n - 1);
   const int64_t max_moves = 64 * (int64_t)n;
   int64_t moves = 0;
   int head = 0, count = n, pend = -1;
@@ -1976,7 +2027,12 @@ __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain,
     }
     count = rd_lane(count, 0);
     wave_sync();
-    dir_prefix(d, n, w, (mi_ <= mj && mi_ >= 1) ? mi_ - 1 : 0);
+    // the edges mi_ - 1 .. mj changed (all of them when the path wraps or
+    // starts at position 0, where the closing edge changes too)
+    if (mi_ >= 1 && mi_ <= mj)
+      dir_prefix(d, n, w, mi_ - 1, mj);
+    else
+      dir_prefix(d, n, w, 0, n - 1);
     ++moves;
     pend = a;
   }
@@ -2384,6 +2440,7 @@ hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max
     if (e == hipSuccess) e = launch_directed(d_insts, count, max_n_dir, 1, true, s);
     if (e != hipSuccess) return e;
   }
+  if (max_n <= 0) return hipSuccess;  // no symmetric instance searches
   const int mode = ls_mode(max_n, all_coords);
   const dim3 grid(count), block(LS_WAVES * WAVE);
   if (mode == 2)
@@ -2580,6 +2637,7 @@ hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t m
     const hipError_t e = launch_directed(d_insts, count, max_n_dir, tours_per_inst, false, s);
     if (e != hipSuccess) return e;
   }
+  if (max_n <= 0) return hipSuccess;  // no symmetric instance searches
   const int mode = ls_mode(max_n, all_coords);
   const int tpi = std::max(tours_per_inst, 1);
   const int waves = tpi > 1 ? ls_block_waves(max_n, mode, (int64_t)count * tpi) : LS_WAVES;

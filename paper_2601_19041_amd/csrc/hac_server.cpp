@@ -390,15 +390,16 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
       }
       dirty = false;
     }
+    // max_n: the largest symmetric instance with 2-opt (0: none); max_n_dir: ATSP
     int32_t remaining = 1 << 30, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0;
     bool any_ls = false;
     for (auto& sl : LN.active) {
       remaining = std::min(remaining, sl.h.p.iterations - sl.done_iters);
-      max_n = std::max(max_n, sl.h.lay.n);
       any_ls |= sl.h.p.local_search != 0;
       if (sl.h.p.local_search == 2) ls_tours = std::max(ls_tours, sl.h.p.ants);
       if (sl.h.lay.directed) max_n_dir = std::max(max_n_dir, sl.h.lay.n);
-      else if (sl.h.p.local_search && !sl.h.lay.coords) all_coords = 0;
+      else if (sl.h.p.local_search) max_n = std::max(max_n, sl.h.lay.n);
+      if (sl.h.p.local_search && !sl.h.lay.directed && !sl.h.lay.coords) all_coords = 0;
     }
     bool queued = false;
     {
