@@ -1961,11 +1961,20 @@ __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain,
       if (lane == 0) w.inq[a] = 0;
       wave_sync();
     }
+    // the tour edges a-b and c-e are entries of ef (read from LDS); only
+    // d(a,c) and d(b,e) come from the matrix, both loaded once e is known
+    const int step = pred_side ? -1 : 1;
     const int pa = w.pos[a];
-    const int b = pred_side ? w.tour[pa == 0 ? n - 1 : pa - 1] : w.tour[pa + 1 == n ? 0 : pa + 1];
+    const int pb = cyc_step(pa, step, n);
+    const int b = w.tour[pb];
+    const double dab = w.ef[pred_side ? pb : pa];  // d(a,b), or d(b,a) on the predecessor side
     const int c = pred_side ? in_l[(int64_t)a * kls + (in_list ? q : 0)] : out_l[(int64_t)a * kg + (in_list ? q : 0)];
-    const double dab = pred_side ? d[(int64_t)b * n + a] : d[(int64_t)a * n + b];
+    const int pc = w.pos[c];
+    const int pe = cyc_step(pc, step, n);
+    const int e = w.tour[pe];
+    const double dce = w.ef[pred_side ? pe : pc];  // d(c,e), or d(e,c)
     const double dac = pred_side ? d[(int64_t)c * n + a] : d[(int64_t)a * n + c];
+    const double dbe = pred_side ? d[(int64_t)e * n + b] : d[(int64_t)b * n + e];
     const bool g1pos = dab - dac > 0.0;
     // a side stops at its first list entry that cannot gain
     const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !g1pos);
@@ -1973,20 +1982,14 @@ __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain,
     const int lim = pred_side ? (stop_p ? (int)__builtin_ctzll(stop_p) : 32)
                               : (stop_s ? (int)__builtin_ctzll(stop_s) : 32);
     const bool ok = in_list && q < lim;
-    const int pc = w.pos[c];
-    const int e = pred_side ? w.tour[pc == 0 ? n - 1 : pc - 1] : w.tour[pc + 1 == n ? 0 : pc + 1];
     const bool degenerate = e == a || c == b || c == a;
     int i = 0, j = 0;
     bool imp = false;
     if (ok && !degenerate) {
-      i = pred_side ? pc : w.pos[b];
-      j = pred_side ? w.pos[b] : pc;
+      i = pred_side ? pc : pb;
+      j = pred_side ? pb : pc;
       const double F = dir_path_cost(w.pf, n, i, j), B = dir_path_cost(w.pb, n, i, j);
-      double gain;
-      if (pred_side)
-        gain = ((dab + d[(int64_t)e * n + c]) + F) - ((dac + d[(int64_t)e * n + b]) + B);
-      else
-        gain = ((dab + d[(int64_t)c * n + e]) + F) - ((dac + d[(int64_t)b * n + e]) + B);
+      const double gain = ((dab + dce) + F) - ((dac + dbe) + B);
       imp = gain > min_gain;
     }
     const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
