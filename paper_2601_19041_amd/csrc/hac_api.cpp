@@ -615,6 +615,12 @@ size_t shape_lds(const std::vector<HostInst>& hs, LaunchShape sh) {
   return b;
 }
 
+// construction blocks have at most kMaxConstructWaves waves (the kernel's
+// launch bounds), so that it may hold more than 128 registers per lane
+static bool waves_ok(const LaunchShape& sh) {
+  return sh.rows_per_wave >= 1 && (sh.ants_per_block + sh.rows_per_wave - 1) / sh.rows_per_wave <= kMaxConstructWaves;
+}
+
 static std::string shape_key(const std::vector<HostInst>& hs) {
   int32_t max_n = 0, k = 0;
   int64_t ants = 0;
@@ -646,7 +652,7 @@ LaunchShape default_shape(const std::vector<HostInst>& hs) {
       LaunchShape sh = with_marks(hs, {it->second.ants_per_block, it->second.staged, kmax,
                                        it->second.rows_per_wave, 0});
       sh.geo = geo_modes(hs, sh.staged)[0];
-      if (shape_fits(hs, sh)) return sh;
+      if (waves_ok(sh) && shape_fits(hs, sh)) return sh;
     }
   }
   for (int st : {1, 2, 3}) {
@@ -677,7 +683,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
         if (bits[0] == '1') sh.bytes = 0;  // pins bit marks (shows both give the same tours)
       }
       sh.geo = geo_modes(hs, sh.staged)[0];
-      if (sh.ants_per_block <= 16 * sh.rows_per_wave && shape_fits(hs, sh)) return sh;
+      if (waves_ok(sh) && shape_fits(hs, sh)) return sh;
     }
   }
   const std::string key = shape_key(hs);
@@ -691,7 +697,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
       sh.geo = it->second.geo;
       const std::vector<int32_t> gm = geo_modes(hs, sh.staged);
       if (std::find(gm.begin(), gm.end(), sh.geo) == gm.end()) sh.geo = gm[0];
-      if (shape_fits(hs, sh)) return sh;
+      if (waves_ok(sh) && shape_fits(hs, sh)) return sh;
     }
   }
   // Staging forms tried: the table in global memory, and 8-byte entries in
@@ -700,11 +706,11 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
   // win wherever they fit).
   bool fits8 = false;
   for (int rpw : {4, 2, 1})
-    for (int waves : {1, 2, 4, 8, 16}) fits8 |= shape_fits(hs, with_marks(hs, {rpw * waves, 1, kmax, rpw, 0}));
+    for (int waves : {1, 2, 4}) fits8 |= shape_fits(hs, with_marks(hs, {rpw * waves, 1, kmax, rpw, 0}));
   std::vector<int> forms = fits8 ? std::vector<int>{0, 1} : std::vector<int>{0, 2, 3};
   std::vector<LaunchShape> cands;
   for (int rpw : {4, 2, 1})
-    for (int waves : {1, 2, 4, 8, 16})
+    for (int waves : {1, 2, 4})
       for (int st : forms) {
         LaunchShape sh = with_marks(hs, {rpw * waves, st, kmax, rpw, 0});
         if (!shape_fits(hs, sh)) continue;

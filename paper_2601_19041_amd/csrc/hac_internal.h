@@ -158,6 +158,9 @@ hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 // builds the coordinate grid of every instance that has one
 hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s);
+// Waves per construction block, at most (its launch bounds: 256 threads).
+constexpr int kMaxConstructWaves = 4;
+
 // geo_mode: how an exhausted row consults its geometric list before a
 // scan: 0 not at all, 1 int32 lists loaded at the top of each step, 2
 // uint16 lists loaded one step ahead (every instance has geo16).

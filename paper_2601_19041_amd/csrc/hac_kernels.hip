@@ -1553,7 +1553,7 @@ __device__ __forceinline__ void sum_row_in_order(double& len, double d) {
 }
 
 template <int STAGED, int S, bool BYTES>
-__global__ void __launch_bounds__(1024) construct_kernel(const InstDesc* __restrict__ insts,
+__global__ void __launch_bounds__(kMaxConstructWaves * WAVE) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
                                                          int ants_per_block, int rows_per_wave,
                                                          int lds_bytes, int geo_mode, int step_cap) {
@@ -2591,6 +2591,7 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
   if (geo_mode < 0 || geo_mode > 2 || step_cap < 1) return hipErrorInvalidValue;
   if (rows_per_wave < 1 || rows_per_wave > 4) return hipErrorInvalidValue;
   const int waves = (ants_per_block + rows_per_wave - 1) / rows_per_wave;
+  if (waves < 1 || waves > kMaxConstructWaves) return hipErrorInvalidValue;
   const dim3 grid(blocks), block(waves * WAVE);
   const int S = max_k <= 16 ? 1 : (max_k <= 32 ? 2 : 4);
 #define HAC_LAUNCH(ST, SL, BY)                                                                 \

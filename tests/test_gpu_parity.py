@@ -141,8 +141,8 @@ def test_batch_equals_alone(ctx):
         assert np.array_equal(alone[0], got[x][0]) and alone[1] == got[x][1]
 
 
-@pytest.mark.parametrize("shape", ["1,0", "4,0", "16,0", "1,1", "8,1", "4,0,1", "3,1,2", "8,1,1", "8,2", "3,2,2",
-                                   "5,2,1", "8,3", "3,3,2"])
+@pytest.mark.parametrize("shape", ["1,0", "4,0", "16,0", "1,1", "8,1", "4,0,1", "3,1,2", "4,1,1", "8,2", "3,2,2",
+                                   "3,2,1", "8,3", "3,3,2"])
 def test_launch_shape_independence(ctx, shape, monkeypatch):
     """Ants per block, LDS staging and ants per wave change nothing."""
     inst = wl.tsp100(instance=4, seed=4, iterations=25)
@@ -163,8 +163,8 @@ def test_bit_marks(ctx, shape, monkeypatch):
     assert ctx.stats()["byte_marks"] == 0
 
 
-@pytest.mark.parametrize("k,shape", [(24, "8,0"), (24, "5,1,1"), (40, "8,1"), (40, "2,0,2"), (64, "4,0"),
-                                     (24, "8,2"), (40, "3,2,1"), (64, "4,2,2"), (24, "5,3,1")])
+@pytest.mark.parametrize("k,shape", [(24, "8,0"), (24, "4,1,1"), (40, "8,1"), (40, "2,0,2"), (64, "4,0"),
+                                     (24, "8,2"), (40, "3,2,1"), (64, "4,2,2"), (24, "3,3,1")])
 def test_wide_candidate_rows(ctx, k, shape, monkeypatch):
     """k > 16: each lane of an ant's row holds 2 or 4 slots; a batch with
     rows of different widths uses the widest."""
