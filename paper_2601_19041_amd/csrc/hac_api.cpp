@@ -160,7 +160,7 @@ size_t Layout::bytes() const {
   b += align256(4 * nn * (size_t)ants) + align256(8 * (size_t)ants);
   b += 6 * align256(4 * nn);
   b += ls ? align256((directed ? dir_work_stride(n) : 12 * nn) * (size_t)ls_tours) : 0;
-  b += directed ? align256(4 * nn * (size_t)kls) : 0;
+  b += directed ? align256(8 * nn * (size_t)kls) : 0;
   if (gside > 0) {
     const size_t cells = (size_t)gside * gside;
     b += align256(4 * (cells + 1)) + align256(4 * cells) + align256(4 * nn) + align256(16 * nn) +
@@ -196,7 +196,7 @@ void assign_slot(HostInst& h, const std::function<void*(size_t)>& carve) {
   d.succ = (int32_t*)carve(4 * nn);
   d.pred = (int32_t*)carve(4 * nn);
   d.ls_work = L.ls ? (int32_t*)carve((L.directed ? dir_work_stride(L.n) : 12 * nn) * (size_t)L.ls_tours) : nullptr;
-  d.nl_in = L.directed ? (int32_t*)carve(4 * nn * (size_t)L.kls) : nullptr;
+  d.nl_in = L.directed ? (int32_t*)carve(8 * nn * (size_t)L.kls) : nullptr;
   d.gside = L.gside;
   if (L.gside > 0) {
     const size_t cells = (size_t)L.gside * L.gside;
@@ -451,14 +451,14 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   HAC_HIP(launch_grid(d_descs, count, s));
   HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
   bool any_ls = false;
-  int32_t all_coords = 1, max_n_dir = 0, max_n_sym = 0;  // largest directed / symmetric instance with 2-opt
+  int32_t all_coords = 1, max_n_dir = 0, max_kls_dir = 0, max_n_sym = 0;  // largest directed / symmetric
   for (auto& h : hs) {
     any_ls |= h.p.local_search != 0;
-    if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n);
+    if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n), max_kls_dir = std::max(max_kls_dir, h.lay.kls);
     else if (h.p.local_search) max_n_sym = std::max(max_n_sym, h.lay.n);
     if (h.p.local_search && !h.lay.directed && !h.lay.coords) all_coords = 0;
   }
-  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n_sym, all_coords, max_n_dir, s));
+  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n_sym, all_coords, max_n_dir, max_kls_dir, s));
   std::vector<State> sts(count);
   if (stage) {
     // after the weights' scatter on the same stream: the staging arena is reused
@@ -1173,12 +1173,12 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   if (m > 0) {
     bool any_ls = false;
     // max_n: the largest symmetric instance with 2-opt (0: none); max_n_dir: ATSP
-    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0;
+    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0, max_kls_dir = 0;
     for (auto& h : hs) {
       any_ls |= h.p.local_search != 0;
       if (h.p.local_search == 2) ls_tours = std::max(ls_tours, h.p.ants);
       max_iter = std::max(max_iter, h.p.iterations);
-      if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n);
+      if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n), max_kls_dir = std::max(max_kls_dir, h.lay.kls);
       else if (h.p.local_search) max_n = std::max(max_n, h.lay.n);
       if (h.p.local_search && !h.lay.directed && !h.lay.coords) all_coords = 0;
     }
@@ -1218,7 +1218,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
                                       shape.bytes, shape.kmax, lds, shape.geo, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
-        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, s);
+        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, s);
         if (e != hipSuccess) return e;
       }
       return launch_iter_end(d_descs, m, s);
@@ -1242,7 +1242,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
                                       shape.bytes, shape.kmax, lds, shape.geo, s));
         CTX_HIP(hipEventRecord(ev[1], s));
-        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, s));
+        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, s));
         CTX_HIP(hipEventRecord(ev[2], s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
         CTX_HIP(hipEventRecord(ev[3], s));

@@ -80,7 +80,7 @@ struct InstDesc {
   int32_t* ls_work;           // [3n] pos, queue, in-queue for 2-opt ([ants][3n] when
                               // every ant's tour is searched; dir_work_stride(n) bytes
                               // per tour for the directed 2-opt's arrays)
-  int32_t* nl_in;             // [n][kls] incoming lists (ATSP with local search), else null
+  int32_t* nl_in;             // [2][n][kls] incoming, then outgoing lists (ATSP with local search), else null
   int32_t gside;              // grid cells per side (0: no grid)
   int32_t* g_start;           // [side^2 + 1] first slot of each cell
   int32_t* g_cur;             // [side^2] build cursors
@@ -151,10 +151,10 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
 // (0: none, and the symmetric kernel is not launched); all_coords = 1 when
 // every such instance has coordinates (the FP32-filtered LDS mode needs
 // them); max_n_dir: largest ATSP instance with local search (0: none); such
-// instances take the directed 2-opt (and their incoming lists are built
-// first)
+// instances take the directed 2-opt (and their neighbour lists are built
+// first); max_kls_dir: their largest k_ls
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
-                             int32_t max_n_dir, hipStream_t s);
+                             int32_t max_n_dir, int32_t max_kls_dir, hipStream_t s);
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 // builds the coordinate grid of every instance that has one
 hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s);
@@ -174,7 +174,7 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
 // that search every ant's tour, else 1)
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                int32_t all_coords, int32_t tours_per_inst, int32_t max_n_dir,
-                               hipStream_t s);
+                               int32_t max_kls_dir, hipStream_t s);
 hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const* d_out_tours,
                          double* d_out_lens, hipStream_t s);

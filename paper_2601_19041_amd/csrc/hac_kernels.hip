@@ -1830,6 +1830,8 @@ struct DirWork {
   int32_t* pos;
   int32_t* queue;
   uint8_t* inq;
+  uint16_t* lo;  // LDS copies of the outgoing and incoming lists ([n][kls] each), or null
+  uint16_t* li;
 };
 
 __device__ __forceinline__ DirWork dir_work_at(char* base, int n) {
@@ -1932,8 +1934,14 @@ __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain,
   const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id();
   if (n < 5 || kls < 1) return;
   const HAC_AS1 double* d = as_global(D.dist);
-  const HAC_AS1 int32_t* out_l = as_global(D.geo);   // outgoing lists: d(a, .) order
-  const HAC_AS1 int32_t* in_l = as_global(D.nl_in);  // incoming lists: d(., a) order
+  const HAC_AS1 int32_t* in_l = as_global(D.nl_in);                   // incoming lists: d(., a) order
+  const HAC_AS1 int32_t* out_l = in_l + (int64_t)n * kls;              // outgoing lists: d(a, .) order
+  if (w.lo) {
+    for (int x = lane; x < n * kls; x += WAVE) {
+      w.lo[x] = (uint16_t)out_l[x];
+      w.li[x] = (uint16_t)in_l[x];
+    }
+  }
   for (int s = lane; s < n; s += WAVE) {
     const int v = tour_g[s];
     w.tour[s] = v;
@@ -1968,7 +1976,8 @@ __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain,
     const int pb = cyc_step(pa, step, n);
     const int b = w.tour[pb];
     const double dab = w.ef[pred_side ? pb : pa];  // d(a,b), or d(b,a) on the predecessor side
-    const int c = pred_side ? in_l[(int64_t)a * kls + (in_list ? q : 0)] : out_l[(int64_t)a * kg + (in_list ? q : 0)];
+    const int at = a * kls + (in_list ? q : 0);
+    const int c = w.lo ? (int)(pred_side ? w.li[at] : w.lo[at]) : (pred_side ? in_l[at] : out_l[at]);
     const int pc = w.pos[c];
     const int pe = cyc_step(pc, step, n);
     const int e = w.tour[pe];
@@ -2044,12 +2053,19 @@ __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain,
 }
 
 // the directed 2-opt's working arrays: in LDS when the launch gave room for
-// them (lds_ok), else in the tour's part of the work area
-__device__ __forceinline__ DirWork dir_work_for(const InstDesc& D, int lds_ok, int tour_index) {
+// them (lds_mode >= 1), else in the tour's part of the work area; with
+// lds_mode 2 the neighbour lists are copied into LDS behind them as uint16
+__device__ __forceinline__ DirWork dir_work_for(const InstDesc& D, int lds_mode, int tour_index) {
   extern __shared__ __align__(16) char dir_lds[];
-  return dir_work_at(lds_ok ? dir_lds
-                            : reinterpret_cast<char*>(D.ls_work) + (int64_t)tour_index * dir_work_stride(D.n),
-                     D.n);
+  DirWork w = dir_work_at(lds_mode ? dir_lds
+                                   : reinterpret_cast<char*>(D.ls_work) + (int64_t)tour_index * dir_work_stride(D.n),
+                          D.n);
+  w.lo = w.li = nullptr;
+  if (lds_mode == 2) {
+    w.lo = reinterpret_cast<uint16_t*>(dir_lds + ((dir_work_bytes(D.n) + 15) & ~(size_t)15));
+    w.li = w.lo + (size_t)D.n * D.kls;
+  }
+  return w;
 }
 
 // incoming lists: for node i the kls nodes j with the smallest d(j, i),
@@ -2068,13 +2084,17 @@ __global__ void __launch_bounds__(256) in_lists_kernel(const InstDesc* insts) {
     const bool valid = j < n && j != i;
     topk_offer(t, valid ? d[(int64_t)j * n + i] : 0.0, j, valid);
   }
-  if (lane < kls) D.nl_in[(int64_t)i * kls + lane] = t.id;
+  if (lane < kls) {
+    D.nl_in[(int64_t)i * kls + lane] = t.id;
+    // the first kls entries of the geometric list: the outgoing list
+    D.nl_in[(int64_t)n * kls + (int64_t)i * kls + lane] = D.geo[(int64_t)i * D.kg + lane];
+  }
 }
 
-__global__ void __launch_bounds__(WAVE) directed_two_opt_nn_kernel(const InstDesc* insts, int lds_ok) {
+__global__ void __launch_bounds__(WAVE) directed_two_opt_nn_kernel(const InstDesc* insts, int lds_mode) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || D.sym) return;
-  dir_two_opt(D, D.nn_tour, D.st->min_gain, dir_work_for(D, lds_ok, 0));
+  dir_two_opt(D, D.nn_tour, D.st->min_gain, dir_work_for(D, lds_mode, 0));
   const double len = tour_length_wave(D, D.nn_tour);
   if (threadIdx.x == 0) {
     D.st->l_gb = len;
@@ -2084,14 +2104,14 @@ __global__ void __launch_bounds__(WAVE) directed_two_opt_nn_kernel(const InstDes
 
 // local_search = 1: block (i, 0) improves a copy of the iteration best;
 // local_search = 2: block (i, y) improves ant tours y, y + gridDim.y, ...
-__global__ void __launch_bounds__(WAVE) directed_local_search_kernel(const InstDesc* insts, int lds_ok) {
+__global__ void __launch_bounds__(WAVE) directed_local_search_kernel(const InstDesc* insts, int lds_mode) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || D.sym || D.st->t > D.iterations || D.st->err) return;
   const int n = D.n;
   if (D.local_search == 2) {
     for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
       int32_t* tour = D.tours + (int64_t)a * n;
-      dir_two_opt(D, tour, D.st->min_gain, dir_work_for(D, lds_ok, a));
+      dir_two_opt(D, tour, D.st->min_gain, dir_work_for(D, lds_mode, a));
       const double len = tour_length_wave(D, tour);
       if (threadIdx.x == 0) D.lens[a] = len;
       wave_sync();
@@ -2105,7 +2125,7 @@ __global__ void __launch_bounds__(WAVE) directed_local_search_kernel(const InstD
   const int32_t* src = D.tours + (int64_t)ib * n;
   for (int s = threadIdx.x; s < n; s += WAVE) D.t_ib[s] = src[s];
   wave_sync();
-  dir_two_opt(D, D.t_ib, D.st->min_gain, dir_work_for(D, lds_ok, 0));
+  dir_two_opt(D, D.t_ib, D.st->min_gain, dir_work_for(D, lds_mode, 0));
   const double len = tour_length_wave(D, D.t_ib);
   if (threadIdx.x == 0) {
     D.st->ib = ib;
@@ -2413,34 +2433,43 @@ static int ls_mode(int32_t max_n, int32_t all_coords) {
   return 0;
 }
 
-// LDS for the directed 2-opt of the largest ATSP instance, or 0 when its
-// arrays go to the work area in global memory
-static size_t dir_lds_bytes(int32_t max_n_dir) {
-  if (const char* f = std::getenv("HAC_LS_MODE"))
-    if (f[0] == '0') return 0;  // pins the work area to global memory (as for the symmetric 2-opt)
-  const size_t need = dir_work_bytes(max_n_dir);
-  return need <= (size_t)max_lds_bytes() - 1024 ? need : 0;
+// Where the directed 2-opt of the largest ATSP instance keeps its arrays:
+// mode 2 the work arrays and uint16 copies of both neighbour lists in LDS,
+// 1 the work arrays in LDS, 0 the work area in global memory; and the LDS
+// bytes that takes.  HAC_LS_MODE (0 or 1) pins mode 0 or 1.
+static int dir_lds_mode(int32_t max_n_dir, int32_t max_kls_dir, size_t* bytes) {
+  const size_t cap = (size_t)max_lds_bytes() - 1024;
+  const size_t work = dir_work_bytes(max_n_dir);
+  const size_t lists = ((work + 15) & ~(size_t)15) + (size_t)4 * max_n_dir * max_kls_dir;
+  int mode = lists <= cap && max_n_dir <= 65535 ? 2 : (work <= cap ? 1 : 0);
+  if (const char* f = std::getenv("HAC_LS_MODE")) {
+    if (f[0] == '0') mode = 0;  // pins the work area to global memory (as for the symmetric 2-opt)
+    if (f[0] == '1' && mode == 2) mode = 1;
+  }
+  *bytes = mode == 2 ? lists : (mode == 1 ? work : 0);
+  return mode;
 }
 
-static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_t max_n_dir, int32_t tpi,
-                                  bool nn, hipStream_t s) {
-  const size_t lds = dir_lds_bytes(max_n_dir);
+static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_t max_n_dir, int32_t max_kls_dir,
+                                  int32_t tpi, bool nn, hipStream_t s) {
+  size_t lds = 0;
+  const int mode = dir_lds_mode(max_n_dir, max_kls_dir, &lds);
   if (nn)
-    hipLaunchKernelGGL(directed_two_opt_nn_kernel, dim3(count), dim3(WAVE), lds, s, d_insts, lds ? 1 : 0);
+    hipLaunchKernelGGL(directed_two_opt_nn_kernel, dim3(count), dim3(WAVE), lds, s, d_insts, mode);
   else
     hipLaunchKernelGGL(directed_local_search_kernel, dim3(count, std::max(tpi, 1)), dim3(WAVE), lds, s, d_insts,
-                       lds ? 1 : 0);
+                       mode);
   return hipGetLastError();
 }
 
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
-                             int32_t max_n_dir, hipStream_t s) {
+                             int32_t max_n_dir, int32_t max_kls_dir, hipStream_t s) {
   if (max_n_dir > 0) {
     const int waves = 4;
     hipLaunchKernelGGL(in_lists_kernel, dim3((max_n_dir + waves - 1) / waves, count), dim3(waves * WAVE), 0, s,
                        d_insts);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = launch_directed(d_insts, count, max_n_dir, 1, true, s);
+    if (e == hipSuccess) e = launch_directed(d_insts, count, max_n_dir, max_kls_dir, 1, true, s);
     if (e != hipSuccess) return e;
   }
   if (max_n <= 0) return hipSuccess;  // no symmetric instance searches
@@ -2636,9 +2665,9 @@ static int ls_block_waves(int32_t max_n, int mode, int64_t tours) {
 
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                int32_t all_coords, int32_t tours_per_inst, int32_t max_n_dir,
-                               hipStream_t s) {
+                               int32_t max_kls_dir, hipStream_t s) {
   if (max_n_dir > 0) {
-    const hipError_t e = launch_directed(d_insts, count, max_n_dir, tours_per_inst, false, s);
+    const hipError_t e = launch_directed(d_insts, count, max_n_dir, max_kls_dir, tours_per_inst, false, s);
     if (e != hipSuccess) return e;
   }
   if (max_n <= 0) return hipSuccess;  // no symmetric instance searches

@@ -59,11 +59,15 @@ def _atsp(n, seed, ls, **kw):
 
 
 @pytest.mark.parametrize("ls", [1, 2])
-@pytest.mark.parametrize("mode", ["lds", "global"])
+@pytest.mark.parametrize("mode", ["lds", "lds_work_only", "global"])
 def test_directed_small(ctx, ls, mode, monkeypatch):
+    """Work arrays and neighbour lists in LDS (the default here), work
+    arrays only in LDS, and everything in global memory."""
     inst = _atsp(90, 50 + ls, ls)
     if mode == "global":
         monkeypatch.setenv("HAC_LS_MODE", "0")
+    elif mode == "lds_work_only":
+        monkeypatch.setenv("HAC_LS_MODE", "1")
     print(f"case directed n=90 local_search {ls} {mode}", flush=True)
     _same(ctx.decode(inst), oracle.decode(inst), f"ls{ls} {mode}")
     _state(ctx, inst)
