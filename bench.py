@@ -362,6 +362,49 @@ def sub_tsp10k(hac, insts, plain_count=1):
             "launch_shape": launch_shape(st)}
 
 
+def atsp_specs(count, iterations):
+    """The served ATSP1000 request kind with the directed 2-opt (20 neighbours)
+    on each iteration best."""
+    return [("atsp1000", r, iterations) for r in range(count)]
+
+
+def with_directed_2opt(insts, ls=1):
+    import dataclasses
+    return [dataclasses.replace(x, local_search=ls, k_ls=20) for x in insts]
+
+
+def sub_atsp(hac, insts, plain_count=2):
+    """16 ATSP instances with the directed 2-opt: one timed batched decode on
+    the production path, the kernel lines from a timed decode, and plain
+    decodes of the first instances (tours asserted equal)."""
+    import torch
+    ctx = hac.Context(0)
+    db = hac.DeviceBatch(insts)
+    print("bench: atsp timing pass", file=sys.stderr, flush=True)
+    st = timing_pass(ctx, lambda: ctx.decode_batch_dev(db))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.decode_batch_dev(db)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    batched = db.results()
+    lat, _, equal = plain_sample(ctx, insts, plain_count, batched)
+    ctx.close()
+    assert equal, "plain and batched tours differ (atsp)"
+    dps, plain_dps = len(insts) / wall, len(lat) / sum(lat)
+    ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
+    lines = kernel_lines(insts, st)
+    return {"workload": f"atsp: {len(insts)} ATSP instances (the served ATSP1000 kind), n=1000, directed top-20 "
+                        f"heatmaps, k=20, 50 ants, {insts[0].iterations} iterations, directed 2-opt (20) on each "
+                        "iteration best",
+            "steps": 1, "ms_per_step": 1000 * wall, "ant_steps_per_s": ant_steps / wall,
+            "decodes_per_s": dps, "plain": {"decodes_per_s": plain_dps, "sample": len(lat)},
+            "batched_vs_plain": dps / plain_dps, "equal_gap": equal,
+            "latency_ms": {"batched": 1000 * wall, "plain_p50": 1000 * percentile(lat, 0.5)},
+            "roofline": lines["construct"], "kernels": {k: v for k, v in lines.items() if k != "construct"},
+            "launch_shape": launch_shape(st)}
+
+
 def run_plain(args, hac, inst, cpu, name, desc):
     ctx = hac.Context(0)
     db = hac.DeviceBatch([inst])
@@ -608,7 +651,7 @@ def main():
     ap.add_argument("--cpu-iterations", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="batch64: leave out the tsp10k and serve sub-objects")
+                    help="batch64: leave out the tsp10k, atsp and serve sub-objects")
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -652,13 +695,12 @@ def main():
     elif args.workload == "tsp10k":
         insts = generate([("tsp10k", x, it or 200) for x in range(8)])
     elif args.workload == "atsp":
-        import dataclasses
-        insts = [dataclasses.replace(x, local_search=args.ls or 1, k_ls=20)
-                 for x in generate([("atsp1000", r, it or 100) for r in range(args.instances or 16)])]
+        insts = with_directed_2opt(generate(atsp_specs(args.instances or 16, it or 100)), args.ls or 1)
     else:
         insts = None
     if extras:
         tsp10k_insts = generate([("tsp10k", x, 200) for x in range(8)])
+        atsp_insts = with_directed_2opt(generate(atsp_specs(16, 100)))
         mix, specs = serve_specs(args.requests)
         serve_reqs = generate(specs)
     print(f"bench: inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
@@ -678,6 +720,7 @@ def main():
                           "k=10, 50 ants, 500 iterations, no local search", args.plain_sample, "batch64")
         if extras:
             out["tsp10k"] = sub_tsp10k(hac, tsp10k_insts)
+            out["atsp"] = sub_atsp(hac, atsp_insts)
             out["serve"] = sub_serve(hac, wl, mix, serve_reqs, args.serve_budget_gb, args.slots)
     elif args.workload == "tsp10k":
         out = run_batched(args, hac, insts, cpu, "8 TSP instances, n 10000, 2-opt",
