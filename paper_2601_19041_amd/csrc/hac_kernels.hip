@@ -1798,7 +1798,7 @@ __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const Ins
 }
 
 // ------------------------------------------------------------------------
-// Directed 2-opt for the ATSP (Section III-D), one wave per tour.
+// Directed 2-opt for the ATSP (Section III-D), one block per tour.
 //
 // A move reverses the tour path between its two inner nodes and prices it in
 // its new direction: on the successor side of node a (b = succ a, c from a's
@@ -1807,15 +1807,16 @@ __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const Ins
 // a's incoming list, e = pred c) (b->a), (e->c) become (c->a), (e->b) and
 // the path c..b is reversed.  gain = (removed edges + F) - (added edges + B)
 // with F and B the path's cost in its old and new direction, from prefix
-// sums of the directed edge lengths in tour order (pf, pb), which one lane
-// adds up in tour order after each move, from the first position whose edge
-// changed, so that they are the sums of a full recomputation.  The queue,
+// sums of the directed edge lengths in tour order (pf, pb), summed in blocks
+// of 64 positions (dir_prefix) and brought up to date after each move from
+// the first block whose edge changed, so that they equal a full
+// recomputation.  The queue,
 // the side order, the list stop rule, the threshold, the re-queueing of the
 // end nodes and the re-examination of a are those of the symmetric 2-opt;
 // the reversed part is always the path itself, and a search applies at most
-// 64 n moves.  The 64 lanes evaluate a's moves at once: lanes 0..31 the
-// successor side in list order, 32..63 the predecessor side; the first
-// improving move in that order is the sequential one.
+// 64 n moves.  The 64 lanes of a wave evaluate a's moves at once: lanes
+// 0..31 the successor side in list order, 32..63 the predecessor side; the
+// first improving move in that order is the sequential one.
 // ------------------------------------------------------------------------
 struct DirWork {
   double* ef;   // [n] d(T[q], T[q+1]) (the closing edge at n - 1)
@@ -1879,15 +1880,15 @@ __device__ __forceinline__ void dir_block_sums(const double* e, int q0, int q1, 
 }
 
 __device__ void dir_prefix(const HAC_AS1 double* d, int n, const DirWork& w, int lo, int hi) {
-  const int lane = lane_id();
-  for (int q = lo + lane; q <= hi; q += WAVE) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int q = lo + t; q <= hi; q += nt) {
     const int x = w.tour[q], y = w.tour[q + 1 == n ? 0 : q + 1];
     w.ef[q] = d[(int64_t)x * n + y];
     w.eb[q] = d[(int64_t)y * n + x];
   }
-  wave_sync();
+  __syncthreads();
   const int blo = lo / 64, bhi = hi / 64, blast = n / 64;
-  for (int b = blo + lane; b <= bhi; b += WAVE) {
+  for (int b = blo + t; b <= bhi; b += nt) {
     const int q0 = 64 * b, q1 = min(q0 + 64, n);
     double f = 0.0, r = 0.0;
     dir_block_sums(w.ef, q0, q1, f);
@@ -1895,8 +1896,8 @@ __device__ void dir_prefix(const HAC_AS1 double* d, int n, const DirWork& w, int
     w.tf[b] = f;
     w.tb[b] = r;
   }
-  wave_sync();
-  if (lane == 0) {
+  __syncthreads();
+  if (t == 0) {
     if (blo == 0) {
       w.sf[0] = 0.0;
       w.sb[0] = 0.0;
@@ -1909,8 +1910,8 @@ __device__ void dir_prefix(const HAC_AS1 double* d, int n, const DirWork& w, int
       w.sb[b + 1] = r;
     }
   }
-  wave_sync();
-  for (int b = blo + lane; b <= blast; b += WAVE) {
+  __syncthreads();
+  for (int b = blo + t; b <= blast; b += nt) {
     const int q0 = 64 * b, qe = min(q0 + 64, n + 1);
     const double s1 = w.sf[b], s2 = w.sb[b];
     double f = 0.0, r = 0.0;
@@ -1923,98 +1924,170 @@ __device__ void dir_prefix(const HAC_AS1 double* d, int n, const DirWork& w, int
       }
     }
   }
-  wave_sync();
+  __syncthreads();
 }
 
 __device__ __forceinline__ double dir_path_cost(const double* pre, int n, int i, int j) {
   return i <= j ? pre[j] - pre[i] : (pre[n] - pre[i]) + pre[j];
 }
 
+struct DirMove {
+  int imp, a, b, c, e, i, j;
+};
+
+// The search is block-wide, like the symmetric 2-opt: each round the waves
+// evaluate the next queue entries against the same tour (wave 0 re-examines
+// the node of the last applied move first), the first improving result in
+// that order is applied, and the entries before it are consumed as the
+// sequential scan would consume them; the results behind it are dropped.
+// The last wave does the queue bookkeeping while the others reverse the
+// path.  On an ant's tour most entries have no improving move, so a round
+// consumes many of them.
 __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain, const DirWork& w) {
-  const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id();
+  __shared__ int sh_head, sh_count;
+  __shared__ DirMove sh_mv[LS_WAVES];
+  const int n = D.n, kls = D.kls, lane = lane_id(), wave = threadIdx.x / WAVE;
+  const int nw = (int)(blockDim.x / WAVE);
   if (n < 5 || kls < 1) return;
   const HAC_AS1 double* d = as_global(D.dist);
-  const HAC_AS1 int32_t* in_l = as_global(D.nl_in);                   // incoming lists: d(., a) order
-  const HAC_AS1 int32_t* out_l = in_l + (int64_t)n * kls;              // outgoing lists: d(a, .) order
+  const HAC_AS1 int32_t* in_l = as_global(D.nl_in);        // incoming lists: d(., a) order
+  const HAC_AS1 int32_t* out_l = in_l + (int64_t)n * kls;   // outgoing lists: d(a, .) order
   if (w.lo) {
-    for (int x = lane; x < n * kls; x += WAVE) {
+    for (int x = threadIdx.x; x < n * kls; x += blockDim.x) {
       w.lo[x] = (uint16_t)out_l[x];
       w.li[x] = (uint16_t)in_l[x];
     }
   }
-  for (int s = lane; s < n; s += WAVE) {
+  for (int s = threadIdx.x; s < n; s += blockDim.x) {
     const int v = tour_g[s];
     w.tour[s] = v;
     w.queue[s] = v;
   }
-  wave_sync();
-  for (int s = lane; s < n; s += WAVE) {
+  __syncthreads();
+  for (int s = threadIdx.x; s < n; s += blockDim.x) {
     w.pos[w.tour[s]] = s;
     w.inq[w.tour[s]] = 1;
   }
+  if (threadIdx.x == 0) {
+    sh_head = 0;
+    sh_count = n;
+  }
+  __syncthreads();
   dir_prefix(d, n, w, 0, n - 1);
   const int64_t max_moves = 64 * (int64_t)n;
   int64_t moves = 0;
-  int head = 0, count = n, pend = -1;
+  int pend = -1;
   const bool pred_side = lane >= 32;
   const int q = lane & 31;
   const bool in_list = q < kls;
+  const int step = pred_side ? -1 : 1;
+  const int bw = nw - 1;  // the bookkeeping wave
   while (moves < max_moves) {
-    int a = pend;
-    if (a < 0) {
-      if (count == 0) break;
-      a = w.queue[head];
-      head = head + 1 == n ? 0 : head + 1;
-      --count;
-      if (lane == 0) w.inq[a] = 0;
-      wave_sync();
+    const int head = sh_head, count = sh_count;
+    const int re = pend >= 0 ? 1 : 0;
+    const int nq = min(nw - re, count);  // queue entries in this batch
+    const int nb = nq + re;
+    if (nb == 0) break;
+    if (wave < nb) {
+      int a = pend;
+      if (wave >= re) {
+        int slot = head + wave - re;
+        if (slot >= n) slot -= n;
+        a = w.queue[slot];
+      }
+      // the tour edges a-b and c-e are entries of ef; only d(a,c) and
+      // d(b,e) come from the matrix, both loaded once e is known
+      const int pa = w.pos[a];
+      const int pb = cyc_step(pa, step, n);
+      const int b = w.tour[pb];
+      const double dab = w.ef[pred_side ? pb : pa];  // d(a,b), or d(b,a) on the predecessor side
+      const int at = a * kls + (in_list ? q : 0);
+      const int c = w.lo ? (int)(pred_side ? w.li[at] : w.lo[at]) : (pred_side ? in_l[at] : out_l[at]);
+      const int pc = w.pos[c];
+      const int pe = cyc_step(pc, step, n);
+      const int e = w.tour[pe];
+      const double dce = w.ef[pred_side ? pe : pc];  // d(c,e), or d(e,c)
+      const double dac = pred_side ? d[(int64_t)c * n + a] : d[(int64_t)a * n + c];
+      const double dbe = pred_side ? d[(int64_t)e * n + b] : d[(int64_t)b * n + e];
+      const bool g1pos = dab - dac > 0.0;
+      // a side stops at its first list entry that cannot gain
+      const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !g1pos);
+      const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
+      const int lim = pred_side ? (stop_p ? (int)__builtin_ctzll(stop_p) : 32)
+                                : (stop_s ? (int)__builtin_ctzll(stop_s) : 32);
+      const bool ok = in_list && q < lim;
+      const bool degenerate = e == a || c == b || c == a;
+      int i = 0, j = 0;
+      bool imp = false;
+      if (ok && !degenerate) {
+        i = pred_side ? pc : pb;
+        j = pred_side ? pb : pc;
+        const double F = dir_path_cost(w.pf, n, i, j), B = dir_path_cost(w.pb, n, i, j);
+        const double gain = ((dab + dce) + F) - ((dac + dbe) + B);
+        imp = gain > min_gain;
+      }
+      const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
+      DirMove m{0, a, 0, 0, 0, 0, 0};
+      if (mi) {
+        const int l = (int)__builtin_ctzll(mi);
+        m.imp = 1;
+        m.b = rd_lane(b, l);
+        m.c = rd_lane(c, l);
+        m.e = rd_lane(e, l);
+        m.i = rd_lane(i, l);
+        m.j = rd_lane(j, l);
+      }
+      if (lane == 0) sh_mv[wave] = m;
     }
-    // the tour edges a-b and c-e are entries of ef (read from LDS); only
-    // d(a,c) and d(b,e) come from the matrix, both loaded once e is known
-    const int step = pred_side ? -1 : 1;
-    const int pa = w.pos[a];
-    const int pb = cyc_step(pa, step, n);
-    const int b = w.tour[pb];
-    const double dab = w.ef[pred_side ? pb : pa];  // d(a,b), or d(b,a) on the predecessor side
-    const int at = a * kls + (in_list ? q : 0);
-    const int c = w.lo ? (int)(pred_side ? w.li[at] : w.lo[at]) : (pred_side ? in_l[at] : out_l[at]);
-    const int pc = w.pos[c];
-    const int pe = cyc_step(pc, step, n);
-    const int e = w.tour[pe];
-    const double dce = w.ef[pred_side ? pe : pc];  // d(c,e), or d(e,c)
-    const double dac = pred_side ? d[(int64_t)c * n + a] : d[(int64_t)a * n + c];
-    const double dbe = pred_side ? d[(int64_t)e * n + b] : d[(int64_t)b * n + e];
-    const bool g1pos = dab - dac > 0.0;
-    // a side stops at its first list entry that cannot gain
-    const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !g1pos);
-    const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
-    const int lim = pred_side ? (stop_p ? (int)__builtin_ctzll(stop_p) : 32)
-                              : (stop_s ? (int)__builtin_ctzll(stop_s) : 32);
-    const bool ok = in_list && q < lim;
-    const bool degenerate = e == a || c == b || c == a;
-    int i = 0, j = 0;
-    bool imp = false;
-    if (ok && !degenerate) {
-      i = pred_side ? pc : pb;
-      j = pred_side ? pb : pc;
-      const double F = dir_path_cost(w.pf, n, i, j), B = dir_path_cost(w.pb, n, i, j);
-      const double gain = ((dab + dce) + F) - ((dac + dbe) + B);
-      imp = gain > min_gain;
+    __syncthreads();
+    // the first improving result in batch order (one entry per lane)
+    const uint64_t fm = __builtin_amdgcn_ballot_w64(lane < nb && sh_mv[min(lane, LS_WAVES - 1)].imp);
+    const int f = fm ? (int)__builtin_ctzll(fm) : -1;
+    const DirMove mv = f >= 0 ? sh_mv[f] : DirMove{0, 0, 0, 0, 0, 0, 0};
+    if (wave == bw) {
+      // queue entries consumed as a sequential scan would: all of them if
+      // no move improves, else those up to and including the improving one
+      const int used = f < 0 ? nq : max(0, f + 1 - re);
+      if (lane < used) {
+        int slot = head + lane;
+        if (slot >= n) slot -= n;
+        w.inq[w.queue[slot]] = 0;
+      }
+      int h = head + used;
+      if (h >= n) h -= n;
+      int cnt = count - used;
+      if (f >= 0) {
+        // the end nodes a, b, c, e join the queue tail in that order if
+        // absent, one lane each
+        const bool mine = lane < 4;
+        const int x = lane == 0 ? mv.a : (lane == 1 ? mv.b : (lane == 2 ? mv.c : mv.e));
+        const bool absent = mine && !w.inq[x];
+        const uint32_t am = (uint32_t)__builtin_amdgcn_ballot_w64(absent) & 0xfu;
+        if (absent) {
+          int slot = h + cnt + __builtin_popcount(am & ((1u << lane) - 1u));
+          if (slot >= n) slot -= n;
+          w.queue[slot] = x;
+          w.inq[x] = 1;
+        }
+        cnt += __builtin_popcount(am);
+      }
+      if (lane == 0) {
+        sh_head = h;
+        sh_count = cnt;
+      }
     }
-    const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
-    if (!mi) {
+    if (f < 0) {
       pend = -1;
+      __syncthreads();
       continue;
     }
-    const int l = (int)__builtin_ctzll(mi);
-    const int mb = rd_lane(b, l), mc = rd_lane(c, l), me = rd_lane(e, l);
-    const int mi_ = rd_lane(i, l), mj = rd_lane(j, l);
-    // reverse the positions mi_..mj (cyclic)
-    const int len = ((mj - mi_ + n) % n) + 1;
-    for (int s = lane; s < len / 2; s += WAVE) {
-      int x = mi_ + s;
+    // reverse the positions mv.i .. mv.j (cyclic), by the other waves
+    const int len = (mv.j >= mv.i ? mv.j - mv.i : mv.j - mv.i + n) + 1;
+    const int rthreads = bw > 0 ? bw * WAVE : WAVE;
+    for (int s2 = (bw > 0 && wave == bw) ? len : (int)threadIdx.x; s2 < len / 2; s2 += rthreads) {
+      int x = mv.i + s2;
       if (x >= n) x -= n;
-      int y = mj - s;
+      int y = mv.j - s2;
       if (y < 0) y += n;
       const int tx = w.tour[x], ty = w.tour[y];
       w.tour[x] = ty;
@@ -2022,34 +2095,19 @@ __device__ void dir_two_opt(const InstDesc& D, int32_t* tour_g, double min_gain,
       w.pos[ty] = x;
       w.pos[tx] = y;
     }
-    wave_sync();
-    // the end nodes join the queue tail in the order a, b, c, e if absent
-    if (lane == 0) {
-      const int ends[4] = {a, mb, mc, me};
-      for (int z = 0; z < 4; ++z) {
-        const int x = ends[z];
-        if (!w.inq[x]) {
-          int slot = head + count;
-          if (slot >= n) slot -= n;
-          w.queue[slot] = x;
-          ++count;
-          w.inq[x] = 1;
-        }
-      }
-    }
-    count = rd_lane(count, 0);
-    wave_sync();
-    // the edges mi_ - 1 .. mj changed (all of them when the path wraps or
+    __syncthreads();
+    // the edges i - 1 .. j changed (all of them when the path wraps or
     // starts at position 0, where the closing edge changes too)
-    if (mi_ >= 1 && mi_ <= mj)
-      dir_prefix(d, n, w, mi_ - 1, mj);
+    if (mv.i >= 1 && mv.i <= mv.j)
+      dir_prefix(d, n, w, mv.i - 1, mv.j);
     else
       dir_prefix(d, n, w, 0, n - 1);
     ++moves;
-    pend = a;
+    pend = mv.a;
   }
-  for (int s = lane; s < n; s += WAVE) tour_g[s] = w.tour[s];
-  wave_sync();
+  __syncthreads();
+  for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = w.tour[s];
+  __syncthreads();
 }
 
 // the directed 2-opt's working arrays: in LDS when the launch gave room for
@@ -2091,20 +2149,22 @@ __global__ void __launch_bounds__(256) in_lists_kernel(const InstDesc* insts) {
   }
 }
 
-__global__ void __launch_bounds__(WAVE) directed_two_opt_nn_kernel(const InstDesc* insts, int lds_mode) {
+__global__ void __launch_bounds__(LS_WAVES * WAVE) directed_two_opt_nn_kernel(const InstDesc* insts, int lds_mode) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || D.sym) return;
   dir_two_opt(D, D.nn_tour, D.st->min_gain, dir_work_for(D, lds_mode, 0));
-  const double len = tour_length_wave(D, D.nn_tour);
-  if (threadIdx.x == 0) {
-    D.st->l_gb = len;
-    D.st->l_ib = len;
+  if (threadIdx.x < WAVE) {
+    const double len = tour_length_wave(D, D.nn_tour);
+    if (threadIdx.x == 0) {
+      D.st->l_gb = len;
+      D.st->l_ib = len;
+    }
   }
 }
 
 // local_search = 1: block (i, 0) improves a copy of the iteration best;
 // local_search = 2: block (i, y) improves ant tours y, y + gridDim.y, ...
-__global__ void __launch_bounds__(WAVE) directed_local_search_kernel(const InstDesc* insts, int lds_mode) {
+__global__ void __launch_bounds__(LS_WAVES * WAVE) directed_local_search_kernel(const InstDesc* insts, int lds_mode) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || D.sym || D.st->t > D.iterations || D.st->err) return;
   const int n = D.n;
@@ -2112,24 +2172,35 @@ __global__ void __launch_bounds__(WAVE) directed_local_search_kernel(const InstD
     for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
       int32_t* tour = D.tours + (int64_t)a * n;
       dir_two_opt(D, tour, D.st->min_gain, dir_work_for(D, lds_mode, a));
-      const double len = tour_length_wave(D, tour);
-      if (threadIdx.x == 0) D.lens[a] = len;
-      wave_sync();
+      if (threadIdx.x < WAVE) {
+        const double len = tour_length_wave(D, tour);
+        if (threadIdx.x == 0) D.lens[a] = len;
+      }
+      __syncthreads();
     }
     return;
   }
   if (blockIdx.y != 0) return;
-  int ib;
-  double lib;
-  iteration_best_wave(D, ib, lib);
+  __shared__ int sh_ib;
+  if (threadIdx.x < WAVE) {
+    int ib;
+    double lib;
+    iteration_best_wave(D, ib, lib);
+    if (threadIdx.x == 0) sh_ib = ib;
+  }
+  __syncthreads();
+  const int ib = sh_ib;
   const int32_t* src = D.tours + (int64_t)ib * n;
-  for (int s = threadIdx.x; s < n; s += WAVE) D.t_ib[s] = src[s];
-  wave_sync();
+  for (int s = threadIdx.x; s < n; s += blockDim.x) D.t_ib[s] = src[s];
+  __threadfence_block();
+  __syncthreads();
   dir_two_opt(D, D.t_ib, D.st->min_gain, dir_work_for(D, lds_mode, 0));
-  const double len = tour_length_wave(D, D.t_ib);
-  if (threadIdx.x == 0) {
-    D.st->ib = ib;
-    D.st->l_ib = len;
+  if (threadIdx.x < WAVE) {
+    const double len = tour_length_wave(D, D.t_ib);
+    if (threadIdx.x == 0) {
+      D.st->ib = ib;
+      D.st->l_ib = len;
+    }
   }
 }
 
@@ -2450,15 +2521,30 @@ static int dir_lds_mode(int32_t max_n_dir, int32_t max_kls_dir, size_t* bytes) {
   return mode;
 }
 
+// Waves per directed 2-opt block, chosen as for the symmetric search: the
+// full LS_WAVES while the tours number at most 256, else as few as 4 so that
+// as many tours run at once as LDS allows on a CU.  HAC_LS_WAVES pins it.
+// Results do not depend on it.
+static int dir_block_waves(size_t lds, int64_t tours) {
+  if (const char* env = std::getenv("HAC_LS_WAVES")) {
+    const int w = std::atoi(env);
+    if (w >= 1 && w <= LS_WAVES) return w;
+  }
+  if (tours <= 256) return LS_WAVES;
+  const int by_lds = lds ? (int)std::max<size_t>(1, (size_t)max_lds_bytes() / lds) : 8;
+  return std::max(4, std::min(LS_WAVES, 32 / std::min(by_lds, 8)));
+}
+
 static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_t max_n_dir, int32_t max_kls_dir,
                                   int32_t tpi, bool nn, hipStream_t s) {
   size_t lds = 0;
   const int mode = dir_lds_mode(max_n_dir, max_kls_dir, &lds);
+  const int64_t tours = nn ? count : (int64_t)count * std::max(tpi, 1);
+  const dim3 block(dir_block_waves(lds, tours) * WAVE);
   if (nn)
-    hipLaunchKernelGGL(directed_two_opt_nn_kernel, dim3(count), dim3(WAVE), lds, s, d_insts, mode);
+    hipLaunchKernelGGL(directed_two_opt_nn_kernel, dim3(count), block, lds, s, d_insts, mode);
   else
-    hipLaunchKernelGGL(directed_local_search_kernel, dim3(count, std::max(tpi, 1)), dim3(WAVE), lds, s, d_insts,
-                       mode);
+    hipLaunchKernelGGL(directed_local_search_kernel, dim3(count, std::max(tpi, 1)), block, lds, s, d_insts, mode);
   return hipGetLastError();
 }
 
