@@ -1533,8 +1533,13 @@ struct AntRows {
       }
       if (g == gg) jg = jj;
     }
+    // idle rows take row 0's node, so that they stay in step with it (they
+    // read its marks and draws) instead of wandering off and sending the
+    // wave into this branch on steps where no live row is exhausted
+    const int jg0 = rd_lane(jg, 0);
+    if (!live) jg = jg0;
     if (exhausted) {
-      j = jg < 0 ? 0 : jg;  // only idle rows can be left without a node
+      j = jg < 0 ? 0 : jg;
       if (u == 0 && live) {
         mark(j);
         fallbacks++;
