@@ -1303,7 +1303,7 @@ constexpr int kListScanMax = 1024;
 // to LDS as 8-byte {id, weight} entries; 2 as uint16 ids and FP32 weights
 // (six bytes per slot, for tables that do not fit as 8-byte entries); 3 as
 // in 2 but without the coordinates, which leaves room for unvisited lists.
-template <int STAGED, int S, bool BYTES>
+template <int STAGED, int S, bool BYTES, int GEO>
 struct AntRows {
   int n, k, kg, u, g;
   const HAC_AS1 char* cw_g;       // the candidate table in global memory
@@ -1318,7 +1318,10 @@ struct AntRows {
   GDist D;
   const HAC_AS1 int32_t* geo;
   const HAC_AS1 uint64_t* geo16;  // uint16 lists, 16 x 8 bytes (64 entries) per node
-  int geo_mode;                   // 0 no list check, 1 int32 lists, 2 uint16 lists a step ahead
+  // how an exhausted row consults its geometric list: 0 not at all, 1 int32
+  // lists, 2 uint16 lists a step ahead (a template parameter, so that each
+  // kernel's step holds only its own mode's code)
+  static constexpr int geo_mode = GEO;
   uint64_t glr;                   // mode 2: entries 4u .. 4u + 3 of the current node's list
   uint32_t* vis_wave;  // visited marks of the wave's live rows, vis_words apart
   uint32_t* vis_g;     // this row's marks (row 0's for an idle row, which never writes)
@@ -1557,11 +1560,11 @@ __device__ __forceinline__ void sum_row_in_order(double& len, double d) {
   }
 }
 
-template <int STAGED, int S, bool BYTES>
+template <int STAGED, int S, bool BYTES, int GEO>
 __global__ void __launch_bounds__(kMaxConstructWaves * WAVE) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
                                                          int ants_per_block, int rows_per_wave,
-                                                         int lds_bytes, int geo_mode, int step_cap) {
+                                                         int lds_bytes, int step_cap) {
   const BlockMap bm = map[blockIdx.x];
   if (bm.inst < 0) return;
   const InstDesc I = insts[bm.inst];  // by value: the fields stay in registers
@@ -1611,7 +1614,7 @@ __global__ void __launch_bounds__(kMaxConstructWaves * WAVE) construct_kernel(co
   const int first_ant = bm.ant0 + wave * rpw;
   if (wave * rpw >= ants_per_block || first_ant >= I.ants) return;  // whole wave idle
 
-  AntRows<STAGED, S, BYTES> A{};
+  AntRows<STAGED, S, BYTES, GEO> A{};
   A.n = n;
   A.k = k;
   A.kg = I.kg;
@@ -1645,7 +1648,6 @@ __global__ void __launch_bounds__(kMaxConstructWaves * WAVE) construct_kernel(co
   A.grid = grid_view(I);
   A.geo = as_global(I.geo);
   A.geo16 = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.geo16));
-  A.geo_mode = geo_mode;
   A.vis_words = vis_words;
   A.vis_wave = lds + wave * rpw * vis_words;
   A.vis_g = A.vis_wave + (A.live ? A.g : 0) * vis_words;
@@ -1673,7 +1675,7 @@ __global__ void __launch_bounds__(kMaxConstructWaves * WAVE) construct_kernel(co
   rnd = dpp_zero<0x101>(rnd);  // row_shl:1, step 1's draw to lane 0
   A.cur = start;
   A.set_row(__umul24((uint32_t)start, A.k8));
-  if (geo_mode == 2) A.glr = A.geo16[(uint32_t)start * 16u + (uint32_t)A.u];
+  if (GEO == 2) A.glr = A.geo16[(uint32_t)start * 16u + (uint32_t)A.u];
   if (A.u == 0 && A.live) A.mark(start);
   A.fallbacks = 0;
   A.row_max = (uint32_t)(n - 1) * A.k8;
@@ -2714,14 +2716,20 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
   if (waves < 1 || waves > kMaxConstructWaves) return hipErrorInvalidValue;
   const dim3 grid(blocks), block(waves * WAVE);
   const int S = max_k <= 16 ? 1 : (max_k <= 32 ? 2 : 4);
-#define HAC_LAUNCH(ST, SL, BY)                                                                 \
-  hipLaunchKernelGGL((construct_kernel<ST, SL, BY>), grid, block, lds_bytes, s, d_insts, d_map, \
-                     ants_per_block, rows_per_wave, (int)lds_bytes, (int)geo_mode, (int)step_cap)
+#define HAC_LAUNCH_G(ST, SL, BY, GM)                                                               \
+  hipLaunchKernelGGL((construct_kernel<ST, SL, BY, GM>), grid, block, lds_bytes, s, d_insts, d_map, \
+                     ants_per_block, rows_per_wave, (int)lds_bytes, (int)step_cap)
+#define HAC_LAUNCH(ST, SL, BY)                                   \
+  {                                                              \
+    if (geo_mode == 0) HAC_LAUNCH_G(ST, SL, BY, 0);              \
+    else if (geo_mode == 1) HAC_LAUNCH_G(ST, SL, BY, 1);         \
+    else HAC_LAUNCH_G(ST, SL, BY, 2);                            \
+  }
 #define HAC_LAUNCH_S(ST, BY)             \
   {                                      \
-    if (S == 1) HAC_LAUNCH(ST, 1, BY);   \
-    else if (S == 2) HAC_LAUNCH(ST, 2, BY); \
-    else HAC_LAUNCH(ST, 4, BY);          \
+    if (S == 1) HAC_LAUNCH(ST, 1, BY)    \
+    else if (S == 2) HAC_LAUNCH(ST, 2, BY) \
+    else HAC_LAUNCH(ST, 4, BY)           \
   }
   if (staged < 0 || staged > 3) return hipErrorInvalidValue;
   if (staged == 3) {
@@ -2735,6 +2743,7 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
   }
 #undef HAC_LAUNCH_S
 #undef HAC_LAUNCH
+#undef HAC_LAUNCH_G
   return hipGetLastError();
 }
 
