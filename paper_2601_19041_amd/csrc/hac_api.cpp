@@ -575,8 +575,11 @@ static void tune_cache_store() {
 // byte marks when they fit every instance of the batch
 static LaunchShape with_marks(const std::vector<HostInst>& hs, LaunchShape sh) {
   sh.bytes = 1;
-  for (auto& h : hs)
+  sh.grid = 0;
+  for (auto& h : hs) {
     if (!construct_bytes_fit(h.lay.n, h.lay.k, sh.ants_per_block, sh.rows_per_wave, sh.staged)) sh.bytes = 0;
+    if (h.lay.gside > 0) sh.grid = 1;
+  }
   return sh;
 }
 
@@ -719,7 +722,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
           cands.push_back(sh);
         }
       }
-  LaunchShape best{4, 0, kmax, 4, 0};
+  LaunchShape best = with_marks(hs, {4, 0, kmax, 4, 0});
   best.geo = geo_modes(hs, 0)[0];
   float best_ms = 1e30f;
   hipEvent_t e0, e1;
@@ -742,7 +745,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
     for (int rep = 0; rep < reps; ++rep) {
       (void)hipEventRecord(e0, s);
       (void)launch_construct(d_descs, d_map, (int32_t)map.size(), sh.ants_per_block, sh.rows_per_wave,
-                             sh.staged, sh.bytes, sh.kmax, shape_lds(hs, sh), sh.geo, s, cap);
+                             sh.staged, sh.bytes, sh.kmax, shape_lds(hs, sh), sh.geo, sh.grid, s, cap);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) return -1.0f;
       float ms = 0;
@@ -1215,7 +1218,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
     const int32_t blocks = (int32_t)map.size();
     auto one_iteration = [&]() -> hipError_t {
       hipError_t e = launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
-                                      shape.bytes, shape.kmax, lds, shape.geo, s);
+                                      shape.bytes, shape.kmax, lds, shape.geo, shape.grid, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
         e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, s);
@@ -1240,7 +1243,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
         hipEvent_t* ev = &c->events[4 * it];
         CTX_HIP(hipEventRecord(ev[0], s));
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
-                                      shape.bytes, shape.kmax, lds, shape.geo, s));
+                                      shape.bytes, shape.kmax, lds, shape.geo, shape.grid, s));
         CTX_HIP(hipEventRecord(ev[1], s));
         if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, s));
         CTX_HIP(hipEventRecord(ev[2], s));

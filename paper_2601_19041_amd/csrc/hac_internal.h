@@ -164,12 +164,14 @@ constexpr int kMaxConstructWaves = 4;
 // geo_mode: how an exhausted row consults its geometric list before a
 // scan: 0 not at all, 1 int32 lists loaded at the top of each step, 2
 // uint16 lists loaded one step ahead (every instance has geo16).
+// grid = 0 when no instance of the launch has a coordinate grid: the grid
+// search is then compiled out of the kernel (results do not depend on it).
 // step_cap < n (timing launches only): each ant stops after step_cap tour
 // positions and writes neither its length nor its checks
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
                             int32_t bytes, int32_t max_k, size_t lds_bytes, int32_t geo_mode,
-                            hipStream_t s, int32_t step_cap = INT32_MAX);
+                            int32_t grid, hipStream_t s, int32_t step_cap = INT32_MAX);
 // tours_per_inst: blocks per instance (the largest ant count among instances
 // that search every ant's tour, else 1)
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,

@@ -1303,7 +1303,7 @@ constexpr int kListScanMax = 1024;
 // to LDS as 8-byte {id, weight} entries; 2 as uint16 ids and FP32 weights
 // (six bytes per slot, for tables that do not fit as 8-byte entries); 3 as
 // in 2 but without the coordinates, which leaves room for unvisited lists.
-template <int STAGED, int S, bool BYTES, int GEO>
+template <int STAGED, int S, bool BYTES, int GEO, bool GRID>
 struct AntRows {
   int n, k, kg, u, g;
   const HAC_AS1 char* cw_g;       // the candidate table in global memory
@@ -1521,7 +1521,7 @@ struct AntRows {
       else
         vv = VisBits{vw_};
       int jj;
-      if (grid.start && (!list_wave || left > kListScanMax)) {
+      if (GRID && grid.start && (!list_wave || left > kListScanMax)) {
         const double xi = xy_lds ? xy_lds[ii].x : D.xy[2 * ii];
         const double yi = xy_lds ? xy_lds[ii].y : D.xy[2 * ii + 1];
         jj = grid_nearest(grid, n, xi, yi, vv);
@@ -1560,7 +1560,7 @@ __device__ __forceinline__ void sum_row_in_order(double& len, double d) {
   }
 }
 
-template <int STAGED, int S, bool BYTES, int GEO>
+template <int STAGED, int S, bool BYTES, int GEO, bool GRID>
 __global__ void __launch_bounds__(kMaxConstructWaves * WAVE) construct_kernel(const InstDesc* __restrict__ insts,
                                                          const BlockMap* __restrict__ map,
                                                          int ants_per_block, int rows_per_wave,
@@ -1614,7 +1614,7 @@ __global__ void __launch_bounds__(kMaxConstructWaves * WAVE) construct_kernel(co
   const int first_ant = bm.ant0 + wave * rpw;
   if (wave * rpw >= ants_per_block || first_ant >= I.ants) return;  // whole wave idle
 
-  AntRows<STAGED, S, BYTES, GEO> A{};
+  AntRows<STAGED, S, BYTES, GEO, GRID> A{};
   A.n = n;
   A.k = k;
   A.kg = I.kg;
@@ -1645,7 +1645,7 @@ __global__ void __launch_bounds__(kMaxConstructWaves * WAVE) construct_kernel(co
   }
   A.xy_lds = xy_lds;
   A.D = GDist(I);
-  A.grid = grid_view(I);
+  if (GRID) A.grid = grid_view(I);
   A.geo = as_global(I.geo);
   A.geo16 = reinterpret_cast<const HAC_AS1 uint64_t*>(as_global(I.geo16));
   A.vis_words = vis_words;
@@ -2709,21 +2709,26 @@ int32_t construct_group_lanes(int32_t max_k) { (void)max_k; return 16; }
 hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int32_t blocks,
                             int32_t ants_per_block, int32_t rows_per_wave, int32_t staged,
                             int32_t bytes, int32_t max_k, size_t lds_bytes, int32_t geo_mode,
-                            hipStream_t s, int32_t step_cap) {
+                            int32_t grid, hipStream_t s, int32_t step_cap) {
   if (geo_mode < 0 || geo_mode > 2 || step_cap < 1) return hipErrorInvalidValue;
   if (rows_per_wave < 1 || rows_per_wave > 4) return hipErrorInvalidValue;
   const int waves = (ants_per_block + rows_per_wave - 1) / rows_per_wave;
   if (waves < 1 || waves > kMaxConstructWaves) return hipErrorInvalidValue;
-  const dim3 grid(blocks), block(waves * WAVE);
+  const dim3 grid_dim(blocks), block(waves * WAVE);
   const int S = max_k <= 16 ? 1 : (max_k <= 32 ? 2 : 4);
-#define HAC_LAUNCH_G(ST, SL, BY, GM)                                                               \
-  hipLaunchKernelGGL((construct_kernel<ST, SL, BY, GM>), grid, block, lds_bytes, s, d_insts, d_map, \
+#define HAC_LAUNCH_GG(ST, SL, BY, GM, GR)                                                                  \
+  hipLaunchKernelGGL((construct_kernel<ST, SL, BY, GM, GR>), grid_dim, block, lds_bytes, s, d_insts, d_map, \
                      ants_per_block, rows_per_wave, (int)lds_bytes, (int)step_cap)
+#define HAC_LAUNCH_G(ST, SL, BY, GM)               \
+  {                                                \
+    if (grid) HAC_LAUNCH_GG(ST, SL, BY, GM, true); \
+    else HAC_LAUNCH_GG(ST, SL, BY, GM, false);     \
+  }
 #define HAC_LAUNCH(ST, SL, BY)                                   \
   {                                                              \
-    if (geo_mode == 0) HAC_LAUNCH_G(ST, SL, BY, 0);              \
-    else if (geo_mode == 1) HAC_LAUNCH_G(ST, SL, BY, 1);         \
-    else HAC_LAUNCH_G(ST, SL, BY, 2);                            \
+    if (geo_mode == 0) HAC_LAUNCH_G(ST, SL, BY, 0)               \
+    else if (geo_mode == 1) HAC_LAUNCH_G(ST, SL, BY, 1)          \
+    else HAC_LAUNCH_G(ST, SL, BY, 2)                             \
   }
 #define HAC_LAUNCH_S(ST, BY)             \
   {                                      \
@@ -2744,6 +2749,7 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
 #undef HAC_LAUNCH_S
 #undef HAC_LAUNCH
 #undef HAC_LAUNCH_G
+#undef HAC_LAUNCH_GG
   return hipGetLastError();
 }
 

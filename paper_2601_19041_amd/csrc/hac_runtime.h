@@ -74,6 +74,7 @@ struct LaunchShape {
   int32_t rows_per_wave;
   int32_t bytes;  // visited marks: one byte per node (when they fit every instance) or one bit
   int32_t geo = 1;  // geometric-list mode of the construction kernel (launch_construct)
+  int32_t grid = 0; // some instance has a coordinate grid (else the grid search is compiled out)
 };
 
 // One decode batch: everything from uploaded inputs to results.

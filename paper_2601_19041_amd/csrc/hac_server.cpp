@@ -413,7 +413,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
     for (int32_t r = 0; ok && r < rounds; ++r) {
       ok = hip_ok(S, launch_construct(d_descs, d_map, (int32_t)map.size(), shape.ants_per_block,
                                       shape.rows_per_wave, shape.staged, shape.bytes, shape.kmax, lds,
-                                      shape.geo, s), "construct");
+                                      shape.geo, shape.grid, s), "construct");
       if (ok && any_ls) ok = hip_ok(S, launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, s), "local search");
       if (ok) ok = hip_ok(S, launch_iter_end(d_descs, m, s), "iter end");
     }
