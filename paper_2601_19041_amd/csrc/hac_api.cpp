@@ -600,7 +600,7 @@ std::vector<int32_t> geo_modes(const std::vector<HostInst>& hs, int32_t staged) 
     const int m = std::atoi(f);
     if (m == 0 || m == 1 || (m == 2 && all16)) return {m};
   }
-  if (staged) return {1};
+  if (staged) return all16 ? std::vector<int32_t>{2, 1} : std::vector<int32_t>{1};
   return {0, all16 ? 2 : 1};
 }
 

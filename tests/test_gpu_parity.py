@@ -163,6 +163,21 @@ def test_bit_marks(ctx, shape, monkeypatch):
     assert ctx.stats()["byte_marks"] == 0
 
 
+@pytest.mark.parametrize("geo", ["0", "1", "2"])
+@pytest.mark.parametrize("shape", ["4,0", "8,1", "3,2,1", "4,3,2"])
+def test_geo_list_modes(ctx, shape, geo, monkeypatch):
+    """Each way an exhausted row consults its geometric list (not at all,
+    int32 lists, uint16 lists a step ahead; a kernel per mode) with the table
+    in global memory and in each LDS form.  k = 5 makes exhausted rows, list
+    hits and scans frequent."""
+    inst = wl.random_instance(160, seed=33, k=5, ants=8, iterations=12)
+    monkeypatch.setenv("HAC_SHAPE", shape)
+    monkeypatch.setenv("HAC_GEO_MODE", geo)
+    print(f"case list mode {geo} shape {shape}", flush=True)
+    _same(ctx.decode(inst), oracle.decode(inst), f"{shape}/{geo}")
+    assert ctx.stats()["geo_mode"] == int(geo)
+
+
 @pytest.mark.parametrize("k,shape", [(24, "8,0"), (24, "4,1,1"), (40, "8,1"), (40, "2,0,2"), (64, "4,0"),
                                      (24, "8,2"), (40, "3,2,1"), (64, "4,2,2"), (24, "3,3,1")])
 def test_wide_candidate_rows(ctx, k, shape, monkeypatch):
