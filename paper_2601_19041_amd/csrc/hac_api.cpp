@@ -600,7 +600,10 @@ std::vector<int32_t> geo_modes(const std::vector<HostInst>& hs, int32_t staged) 
     const int m = std::atoi(f);
     if (m == 0 || m == 1 || (m == 2 && all16)) return {m};
   }
-  if (staged) return all16 ? std::vector<int32_t>{2, 1} : std::vector<int32_t>{1};
+  // staged tables: uint16 lists a step ahead whenever every instance has them
+  // (faster over whole decodes; the tuner's first-iteration timing cannot
+  // tell the two list forms apart)
+  if (staged) return {all16 ? 2 : 1};
   return {0, all16 ? 2 : 1};
 }
 
@@ -624,7 +627,7 @@ static bool waves_ok(const LaunchShape& sh) {
   return sh.rows_per_wave >= 1 && (sh.ants_per_block + sh.rows_per_wave - 1) / sh.rows_per_wave <= kMaxConstructWaves;
 }
 
-static std::string shape_key(const std::vector<HostInst>& hs) {
+static std::string shape_key(const std::vector<HostInst>& hs, bool shared = false) {
   int32_t max_n = 0, k = 0;
   int64_t ants = 0;
   for (auto& h : hs) {
@@ -637,7 +640,7 @@ static std::string shape_key(const std::vector<HostInst>& hs) {
   int ab = 0;
   while ((1ll << ab) < ants) ab++;
   return "gfx950v2/n" + std::to_string(nb) + "/k" + std::to_string(k) + "/a" + std::to_string(ab) +
-         (hs[0].lay.coords ? "/euc" : "/mat");
+         (hs[0].lay.coords ? "/euc" : "/mat") + (shared ? "/lane" : "");
 }
 
 // A launch shape chosen without timing anything (the allocation-free path):
@@ -671,7 +674,7 @@ LaunchShape default_shape(const std::vector<HostInst>& hs) {
 }
 
 LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs, hipStream_t s,
-                       DeviceArena& scratch, bool* ok) {
+                       DeviceArena& scratch, bool* ok, bool shared) {
   *ok = true;
   const int32_t kmax = batch_max_k(hs);
   if (const char* force = std::getenv("HAC_SHAPE")) {
@@ -689,7 +692,7 @@ LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs,
       if (waves_ok(sh) && shape_fits(hs, sh)) return sh;
     }
   }
-  const std::string key = shape_key(hs);
+  const std::string key = shape_key(hs, shared);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_cache_load();

@@ -104,9 +104,11 @@ std::vector<int32_t> geo_modes(const std::vector<HostInst>& hs, int32_t staged);
 std::vector<BlockMap> build_block_map(const std::vector<HostInst>& hs, int32_t ants_per_block);
 
 // Launch-shape autotuner: picks ants-per-block and LDS staging by timing
-// the construction kernel; cached per shape class.
+// the construction kernel; cached per shape class.  shared = true for the
+// server's lanes, which run beside each other: their choices are timed and
+// cached apart from those of decodes that have the GPU to themselves.
 LaunchShape tune_shape(const std::vector<HostInst>& hs, const InstDesc* d_descs, hipStream_t s,
-                       DeviceArena& scratch, bool* ok);
+                       DeviceArena& scratch, bool* ok, bool shared = false);
 
 // Prepares instances whose inputs are already uploaded into their slots:
 // candidates, host fold, NN tour (+2-opt), range checks, initialisation.

@@ -374,7 +374,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
       if (ok) {
         // construction only reads the search state, so timing it here
         // leaves every instance's trajectory unchanged
-        shape = tune_shape(hs, d_descs, s, LN.scratch, &ok);
+        shape = tune_shape(hs, d_descs, s, LN.scratch, &ok, true);
       }
       if (ok) {
         map = build_block_map(hs, shape.ants_per_block);
