@@ -51,6 +51,7 @@ class Problem(ctypes.Structure):
         ("baseline_scope", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("kappa_fixed", ctypes.c_double),
+        ("ls_op", ctypes.c_int32),
     ]
 
 
@@ -95,6 +96,7 @@ def lib():
         L.orc_tour_length.argtypes = [P, vp]
         L.orc_tour_length.restype = ctypes.c_double
         L.orc_two_opt.argtypes = [P, vp, ctypes.c_int32, ctypes.c_double, vp]
+        L.orc_three_opt.argtypes = [P, vp, ctypes.c_int32, ctypes.c_double, vp]
         L.orc_nearest_in_lists.argtypes = [P, ctypes.c_int32, vp]
         L.orc_nearest_in_lists.restype = ctypes.c_int32
         L.orc_two_opt_directed.argtypes = [P, vp, vp, ctypes.c_int32, ctypes.c_double, vp]
@@ -136,7 +138,8 @@ class OracleProblem:
         self.val = np.ascontiguousarray(inst.heat.val, dtype=np.float32)
         prm = dict(DEFAULTS)
         prm.update(ants=inst.ants, iterations=inst.iterations, k=inst.k, k_ls=inst.k_ls,
-                   local_search=inst.local_search, rho=inst.rho, seed=inst.seed)
+                   local_search=inst.local_search, rho=inst.rho, seed=inst.seed,
+                   ls_op=getattr(inst, "ls_op", 2))
         prm.update(over)
         self.params = prm
         self.s = Problem(n=inst.n, kind=kind, symmetric=sym, coords=_ptr(self.coords),
@@ -221,6 +224,14 @@ def two_opt(inst, nl: np.ndarray, tour, min_gain: float) -> np.ndarray:
     nl = np.ascontiguousarray(nl, dtype=np.int32)
     t = np.array(tour, dtype=np.int32)
     lib().orc_two_opt(p.ref, _ptr(nl), nl.shape[1], min_gain, _ptr(t))
+    return t
+
+
+def three_opt(inst, nl: np.ndarray, tour, min_gain: float) -> np.ndarray:
+    p = OracleProblem(inst)
+    nl = np.ascontiguousarray(nl, dtype=np.int32)
+    t = np.array(tour, dtype=np.int32)
+    lib().orc_three_opt(p.ref, _ptr(nl), nl.shape[1], min_gain, _ptr(t))
     return t
 
 

@@ -536,6 +536,139 @@ void orc_two_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min
 }
 
 /* ------------------------------------------------------------------------ */
+/* Section III-D: first-improvement 3-opt on the same geometric neighbour     */
+/* lists, for symmetric instances.  Reading (the paper names the operator   */
+/* but not its move set): the search is the 2-opt's (queue in tour order,    */
+/* FIFO re-queueing of the end nodes if absent, re-examination of a, gain   */
+/* threshold min_gain) over a larger neighbourhood.  For node a, the 2-opt  */
+/* moves come first, exactly as in orc_two_opt; if none improves, the        */
+/* segment exchange, the 3-opt reconnection that keeps every segment's       */
+/* orientation:                                                             */
+/*   t1 = a, t2 = the next node after t1 in the direction (succ, then pred); */
+/*   t3 over t1's list in order, g1 = d(t1,t2) - d(t1,t3), stop at g1 <= 0;  */
+/*   t4 = the node before t3 in the direction;                              */
+/*   t5 over t4's list in order, g2 = (g1 + d(t4,t3)) - d(t4,t5), stop at    */
+/*   g2 <= 0; t5 must come after t3 in the direction, or be t1 itself;      */
+/*   t6 = the node before t5 in the direction;                              */
+/*   gain = ((d12 + d43) + d65) - ((d13 + d45) + d62).                       */
+/* Walking from t1 in the direction the tour reads t1 | t2..t4 | t3..t6 |    */
+/* t5..; the move makes it t1 | t3..t6 | t2..t4 | t5.., replacing (t1,t2),   */
+/* (t4,t3), (t6,t5) with (t1,t3), (t6,t2), (t4,t5).  In the array the two    */
+/* segments trade places and keep their order (nothing is reversed).  The   */
+/* first move with gain > min_gain is applied and its end nodes t1 .. t6    */
+/* re-queued in that order if absent.  A run applies at most 64 n moves, as  */
+/* the directed 2-opt: every move shortens the tour by more than the        */
+/* threshold, so the bound only guards against a broken gain.               */
+/* ------------------------------------------------------------------------ */
+void orc_three_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min_gain,
+                   int32_t* tour) {
+  int32_t n = p->n;
+  if (n < 5 || kk < 1) return;
+  int32_t* pos = (int32_t*)malloc(4 * (size_t)n);
+  int32_t* queue = (int32_t*)malloc(4 * (size_t)n);
+  int32_t* tmp = (int32_t*)malloc(4 * (size_t)n);
+  uint8_t* inq = (uint8_t*)malloc((size_t)n);
+  for (int32_t s = 0; s < n; s++) { pos[tour[s]] = s; queue[s] = tour[s]; inq[s] = 1; }
+  int32_t head = 0, count = n;
+  int64_t moves = 0, max_moves = 64 * (int64_t)n;
+#define SUCC(x) tour[(pos[x] + 1) % n]
+#define PRED(x) tour[(pos[x] - 1 + n) % n]
+#define PUSH(x)                          \
+  do {                                   \
+    if (!inq[x]) {                       \
+      queue[(head + count) % n] = (x);   \
+      count++;                           \
+      inq[x] = 1;                        \
+    }                                    \
+  } while (0)
+  while (count > 0 && moves < max_moves) {
+    int32_t a = queue[head];
+    head = (head + 1) % n;
+    count--;
+    inq[a] = 0;
+    int improved = 1;
+    while (improved && moves < max_moves) {
+      improved = 0;
+      /* the 2-opt moves of a, as in orc_two_opt */
+      for (int dir = 0; dir < 2 && !improved; dir++) {
+        int32_t b = dir == 0 ? SUCC(a) : PRED(a);
+        double dab = dist(p, a, b);
+        for (int32_t q = 0; q < kk; q++) {
+          int32_t c = nl[(int64_t)a * kk + q];
+          double dac = dist(p, a, c);
+          if (dab - dac <= 0.0) break;
+          int32_t e = dir == 0 ? SUCC(c) : PRED(c);
+          if (e == a || c == b) continue;
+          double gain = (dab + dist(p, c, e)) - (dac + dist(p, b, e));
+          if (gain > min_gain) {
+            if (dir == 0) reverse_path(n, tour, pos, b, c);
+            else reverse_path(n, tour, pos, c, b);
+            PUSH(a);
+            PUSH(b);
+            PUSH(c);
+            PUSH(e);
+            improved = 1;
+            moves++;
+            break;
+          }
+        }
+      }
+      if (improved) continue;
+      /* the segment exchanges of a */
+      for (int dir = 0; dir < 2 && !improved; dir++) {
+        int32_t t1 = a, p1 = pos[a];
+        /* steps from t1 in the direction */
+#define OFF(x) (dir == 0 ? (pos[x] - p1 + n) % n : (p1 - pos[x] + n) % n)
+        int32_t t2 = dir == 0 ? SUCC(t1) : PRED(t1);
+        double d12 = dist(p, t1, t2);
+        for (int32_t q = 0; q < kk && !improved; q++) {
+          int32_t t3 = nl[(int64_t)t1 * kk + q];
+          double d13 = dist(p, t1, t3);
+          double g1 = d12 - d13;
+          if (g1 <= 0.0) break;
+          int32_t r3 = OFF(t3);
+          if (r3 < 2) continue;
+          int32_t t4 = dir == 0 ? PRED(t3) : SUCC(t3);
+          double d43 = dist(p, t4, t3);
+          for (int32_t q5 = 0; q5 < kk; q5++) {
+            int32_t t5 = nl[(int64_t)t4 * kk + q5];
+            double d45 = dist(p, t4, t5);
+            double g2 = (g1 + d43) - d45;
+            if (g2 <= 0.0) break;
+            int32_t r5 = OFF(t5);
+            if (!(r5 > r3 || r5 == 0)) continue;
+            int32_t t6 = dir == 0 ? PRED(t5) : SUCC(t5);
+            double gain = ((d12 + d43) + dist(p, t6, t5)) - ((d13 + d45) + dist(p, t6, t2));
+            if (gain > min_gain) {
+              /* walking from t1: the segment t2..t4 (r3 - 1 nodes), then
+                 t3..t6 (up to the step before t5); afterwards t3..t6 comes
+                 first, then t2..t4, both in their own order */
+              int32_t len1 = r3 - 1, end = r5 == 0 ? n - 1 : r5 - 1, len2 = end - r3 + 1, w = 0;
+              for (int32_t s = 0; s < len2; s++) tmp[w++] = tour[(dir == 0 ? p1 + r3 + s : p1 - r3 - s + 2 * n) % n];
+              for (int32_t s = 0; s < len1; s++) tmp[w++] = tour[(dir == 0 ? p1 + 1 + s : p1 - 1 - s + 2 * n) % n];
+              for (int32_t s = 0; s < w; s++) {
+                int32_t at = (dir == 0 ? p1 + 1 + s : p1 - 1 - s + 2 * n) % n;
+                tour[at] = tmp[s];
+                pos[tmp[s]] = at;
+              }
+              PUSH(t1); PUSH(t2); PUSH(t3); PUSH(t4); PUSH(t5); PUSH(t6);
+              improved = 1;
+              moves++;
+              break;
+            }
+          }
+        }
+#undef OFF
+      }
+    }
+  }
+#undef SUCC
+#undef PRED
+#undef PUSH
+  free(pos); free(queue); free(tmp); free(inq);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Section III-D for the ATSP: directed 2-opt.  Reading of "a directed 2-opt */
 /* based on the Jonker-Volgenant reduction": that reduction makes each city  */
 /* a pair of nodes joined by an edge every tour keeps; a 2-opt move on the   */
@@ -733,6 +866,10 @@ static int valid_problem(const orc_problem* p) {
   if (!(p->rho > 0.0 && p->rho < 1.0) || !(p->p_best > 0.0 && p->p_best < 1.0)) return 0;
   if (p->alpha != 1.0) return 0;
   if (p->local_search < 0 || p->local_search > 2) return 0;
+  /* the local-search operator: 0 or 2 the 2-opt, 3 the 3-opt (symmetric
+     instances only; the paper's ATSP search is the directed 2-opt) */
+  if (p->ls_op != 0 && p->ls_op != 2 && p->ls_op != 3) return 0;
+  if (p->ls_op == 3 && !is_sym(p)) return 0;
   if (!isfinite(p->kappa_fixed)) return 0;
   if (p->row_ptr[0] != 0) return 0;
   for (int32_t i = 0; i < p->n; i++) {
@@ -851,7 +988,8 @@ int32_t orc_decode(const orc_problem* p, int32_t* tour_out, double* len_out, orc
   /* Section III-D: 2-opt for symmetric instances, directed 2-opt for the ATSP */
 #define LOCAL_SEARCH(t)                                                  \
   do {                                                                   \
-    if (sym) orc_two_opt(p, nl, k_ls, min_gain, (t));                    \
+    if (sym && p->ls_op == 3) orc_three_opt(p, nl, k_ls, min_gain, (t)); \
+    else if (sym) orc_two_opt(p, nl, k_ls, min_gain, (t));               \
     else orc_two_opt_directed(p, nl, nl_in, k_ls, min_gain, (t));        \
   } while (0)
 

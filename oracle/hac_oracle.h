@@ -37,6 +37,9 @@ typedef struct {
   /* kappa_fixed < 0: kappa from eq. (14); >= 0: kappa set to this value
      (Sec. IV-E ablation "fixed kappa = 1") */
   double kappa_fixed;
+  /* local-search operator (Section III-D): 0 or 2 the 2-opt, 3 the 3-opt
+     (symmetric instances only) */
+  int32_t ls_op;
 } orc_problem;
 
 /* optional outputs; any pointer may be NULL */
@@ -90,6 +93,10 @@ double orc_tour_length(const orc_problem* p, const int32_t* tour);
 /* First-improvement neighbour-list 2-opt with a don't-look queue. */
 void orc_two_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min_gain,
                  int32_t* tour);
+/* First-improvement neighbour-list 3-opt (the 2-opt moves, then segment
+ * exchanges) with the same queue, for symmetric instances. */
+void orc_three_opt(const orc_problem* p, const int32_t* nl, int32_t kk, double min_gain,
+                   int32_t* tour);
 
 /* Incoming neighbour lists of size kk: for node i the nodes j with the
  * smallest d(j, i) (the directed 2-opt's predecessor side) */

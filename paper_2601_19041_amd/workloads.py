@@ -87,6 +87,7 @@ class Instance:
     rho: float = 0.2
     seed: int = 1
     name: str = ""
+    ls_op: int = 2  # local-search operator: 2 the 2-opt, 3 the 3-opt (symmetric instances)
 
 
 def uniform_coords(n: int, rng: np.random.Generator) -> np.ndarray:

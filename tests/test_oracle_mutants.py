@@ -4,7 +4,7 @@ Each mutant plants one plausible mistake in a copy of oracle/hac_oracle.c:
 a dropped term, a wrong sign or operator, an off-by-one index, a flipped
 comparison or tie rule.  The copy is built with the oracle's own gcc flags,
 and the pin tests (tests/test_oracle_pins.py, tests/test_oracle_reduction.py,
-tests/test_oracle_elite.py, tests/test_oracle_directed.py) run against it in a subprocess (HAC_ORACLE_LIB).  At least one pin must fail
+tests/test_oracle_elite.py, tests/test_oracle_directed.py, tests/test_oracle_3opt.py) run against it in a subprocess (HAC_ORACLE_LIB).  At least one pin must fail
 for every mutant.  The oracle source itself is never changed; every mutant
 keeps the oracle terminating.
 """
@@ -152,6 +152,19 @@ MUTANTS = [
      "double dac = dir == 0 ? dist(p, a, c) : dist(p, c, a);", "double dac = dist(p, a, c);"),
     ("incoming lists ordered by outgoing distance",
      "if (j != i) topk_offer(&t, dist(p, j, i), j);", "if (j != i) topk_offer(&t, dist(p, i, j), j);"),
+    ("3-opt: t4 taken after t3 instead of before",
+     "int32_t t4 = dir == 0 ? PRED(t3) : SUCC(t3);", "int32_t t4 = dir == 0 ? SUCC(t3) : PRED(t3);"),
+    ("3-opt: second stop rule without d(t4,t3)",
+     "double g2 = (g1 + d43) - d45;", "double g2 = g1 - d45;"),
+    ("3-opt: closing edge priced to t1 instead of t2",
+     "((d13 + d45) + dist(p, t6, t2))", "((d13 + d45) + dist(p, t6, t1))"),
+    ("3-opt: exchange end nodes other than t1 not re-queued",
+     "PUSH(t1); PUSH(t2); PUSH(t3); PUSH(t4); PUSH(t5); PUSH(t6);", "PUSH(t1);"),
+    ("3-opt: segment exchanges never tried",
+     "      /* the segment exchanges of a */\n      for (int dir = 0; dir < 2 && !improved; dir++) {",
+     "      /* the segment exchanges of a */\n      for (int dir = 0; dir < 0 && !improved; dir++) {"),
+    ("3-opt: t5 = t1 refused",
+     "if (!(r5 > r3 || r5 == 0)) continue;", "if (!(r5 > r3)) continue;"),
 ]
 
 # Mutants of the elite schedule and the restart (Section III-B).  Each must
@@ -191,7 +204,7 @@ def _build(tmp, x, old, new):
 
 
 PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_reduction.py", "tests/test_oracle_elite.py",
-             "tests/test_oracle_directed.py"]
+             "tests/test_oracle_directed.py", "tests/test_oracle_3opt.py"]
 
 
 def _pins_fail(so, files=tuple(PIN_FILES)):
