@@ -108,6 +108,10 @@ typedef struct hac_params {
   double kappa_fixed;     /* < 0: kappa from eq. (14); >= 0: kappa is this */
                           /* value (the fixed-scale ablation of Sec. IV-E  */
                           /* uses 1; 0 gives plain MMAS weights)           */
+  int32_t ls_op;          /* local-search operator (Sec. III-D): 2 (or 0)  */
+                          /* the 2-opt, 3 the 3-opt (the 2-opt moves, then */
+                          /* segment exchanges); symmetric instances only, */
+                          /* HAC_EUNSUPPORTED on an asymmetric matrix      */
 } hac_params;
 
 typedef struct hac_ctx hac_ctx;

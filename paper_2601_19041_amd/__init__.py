@@ -58,6 +58,7 @@ class hac_params(ctypes.Structure):
         ("restart_stall", ctypes.c_int32), ("ugb_max", ctypes.c_int32),
         ("baseline_scope", ctypes.c_int32),
         ("kappa_fixed", ctypes.c_double),
+        ("ls_op", ctypes.c_int32),
     ]
 
 
@@ -207,7 +208,7 @@ class Marshalled:
                              self.col.ctypes.data if len(self.col) else None,
                              self.val.ctypes.data if len(self.val) else None)
         over = dict(ants=inst.ants, iterations=inst.iterations, k=inst.k, k_ls=inst.k_ls,
-                    local_search=inst.local_search, rho=inst.rho)
+                    local_search=inst.local_search, rho=inst.rho, ls_op=getattr(inst, "ls_op", 2))
         over.update(param_over)
         self.s_params = params_default(**over)
         self.seed = int(param_over.get("seed", inst.seed))

@@ -126,6 +126,9 @@ hac_status validate(const hac_instance* inst, const hac_csr* csr, const hac_para
   if (p->alpha != 1.0) return fail(HAC_EUNSUPPORTED, "only alpha = 1 is supported");
   if (p->k > HAC_MAX_K) return fail(HAC_EUNSUPPORTED, "k above HAC_MAX_K");
   if (p->local_search && p->k_ls > HAC_MAX_KLS) return fail(HAC_EUNSUPPORTED, "k_ls above HAC_MAX_KLS");
+  if (p->ls_op != 0 && p->ls_op != 2 && p->ls_op != 3) return fail(HAC_EINVAL, "ls_op is not 2 or 3");
+  if (p->local_search && p->ls_op == 3 && inst->kind == HAC_MATRIX && !inst->symmetric)
+    return fail(HAC_EUNSUPPORTED, "the 3-opt is for symmetric instances (the ATSP takes the directed 2-opt)");
   return HAC_OK;
 }
 
@@ -144,6 +147,7 @@ Layout make_layout(const hac_instance* inst, const hac_csr* csr, const hac_param
   L.ls = p->local_search != 0;
   L.directed = L.ls && inst->kind == HAC_MATRIX && !inst->symmetric;
   L.ls_tours = p->local_search == 2 ? p->ants : 1;
+  L.three_opt = L.ls && !L.directed && p->ls_op == 3;
   L.nnz = csr->nnz;
   L.gside = (L.coords && L.n >= kGridMinN) ? grid_side(L.n) : 0;
   return L;
@@ -231,6 +235,7 @@ void fill_desc_scalars(HostInst& h) {
   d.ants = p.ants;
   d.iterations = p.iterations;
   d.local_search = p.local_search;
+  d.ls_op = L.three_opt ? 3 : 2;
   d.bf_period = p.bf_period;
   d.restart_stall = p.restart_stall;
   d.ugb_max = p.ugb_max;
@@ -451,14 +456,15 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   HAC_HIP(launch_grid(d_descs, count, s));
   HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
   bool any_ls = false;
-  int32_t all_coords = 1, max_n_dir = 0, max_kls_dir = 0, max_n_sym = 0;  // largest directed / symmetric
+  int32_t all_coords = 1, max_n_dir = 0, max_kls_dir = 0, max_n_sym = 0, max_n3 = 0;  // largest directed / symmetric
   for (auto& h : hs) {
     any_ls |= h.p.local_search != 0;
     if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n), max_kls_dir = std::max(max_kls_dir, h.lay.kls);
+    else if (h.lay.three_opt) max_n3 = std::max(max_n3, h.lay.n);
     else if (h.p.local_search) max_n_sym = std::max(max_n_sym, h.lay.n);
-    if (h.p.local_search && !h.lay.directed && !h.lay.coords) all_coords = 0;
+    if (h.p.local_search && !h.lay.directed && !h.lay.three_opt && !h.lay.coords) all_coords = 0;
   }
-  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n_sym, all_coords, max_n_dir, max_kls_dir, s));
+  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n_sym, all_coords, max_n_dir, max_kls_dir, max_n3, s));
   std::vector<State> sts(count);
   if (stage) {
     // after the weights' scatter on the same stream: the staging arena is reused
@@ -851,6 +857,7 @@ void hac_params_default(hac_params* p) {
   p->k = 20;
   p->k_ls = 20;
   p->local_search = 0;
+  p->ls_op = 2;
   p->alpha = 1.0;
   p->beta = 2.0;
   p->rho = 0.2;
@@ -1179,14 +1186,15 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   if (m > 0) {
     bool any_ls = false;
     // max_n: the largest symmetric instance with 2-opt (0: none); max_n_dir: ATSP
-    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0, max_kls_dir = 0;
+    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0, max_kls_dir = 0, max_n3 = 0;
     for (auto& h : hs) {
       any_ls |= h.p.local_search != 0;
       if (h.p.local_search == 2) ls_tours = std::max(ls_tours, h.p.ants);
       max_iter = std::max(max_iter, h.p.iterations);
       if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n), max_kls_dir = std::max(max_kls_dir, h.lay.kls);
+      else if (h.lay.three_opt) max_n3 = std::max(max_n3, h.lay.n);
       else if (h.p.local_search) max_n = std::max(max_n, h.lay.n);
-      if (h.p.local_search && !h.lay.directed && !h.lay.coords) all_coords = 0;
+      if (h.p.local_search && !h.lay.directed && !h.lay.three_opt && !h.lay.coords) all_coords = 0;
     }
     LaunchShape shape{4, 0, 16, 4, 0};
     if (noalloc) {
@@ -1224,7 +1232,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
                                       shape.bytes, shape.kmax, lds, shape.geo, shape.grid, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
-        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, s);
+        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, max_n3, s);
         if (e != hipSuccess) return e;
       }
       return launch_iter_end(d_descs, m, s);
@@ -1248,7 +1256,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
                                       shape.bytes, shape.kmax, lds, shape.geo, shape.grid, s));
         CTX_HIP(hipEventRecord(ev[1], s));
-        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, s));
+        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, max_n3, s));
         CTX_HIP(hipEventRecord(ev[2], s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
         CTX_HIP(hipEventRecord(ev[3], s));

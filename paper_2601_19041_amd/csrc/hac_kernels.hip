@@ -981,7 +981,7 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
 template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) two_opt_nn_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
-  if (!D.local_search || !D.sym) return;  // the ATSP takes the directed 2-opt
+  if (!D.local_search || !D.sym || D.ls_op == 3) return;  // the ATSP takes the directed 2-opt
   two_opt_tour<MODE>(D, D.nn_tour, D.st->min_gain, D.ls_work);
   if (threadIdx.x < WAVE) {
     const double len = tour_length_wave(D, D.nn_tour);
@@ -1766,7 +1766,7 @@ __device__ void iteration_best_wave(const InstDesc& D, int& ib, double& lib) {
 template <int MODE>
 __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
-  if (!D.local_search || !D.sym || D.st->t > D.iterations || D.st->err) return;
+  if (!D.local_search || !D.sym || D.ls_op == 3 || D.st->t > D.iterations || D.st->err) return;
   const int n = D.n;
   if (D.local_search == 2) {
     for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
@@ -1801,6 +1801,269 @@ __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const Ins
       D.st->ib = ib;
       D.st->l_ib = len;
     }
+  }
+}
+
+// ------------------------------------------------------------------------
+// 3-opt for symmetric instances (Section III-D).  The search is the
+// 2-opt's over a larger neighbourhood: for node a its 2-opt moves come
+// first (ls_eval, in the 2-opt's order); if none improves, its segment
+// exchanges.  With t2 the next node after t1 = a in the direction (the
+// successor side, then the predecessor side), t3 runs over a's list while
+// g1 = d(t1,t2) - d(t1,t3) > 0, t4 is the node before t3, t5 runs over
+// t4's list while g2 = (g1 + d(t4,t3)) - d(t4,t5) > 0 and must come after
+// t3 or be t1, and t6 is the node before t5; the move replaces (t1,t2),
+// (t4,t3), (t6,t5) with (t1,t3), (t6,t2), (t4,t5), so the segments t2..t4
+// and t3..t6 trade places, each keeping its order.  The first move whose
+// gain ((d12 + d43) + d65) - ((d13 + d45) + d62) exceeds the threshold is
+// applied, its end nodes t1 .. t6 are queued in that order if absent, and
+// a is examined again; a search applies at most 64 n moves.
+//
+// One wave per tour examines one node at a time: for each t3 in list order,
+// lanes 0..31 take t4's list entries on the successor side and lanes
+// 32..63 on the predecessor side, so that the first improving entry of a
+// side is one ballot away; the successor side's first move anywhere in
+// t3's order comes before any predecessor-side move.
+// ------------------------------------------------------------------------
+struct Ls3Move {
+  int imp, dir, t1, t2, t3, t4, t5, t6, r3, end;  // end: steps from t1 to t6
+};
+
+template <class IP>
+__device__ Ls3Move ls3_eval(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls, int n, IP tour,
+                            IP pos, int a, double min_gain) {
+  const int lane = lane_id();
+  const int dir = lane >= 32 ? 1 : 0;
+  const int q5 = lane & 31;
+  const bool in5 = q5 < kls;
+  const int p1 = pos[a];
+  const int t2 = dir ? tour[p1 == 0 ? n - 1 : p1 - 1] : tour[p1 + 1 == n ? 0 : p1 + 1];
+  const double d12 = G.len(a, t2);
+  bool s_live = true, p_live = true, p_found = false;
+  Ls3Move pm{0, 1, a, 0, 0, 0, 0, 0, 0, 0};
+  for (int q = 0; q < kls && (s_live || p_live); ++q) {
+    const int t3 = geo[(int64_t)a * kg + q];
+    const double d13 = G.len(a, t3);
+    const double g1 = d12 - d13;
+    // a side stops at the first t3 that cannot gain
+    const uint64_t gm = __builtin_amdgcn_ballot_w64(g1 > 0.0);
+    s_live = s_live && (gm & 1ull);
+    p_live = p_live && ((gm >> 32) & 1ull);
+    const bool live = dir ? p_live : s_live;
+    const int r3 = dir ? (p1 - pos[t3] + n) % n : (pos[t3] - p1 + n) % n;
+    const bool use3 = live && r3 >= 2;
+    int t4 = 0, t5 = 0, t6 = 0, r5 = 0;
+    double d43 = 0.0, d45 = 0.0, g2 = 0.0;
+    if (use3) {
+      const int p3 = pos[t3];
+      t4 = dir ? tour[p3 + 1 == n ? 0 : p3 + 1] : tour[p3 == 0 ? n - 1 : p3 - 1];
+      d43 = G.len(t4, t3);
+      t5 = geo[(int64_t)t4 * kg + min(q5, kls - 1)];
+      d45 = G.len(t4, t5);
+      g2 = (g1 + d43) - d45;
+      r5 = dir ? (p1 - pos[t5] + n) % n : (pos[t5] - p1 + n) % n;
+    }
+    // t4's list stops at the first entry that cannot gain
+    const uint64_t stop = __builtin_amdgcn_ballot_w64(use3 && in5 && !(g2 > 0.0));
+    const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
+    const int lim = dir ? (stop_p ? (int)__builtin_ctzll(stop_p) : 32) : (stop_s ? (int)__builtin_ctzll(stop_s) : 32);
+    const bool cand = use3 && in5 && q5 < lim && (r5 > r3 || r5 == 0);
+    bool imp = false;
+    double gain = 0.0;
+    if (cand) {
+      const int p5 = pos[t5];
+      t6 = dir ? tour[p5 + 1 == n ? 0 : p5 + 1] : tour[p5 == 0 ? n - 1 : p5 - 1];
+      gain = ((d12 + d43) + G.len(t6, t5)) - ((d13 + d45) + G.len(t6, t2));
+      imp = gain > min_gain;
+    }
+    const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
+    const uint64_t ms = mi & 0xffffffffull, mp = mi >> 32;
+    if (ms) {
+      const int l = (int)__builtin_ctzll(ms);
+      Ls3Move m{1, 0, a, rd_lane(t2, l), t3, rd_lane(t4, l), rd_lane(t5, l), rd_lane(t6, l), rd_lane(r3, l), 0};
+      m.end = (rd_lane(r5, l) == 0 ? n : rd_lane(r5, l)) - 1;
+      return m;
+    }
+    if (mp && !p_found) {
+      const int l = 32 + (int)__builtin_ctzll(mp);
+      pm = Ls3Move{1, 1, a, rd_lane(t2, l), t3, rd_lane(t4, l), rd_lane(t5, l), rd_lane(t6, l), rd_lane(r3, l), 0};
+      pm.end = (rd_lane(r5, l) == 0 ? n : rd_lane(r5, l)) - 1;
+      p_found = true;
+      p_live = false;
+    }
+  }
+  if (p_found) return pm;
+  return Ls3Move{0, 0, a, 0, 0, 0, 0, 0, 0, 0};
+}
+
+// reverse the len tour positions from i on (cyclic), exactly these (no
+// complement); block-wide, ends with a barrier
+template <class IP>
+__device__ __forceinline__ void ls_reverse_span(int n, IP tour, IP pos, int i, int len) {
+  for (int s = threadIdx.x; s < len / 2; s += blockDim.x) {
+    int pi = i + s;
+    if (pi >= n) pi -= n;
+    int pj = i + len - 1 - s;
+    if (pj >= n) pj -= n;
+    const int ti = tour[pi], tj = tour[pj];
+    tour[pi] = tj;
+    tour[pj] = ti;
+    pos[tj] = pi;
+    pos[ti] = pj;
+  }
+  __syncthreads();
+}
+
+// one block (of one wave) per tour; tour, pos, queue and the flags in LDS
+// or global memory
+template <class IP, class BP>
+__device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain) {
+  const int n = D.n, kls = D.kls, kg = D.kg;
+  if (n < 5 || kls < 1) return;
+  const GDist G(D);
+  const HAC_AS1 int32_t* geo = as_global(D.geo);
+  for (int s = threadIdx.x; s < n; s += blockDim.x) {
+    const int v = tour[s];
+    pos[v] = s;
+    queue[s] = v;
+    inq[v] = 1;
+  }
+  __syncthreads();
+  // the queue is kept by every lane alike: each writes the same values, so
+  // a lane always reads its own last write
+  int head = 0, count = n;
+  auto push = [&](int x) {
+    if (!inq[x]) {
+      int slot = head + count;
+      if (slot >= n) slot -= n;
+      queue[slot] = x;
+      inq[x] = 1;
+      ++count;
+    }
+  };
+  const int64_t max_moves = 64 * (int64_t)n;
+  int64_t moves = 0;
+  while (count > 0 && moves < max_moves) {
+    const int a = queue[head];
+    head = head + 1 == n ? 0 : head + 1;
+    --count;
+    inq[a] = 0;
+    bool improved = true;
+    while (improved && moves < max_moves) {
+      improved = false;
+      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, a, min_gain);
+      if (m.imp) {
+        const int ri = pos[m.dir == 0 ? m.b : m.c], rj = pos[m.dir == 0 ? m.c : m.b];
+        __syncthreads();  // every lane has its positions before any changes
+        ls_reverse(n, tour, pos, ri, rj);
+        push(a);
+        push(m.b);
+        push(m.c);
+        push(m.e);
+        improved = true;
+        ++moves;
+        continue;
+      }
+      const Ls3Move x = ls3_eval(G, geo, kg, kls, n, tour, pos, a, min_gain);
+      if (x.imp) {
+        // the segments t2..t4 (r3 - 1 nodes) and t3..t6 (end - r3 + 1) trade
+        // places: reversing both together and then each gives that
+        const int p1 = pos[a];
+        const int l1 = x.r3 - 1, l2 = x.end - x.r3 + 1;
+        __syncthreads();
+        int st = x.dir == 0 ? p1 + 1 : p1 - x.end;
+        if (st >= n) st -= n;
+        if (st < 0) st += n;
+        const int first = x.dir == 0 ? l2 : l1;  // the segment that ends up first
+        ls_reverse_span(n, tour, pos, st, x.end);
+        ls_reverse_span(n, tour, pos, st, first);
+        int st2 = st + first;
+        if (st2 >= n) st2 -= n;
+        ls_reverse_span(n, tour, pos, st2, x.end - first);
+        push(x.t1);
+        push(x.t2);
+        push(x.t3);
+        push(x.t4);
+        push(x.t5);
+        push(x.t6);
+        improved = true;
+        ++moves;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// working arrays: MODE 1 int32 tour, positions and queue and byte flags in
+// LDS (13 bytes per node), MODE 0 the tour in place and the rest in the
+// tour's work area
+template <int MODE>
+__device__ __forceinline__ void three_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain,
+                                               int32_t* work) {
+  extern __shared__ int32_t ls_lds[];
+  const int n = D.n;
+  if constexpr (MODE == 1) {
+    int32_t* tour = ls_lds;
+    int32_t* pos = tour + n;
+    int32_t* queue = pos + n;
+    uint8_t* inq = reinterpret_cast<uint8_t*>(queue + n);
+    for (int s = threadIdx.x; s < n; s += blockDim.x) tour[s] = tour_g[s];
+    __syncthreads();
+    three_opt_block(D, tour, pos, queue, inq, min_gain);
+    for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
+  } else {
+    HAC_AS1 int32_t* tour = as_global(tour_g);
+    HAC_AS1 int32_t* pos = as_global(work);
+    HAC_AS1 int32_t* queue = pos + n;
+    HAC_AS1 uint8_t* inq = reinterpret_cast<HAC_AS1 uint8_t*>(queue + n);
+    three_opt_block(D, tour, pos, queue, inq, min_gain);
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(WAVE) three_opt_nn_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.x];
+  if (!D.local_search || !D.sym || D.ls_op != 3) return;
+  three_opt_tour<MODE>(D, D.nn_tour, D.st->min_gain, D.ls_work);
+  const double len = tour_length_wave(D, D.nn_tour);
+  if (threadIdx.x == 0) {
+    D.st->l_gb = len;
+    D.st->l_ib = len;
+  }
+}
+
+// local_search = 1: block (i, 0) improves a copy of the iteration best;
+// local_search = 2: block (i, y) improves ant tours y, y + gridDim.y, ...
+template <int MODE>
+__global__ void __launch_bounds__(WAVE) three_opt_kernel(const InstDesc* insts) {
+  const InstDesc& D = insts[blockIdx.x];
+  if (!D.local_search || !D.sym || D.ls_op != 3 || D.st->t > D.iterations || D.st->err) return;
+  const int n = D.n;
+  if (D.local_search == 2) {
+    for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
+      int32_t* tour = D.tours + (int64_t)a * n;
+      three_opt_tour<MODE>(D, tour, D.st->min_gain, D.ls_work + (int64_t)a * 3 * n);
+      const double len = tour_length_wave(D, tour);
+      if (threadIdx.x == 0) D.lens[a] = len;
+      __syncthreads();
+    }
+    return;
+  }
+  if (blockIdx.y != 0) return;
+  int ib;
+  double lib;
+  iteration_best_wave(D, ib, lib);
+  const int32_t* src = D.tours + (int64_t)ib * n;
+  for (int s = threadIdx.x; s < n; s += blockDim.x) D.t_ib[s] = src[s];
+  __threadfence_block();
+  __syncthreads();
+  three_opt_tour<MODE>(D, D.t_ib, D.st->min_gain, D.ls_work);
+  const double len = tour_length_wave(D, D.t_ib);
+  if (threadIdx.x == 0) {
+    D.st->ib = ib;
+    D.st->l_ib = len;
   }
 }
 
@@ -2555,8 +2818,32 @@ static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_
   return hipGetLastError();
 }
 
+// the 3-opt: one wave per tour, the working arrays in LDS when they fit
+static hipError_t launch_three_opt(const InstDesc* d_insts, int32_t count, int32_t max_n3, int32_t tpi, bool nn,
+                                   hipStream_t s) {
+  const int mode = ls_mode(max_n3, 0);
+  const size_t lds = mode == 1 ? ls_lds_need(max_n3, 1) : 0;
+  const dim3 grid(count, nn ? 1 : std::max(tpi, 1)), block(WAVE);
+  if (nn) {
+    if (mode == 1)
+      hipLaunchKernelGGL(three_opt_nn_kernel<1>, grid, block, lds, s, d_insts);
+    else
+      hipLaunchKernelGGL(three_opt_nn_kernel<0>, grid, block, 0, s, d_insts);
+  } else {
+    if (mode == 1)
+      hipLaunchKernelGGL(three_opt_kernel<1>, grid, block, lds, s, d_insts);
+    else
+      hipLaunchKernelGGL(three_opt_kernel<0>, grid, block, 0, s, d_insts);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
-                             int32_t max_n_dir, int32_t max_kls_dir, hipStream_t s) {
+                             int32_t max_n_dir, int32_t max_kls_dir, int32_t max_n3, hipStream_t s) {
+  if (max_n3 > 0) {
+    const hipError_t e = launch_three_opt(d_insts, count, max_n3, 1, true, s);
+    if (e != hipSuccess) return e;
+  }
   if (max_n_dir > 0) {
     const int waves = 4;
     hipLaunchKernelGGL(in_lists_kernel, dim3((max_n_dir + waves - 1) / waves, count), dim3(waves * WAVE), 0, s,
@@ -2771,7 +3058,11 @@ static int ls_block_waves(int32_t max_n, int mode, int64_t tours) {
 
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                int32_t all_coords, int32_t tours_per_inst, int32_t max_n_dir,
-                               int32_t max_kls_dir, hipStream_t s) {
+                               int32_t max_kls_dir, int32_t max_n3, hipStream_t s) {
+  if (max_n3 > 0) {
+    const hipError_t e = launch_three_opt(d_insts, count, max_n3, tours_per_inst, false, s);
+    if (e != hipSuccess) return e;
+  }
   if (max_n_dir > 0) {
     const hipError_t e = launch_directed(d_insts, count, max_n_dir, max_kls_dir, tours_per_inst, false, s);
     if (e != hipSuccess) return e;

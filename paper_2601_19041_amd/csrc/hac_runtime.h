@@ -35,6 +35,7 @@ struct Layout {
   bool coords, ls;
   bool directed;     // the ATSP with local search: directed 2-opt (incoming lists, larger work area)
   int32_t ls_tours;  // tours with their own 2-opt work area (ants when every ant is searched)
+  bool three_opt = false;  // symmetric local search with the 3-opt
   int32_t gside;  // coordinate grid cells per side (0: none)
   int64_t nnz;
   size_t bytes() const;

@@ -79,6 +79,11 @@ def test_validate_host_only(hac):
     at = wl.random_instance(20, seed=4, kind="matrix", symmetric=False)
     assert hac.validate(at) == hac.HAC_OK
     assert hac.validate(at, local_search=1) == hac.HAC_OK  # the directed 2-opt
+    # the 3-opt is for symmetric instances; other operators are invalid
+    assert hac.validate(at, local_search=1, ls_op=3) == hac.HAC_EUNSUPPORTED
+    assert hac.validate(at, ls_op=3) == hac.HAC_OK  # no local search, nothing to refuse
+    assert hac.validate(inst, local_search=2, ls_op=3) == hac.HAC_OK
+    assert hac.validate(inst, local_search=1, ls_op=4) == hac.HAC_EINVAL
     sm = wl.random_instance(20, seed=4, kind="matrix", symmetric=True)
     sm.dist = sm.dist.copy()
     sm.dist[1, 2] += 1e-3
