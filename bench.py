@@ -33,6 +33,7 @@ Reported on one JSON line:
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -252,7 +253,8 @@ def kernel_lines(insts, st, traffic_key=None):
     lines = {"construct": roofline(insts, st["construct_ms"], st["construct_launches"], traffic_key),
              "update": kernel_line("iter_end_kernel", update_bytes(insts), st["update_ms"], st["update_launches"])}
     if st["local_search_launches"]:
-        lines["two_opt"] = kernel_line("local_search_kernel", two_opt_bytes(insts), st["local_search_ms"],
+        name = "three_opt_kernel" if any(getattr(x, "ls_op", 2) == 3 for x in insts) else "local_search_kernel"
+        lines["two_opt"] = kernel_line(name, two_opt_bytes(insts), st["local_search_ms"],
                                        st["local_search_launches"])
     return lines
 
@@ -534,6 +536,10 @@ PAPER_TIMES_S = {
     (500, 2): {"table_I": [3.99, 4.21], "table_VII_softdist": 1.95},
     (1000, 2): {"table_I": [8.37, 8.49], "table_VII_softdist": 4.30},
     (10000, 2): {"table_I": [112.2, 142.2], "table_VII_softdist": 60.92},
+    # with the 3-opt (Table I, HeatACO+3-opt)
+    (500, 3): {"table_I": [13.63, 14.82]},
+    (1000, 3): {"table_I": [26.43, 28.54]},
+    (10000, 3): {"table_I": [399.0, 488.4]},
 }
 
 
@@ -542,9 +548,11 @@ def run_paper(args, hac, wl):
     rho = 0.8; with --ls 2 the 2-opt on every ant's tour) on synthetic
     uniform instances of the paper's test-set sizes: a batched decode of the
     whole set and plain decodes of a sample, with tours asserted identical."""
-    n, ls = args.paper_n, args.ls
+    n, ls, op = args.paper_n, args.ls, args.ls_op
     count = args.instances or (16 if n >= 10000 else 128)
     insts = wl.paper_budget(n, count, local_search=ls, iterations=args.iterations or 5000)
+    if ls and op == 3:
+        insts = [dataclasses.replace(x, ls_op=3) for x in insts]
     ant_steps = sum(x.ants * (x.n - 1) * x.iterations for x in insts)
     ctx = hac.Context(0)
     db = hac.DeviceBatch(insts)
@@ -557,13 +565,14 @@ def run_paper(args, hac, wl):
     mean_len = float(np.mean([batched[x][1] for x in range(count)]))
     desc = (f"paper{n}: {count} uniform TSP instances, n={n}, top-20 heatmaps, 32 ants, "
             f"{insts[0].iterations} iterations, k=20, rho=0.8, "
-            + ("2-opt (20 neighbours) on every ant's tour" if ls == 2 else "no local search"))
-    out = base_line(args, f"ant-steps/s, batched decode at the paper's budget (n={n}, ls={ls})",
+            + ((f"{op}-opt (20 neighbours) on every ant's tour" if ls == 2 else
+                f"{op}-opt (20 neighbours) on the iteration best") if ls else "no local search"))
+    out = base_line(args, f"ant-steps/s, batched decode at the paper's budget (n={n}, ls={ls}, {op}-opt)",
                     ant_steps * args.steps / wall, 1000.0 * wall / args.steps,
                     {"workload": desc, "instances": count, "iterations": insts[0].iterations, "ants": 32,
                      "k": 20, "inputs": "resident in HBM (hac_decode_batch_dev)",
                      "launch_shape": launch_shape(st)})
-    ctx_paper = PAPER_TIMES_S.get((n, ls))
+    ctx_paper = PAPER_TIMES_S.get((n, 3 if ls == 2 and op == 3 else ls))
     out.update({
         "decodes_per_s": count * args.steps / wall,
         "per_instance_s": {"plain_p50": percentile(lat, 0.5), "batched_equivalent": wall / args.steps / count},
@@ -644,6 +653,8 @@ def main():
     ap.add_argument("--paper-n", type=int, default=500, help="paper/ablation workload: instance size")
     ap.add_argument("--ls", type=int, default=0, choices=[0, 1, 2],
                     help="paper workload: 2 = 2-opt on every ant; atsp workload: 1 (default there) or 2")
+    ap.add_argument("--ls-op", type=int, default=2, choices=[2, 3],
+                    help="paper workload: the local-search operator (2-opt, or the 3-opt of symmetric instances)")
     ap.add_argument("--instances", type=int, default=None, help="paper workload: instances in the batch")
     ap.add_argument("--iterations", type=int, default=None, help="override the workload's iteration count")
     ap.add_argument("--plain-sample", type=int, default=16)

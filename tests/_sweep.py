@@ -59,6 +59,10 @@ def sweep_cases(count: int = 96, seed: int = 2601):
                                   kind="coords" if kind == "coords" else "matrix",
                                   symmetric=kind != "atsp", local_search=ls, k_ls=k_ls, heat=heat,
                                   grid=grid)
-        inst.name = f"sweep{x}:{kind} n={n} k={k} ants={ants} it={iterations} ls={ls}"
+        # the 3-opt on a third of the symmetric cases with local search (a
+        # draw of its own, so the other draws stay as they were)
+        if ls and kind != "atsp" and np.random.default_rng(7000 + x).random() < 0.35:
+            inst.ls_op = 3
+        inst.name = f"sweep{x}:{kind} n={n} k={k} ants={ants} it={iterations} ls={ls} op={inst.ls_op}"
         cases.append((inst, over))
     return cases
