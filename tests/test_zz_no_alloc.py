@@ -4,10 +4,12 @@ hac_decode_noalloc carves every device buffer of a decode from one static
 array per GPU instead of allocating.  Through the C ABI, two calls in a row
 (the second with a smaller input, so the array still holds the first call's
 data) must return exactly what hac_decode returns for the same inputs, and
-so must a call with 2-opt and one on an asymmetric matrix.  An instance
-larger than the array is refused with HAC_ENOMEM and the outputs are left
-untouched.
+so must a call with 2-opt, one with the 3-opt and one on an asymmetric
+matrix.  An instance larger than the array is refused with HAC_ENOMEM and
+the outputs are left untouched.
 """
+
+import dataclasses
 
 import numpy as np
 import pytest
@@ -51,8 +53,11 @@ def test_noalloc_two_opt_and_atsp(ctx):
     # the directed 2-opt: incoming lists and its work area in the array too
     atsp_ls = wl.random_instance(200, seed=9, kind="matrix", symmetric=False, ants=8, iterations=12,
                                  local_search=2, k_ls=10)
-    print("case no-alloc 2-opt n=300, ATSP n=1000, ATSP n=200 with directed 2-opt", flush=True)
-    for inst in (ls, atsp, atsp_ls):
+    # the 3-opt: the same work area as the 2-opt
+    ls3 = dataclasses.replace(wl.random_instance(250, seed=10, ants=10, iterations=15, local_search=2, k_ls=10),
+                              ls_op=3)
+    print("case no-alloc 2-opt n=300, ATSP n=1000, ATSP n=200 with directed 2-opt, 3-opt n=250", flush=True)
+    for inst in (ls, atsp, atsp_ls, ls3):
         _same(ctx.decode_noalloc(inst), ctx.decode(inst), inst.name)
 
 
