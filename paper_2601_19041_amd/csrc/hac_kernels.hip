@@ -1819,11 +1819,11 @@ __global__ void __launch_bounds__(LS_WAVES * WAVE) local_search_kernel(const Ins
 // applied, its end nodes t1 .. t6 are queued in that order if absent, and
 // a is examined again; a search applies at most 64 n moves.
 //
-// One wave per tour examines one node at a time: for each t3 in list order,
-// lanes 0..31 take t4's list entries on the successor side and lanes
-// 32..63 on the predecessor side, so that the first improving entry of a
-// side is one ballot away; the successor side's first move anywhere in
-// t3's order comes before any predecessor-side move.
+// A wave examines one node: for each t3 in list order, lanes 0..31 take
+// t4's list entries on the successor side and lanes 32..63 on the
+// predecessor side, so that the first improving entry of a side is one
+// ballot away; the successor side's first move anywhere in t3's order
+// comes before any predecessor-side move.
 // ------------------------------------------------------------------------
 struct Ls3Move {
   int imp, dir, t1, t2, t3, t4, t5, t6, r3, end;  // end: steps from t1 to t6
@@ -1914,11 +1914,25 @@ __device__ __forceinline__ void ls_reverse_span(int n, IP tour, IP pos, int i, i
   __syncthreads();
 }
 
-// one block (of one wave) per tour; tour, pos, queue and the flags in LDS
-// or global memory
+// The move a wave found for its node: kind 0 none, 2 a 2-opt move, 3 a
+// segment exchange.
+struct Ls3Any {
+  int kind, a, b, c, e, dir, t1, t2, t3, t4, t5, t6, r3, end;
+};
+
+// One block of W waves per tour, organised like the 2-opt's: each round the
+// waves evaluate the next queue entries against the same tour (wave 0 takes
+// the node of the last applied move first, as the sequential search
+// examines it again), the first improving result in queue order is
+// applied, and the entries before it are consumed as the sequential search
+// consumes them; the results behind it are dropped.  Thread 0 keeps the
+// queue; the block reverses paths.
 template <class IP, class BP>
 __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain) {
-  const int n = D.n, kls = D.kls, kg = D.kg;
+  __shared__ int sh_head, sh_count;
+  __shared__ Ls3Any sh_mv[LS_WAVES];
+  const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
+  const int nw = (int)(blockDim.x / WAVE);
   if (n < 5 || kls < 1) return;
   const GDist G(D);
   const HAC_AS1 int32_t* geo = as_global(D.geo);
@@ -1928,68 +1942,136 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
     queue[s] = v;
     inq[v] = 1;
   }
+  if (threadIdx.x == 0) {
+    sh_head = 0;
+    sh_count = n;
+  }
   __syncthreads();
-  // the queue is kept by every lane alike: each writes the same values, so
-  // a lane always reads its own last write
-  int head = 0, count = n;
-  auto push = [&](int x) {
-    if (!inq[x]) {
-      int slot = head + count;
-      if (slot >= n) slot -= n;
-      queue[slot] = x;
-      inq[x] = 1;
-      ++count;
-    }
-  };
   const int64_t max_moves = 64 * (int64_t)n;
   int64_t moves = 0;
-  while (count > 0 && moves < max_moves) {
-    const int a = queue[head];
-    head = head + 1 == n ? 0 : head + 1;
-    --count;
-    inq[a] = 0;
-    bool improved = true;
-    while (improved && moves < max_moves) {
-      improved = false;
-      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, a, min_gain);
-      if (m.imp) {
-        const int ri = pos[m.dir == 0 ? m.b : m.c], rj = pos[m.dir == 0 ? m.c : m.b];
-        __syncthreads();  // every lane has its positions before any changes
-        ls_reverse(n, tour, pos, ri, rj);
-        push(a);
-        push(m.b);
-        push(m.c);
-        push(m.e);
-        improved = true;
-        ++moves;
-        continue;
+  int pend = -1;
+  while (moves < max_moves) {
+    const int head = sh_head, count = sh_count;
+    const int re = pend >= 0 ? 1 : 0;
+    const int nq = min(nw - re, count);  // queue entries in this batch
+    const int nb = nq + re;
+    if (nb == 0) break;
+    if (wave < nb) {
+      int node = pend;
+      if (wave >= re) {
+        int slot = head + wave - re;
+        if (slot >= n) slot -= n;
+        node = queue[slot];
       }
-      const Ls3Move x = ls3_eval(G, geo, kg, kls, n, tour, pos, a, min_gain);
-      if (x.imp) {
-        // the segments t2..t4 (r3 - 1 nodes) and t3..t6 (end - r3 + 1) trade
-        // places: reversing both together and then each gives that
-        const int p1 = pos[a];
-        const int l1 = x.r3 - 1, l2 = x.end - x.r3 + 1;
-        __syncthreads();
-        int st = x.dir == 0 ? p1 + 1 : p1 - x.end;
-        if (st >= n) st -= n;
-        if (st < 0) st += n;
-        const int first = x.dir == 0 ? l2 : l1;  // the segment that ends up first
-        ls_reverse_span(n, tour, pos, st, x.end);
-        ls_reverse_span(n, tour, pos, st, first);
-        int st2 = st + first;
-        if (st2 >= n) st2 -= n;
-        ls_reverse_span(n, tour, pos, st2, x.end - first);
-        push(x.t1);
-        push(x.t2);
-        push(x.t3);
-        push(x.t4);
-        push(x.t5);
-        push(x.t6);
-        improved = true;
-        ++moves;
+      Ls3Any r{0, node, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
+      if (m.imp) {
+        r.kind = 2;
+        r.b = m.b;
+        r.c = m.c;
+        r.e = m.e;
+        r.dir = m.dir;
+      } else {
+        const Ls3Move x = ls3_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
+        if (x.imp) {
+          r.kind = 3;
+          r.dir = x.dir;
+          r.t1 = x.t1;
+          r.t2 = x.t2;
+          r.t3 = x.t3;
+          r.t4 = x.t4;
+          r.t5 = x.t5;
+          r.t6 = x.t6;
+          r.r3 = x.r3;
+          r.end = x.end;
+        }
+      }
+      if (lane == 0) sh_mv[wave] = r;
+    }
+    __syncthreads();
+    // the first improving result in batch order (one entry per lane)
+    const uint64_t fm = __builtin_amdgcn_ballot_w64(lane < nb && sh_mv[min(lane, LS_WAVES - 1)].kind != 0);
+    const int f = fm ? (int)__builtin_ctzll(fm) : -1;
+    // queue entries consumed as a sequential scan would: all of them if no
+    // move improves, else those up to and including the improving one
+    const int used = f < 0 ? nq : max(0, f + 1 - re);
+    Ls3Any mv{};
+    int ri = 0, rj = 0;  // a 2-opt move's path, or an exchange's first position
+    if (f >= 0) {
+      mv = sh_mv[f];
+      if (mv.kind == 2) {
+        ri = pos[mv.dir == 0 ? mv.b : mv.c];
+        rj = pos[mv.dir == 0 ? mv.c : mv.b];
+      } else {
+        const int p1 = pos[mv.a];
+        ri = mv.dir == 0 ? p1 + 1 : p1 - mv.end;
+        if (ri >= n) ri -= n;
+        if (ri < 0) ri += n;
       }
     }
+    if ((int)threadIdx.x < used) {
+      int slot = head + threadIdx.x;
+      if (slot >= n) slot -= n;
+      inq[queue[slot]] = 0;
+    }
+    __syncthreads();
+    if (f < 0) {
+      if (threadIdx.x == 0) {
+        int h = head + used;
+        if (h >= n) h -= n;
+        sh_head = h;
+        sh_count = count - used;
+      }
+      pend = -1;
+      __syncthreads();
+      continue;
+    }
+    // thread 0 moves the head and queues the end nodes in order if absent
+    // (an exchange's ends may repeat); the queue and the tour are separate
+    // arrays, so this runs beside the reversals, whose barriers publish it
+    if (threadIdx.x == 0) {
+      int h = head + used;
+      if (h >= n) h -= n;
+      int cnt = count - used;
+      auto push = [&](int x) {
+        if (!inq[x]) {
+          int slot = h + cnt;
+          if (slot >= n) slot -= n;
+          queue[slot] = x;
+          inq[x] = 1;
+          ++cnt;
+        }
+      };
+      if (mv.kind == 2) {
+        push(mv.a);
+        push(mv.b);
+        push(mv.c);
+        push(mv.e);
+      } else {
+        push(mv.t1);
+        push(mv.t2);
+        push(mv.t3);
+        push(mv.t4);
+        push(mv.t5);
+        push(mv.t6);
+      }
+      sh_head = h;
+      sh_count = cnt;
+    }
+    if (mv.kind == 2) {
+      ls_reverse(n, tour, pos, ri, rj);
+    } else {
+      // the segments t2..t4 (r3 - 1 nodes) and t3..t6 (end - r3 + 1) trade
+      // places: reversing both together and then each gives that
+      const int first = mv.dir == 0 ? mv.end - mv.r3 + 1 : mv.r3 - 1;  // the segment that ends up first
+      ls_reverse_span(n, tour, pos, ri, mv.end);
+      ls_reverse_span(n, tour, pos, ri, first);
+      int st2 = ri + first;
+      if (st2 >= n) st2 -= n;
+      ls_reverse_span(n, tour, pos, st2, mv.end - first);
+    }
+    ++moves;
+    pend = mv.a;
   }
   __syncthreads();
 }
@@ -2023,21 +2105,23 @@ __device__ __forceinline__ void three_opt_tour(const InstDesc& D, int32_t* tour_
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(WAVE) three_opt_nn_kernel(const InstDesc* insts) {
+__global__ void __launch_bounds__(LS_WAVES * WAVE) three_opt_nn_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || !D.sym || D.ls_op != 3) return;
   three_opt_tour<MODE>(D, D.nn_tour, D.st->min_gain, D.ls_work);
-  const double len = tour_length_wave(D, D.nn_tour);
-  if (threadIdx.x == 0) {
-    D.st->l_gb = len;
-    D.st->l_ib = len;
+  if (threadIdx.x < WAVE) {
+    const double len = tour_length_wave(D, D.nn_tour);
+    if (threadIdx.x == 0) {
+      D.st->l_gb = len;
+      D.st->l_ib = len;
+    }
   }
 }
 
 // local_search = 1: block (i, 0) improves a copy of the iteration best;
 // local_search = 2: block (i, y) improves ant tours y, y + gridDim.y, ...
 template <int MODE>
-__global__ void __launch_bounds__(WAVE) three_opt_kernel(const InstDesc* insts) {
+__global__ void __launch_bounds__(LS_WAVES * WAVE) three_opt_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || !D.sym || D.ls_op != 3 || D.st->t > D.iterations || D.st->err) return;
   const int n = D.n;
@@ -2045,25 +2129,35 @@ __global__ void __launch_bounds__(WAVE) three_opt_kernel(const InstDesc* insts) 
     for (int a = blockIdx.y; a < D.ants; a += gridDim.y) {
       int32_t* tour = D.tours + (int64_t)a * n;
       three_opt_tour<MODE>(D, tour, D.st->min_gain, D.ls_work + (int64_t)a * 3 * n);
-      const double len = tour_length_wave(D, tour);
-      if (threadIdx.x == 0) D.lens[a] = len;
+      if (threadIdx.x < WAVE) {
+        const double len = tour_length_wave(D, tour);
+        if (threadIdx.x == 0) D.lens[a] = len;
+      }
       __syncthreads();
     }
     return;
   }
   if (blockIdx.y != 0) return;
-  int ib;
-  double lib;
-  iteration_best_wave(D, ib, lib);
+  __shared__ int sh_ib;
+  if (threadIdx.x < WAVE) {
+    int ib;
+    double lib;
+    iteration_best_wave(D, ib, lib);
+    if (threadIdx.x == 0) sh_ib = ib;
+  }
+  __syncthreads();
+  const int ib = sh_ib;
   const int32_t* src = D.tours + (int64_t)ib * n;
   for (int s = threadIdx.x; s < n; s += blockDim.x) D.t_ib[s] = src[s];
   __threadfence_block();
   __syncthreads();
   three_opt_tour<MODE>(D, D.t_ib, D.st->min_gain, D.ls_work);
-  const double len = tour_length_wave(D, D.t_ib);
-  if (threadIdx.x == 0) {
-    D.st->ib = ib;
-    D.st->l_ib = len;
+  if (threadIdx.x < WAVE) {
+    const double len = tour_length_wave(D, D.t_ib);
+    if (threadIdx.x == 0) {
+      D.st->ib = ib;
+      D.st->l_ib = len;
+    }
   }
 }
 
@@ -2741,13 +2835,14 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
   return hipGetLastError();
 }
 
-// largest static LDS of the 2-opt kernels (their __shared__ variables),
-// read from the compiled kernels once
+// largest static LDS of the 2-opt and 3-opt kernels (their __shared__
+// variables), read from the compiled kernels once
 static size_t ls_static_lds() {
   static size_t v = [] {
     size_t m = 0;
     const void* ks[] = {(const void*)two_opt_nn_kernel<2>, (const void*)two_opt_nn_kernel<1>,
-                        (const void*)local_search_kernel<2>, (const void*)local_search_kernel<1>};
+                        (const void*)local_search_kernel<2>, (const void*)local_search_kernel<1>,
+                        (const void*)three_opt_nn_kernel<1>, (const void*)three_opt_kernel<1>};
     for (const void* k : ks) {
       hipFuncAttributes a{};
       // on failure keep a generous reserve rather than overcommit LDS
@@ -2818,12 +2913,17 @@ static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_
   return hipGetLastError();
 }
 
-// the 3-opt: one wave per tour, the working arrays in LDS when they fit
+static int ls_block_waves(int32_t max_n, int mode, int64_t tours);
+
+// the 3-opt: one block per tour (waves as for the 2-opt), the working
+// arrays in LDS when they fit
 static hipError_t launch_three_opt(const InstDesc* d_insts, int32_t count, int32_t max_n3, int32_t tpi, bool nn,
                                    hipStream_t s) {
   const int mode = ls_mode(max_n3, 0);
   const size_t lds = mode == 1 ? ls_lds_need(max_n3, 1) : 0;
-  const dim3 grid(count, nn ? 1 : std::max(tpi, 1)), block(WAVE);
+  const int t = nn ? 1 : std::max(tpi, 1);
+  const int waves = t > 1 ? ls_block_waves(max_n3, mode, (int64_t)count * t) : LS_WAVES;
+  const dim3 grid(count, t), block(waves * WAVE);
   if (nn) {
     if (mode == 1)
       hipLaunchKernelGGL(three_opt_nn_kernel<1>, grid, block, lds, s, d_insts);
