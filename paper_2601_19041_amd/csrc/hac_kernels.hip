@@ -2913,17 +2913,28 @@ static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_
   return hipGetLastError();
 }
 
-static int ls_block_waves(int32_t max_n, int mode, int64_t tours);
+// Waves per 3-opt block: the most (up to LS_WAVES, a power of two) with
+// which every tour's block is resident at once (8 192 wave slots: 256 CUs x
+// 32); beyond that the speculative evaluations cost more than they save
+// (every ant's tour of 128 n = 1000 instances, per launch: 1 wave 18.1 ms,
+// 2 waves 14.0 ms, 4 waves 15.7 ms).  HAC_LS_WAVES pins the count.
+static int three_opt_waves(int64_t tours) {
+  if (const char* env = std::getenv("HAC_LS_WAVES")) {
+    const int w = std::atoi(env);
+    if (w >= 1 && w <= LS_WAVES) return w;
+  }
+  int w = LS_WAVES;
+  while (w > 1 && tours * w > 8192) w /= 2;
+  return w;
+}
 
-// the 3-opt: one block per tour (waves as for the 2-opt), the working
-// arrays in LDS when they fit
+// the 3-opt: one block per tour, the working arrays in LDS when they fit
 static hipError_t launch_three_opt(const InstDesc* d_insts, int32_t count, int32_t max_n3, int32_t tpi, bool nn,
                                    hipStream_t s) {
   const int mode = ls_mode(max_n3, 0);
   const size_t lds = mode == 1 ? ls_lds_need(max_n3, 1) : 0;
   const int t = nn ? 1 : std::max(tpi, 1);
-  const int waves = t > 1 ? ls_block_waves(max_n3, mode, (int64_t)count * t) : LS_WAVES;
-  const dim3 grid(count, t), block(waves * WAVE);
+  const dim3 grid(count, t), block(three_opt_waves((int64_t)count * t) * WAVE);
   if (nn) {
     if (mode == 1)
       hipLaunchKernelGGL(three_opt_nn_kernel<1>, grid, block, lds, s, d_insts);
