@@ -204,12 +204,17 @@ VARIANT = """      ex[s] = dpp_zero<0x111>(P) + a[s] - q[s];"""
 
 
 def test_no_dpp_operand_from_a_multiply_in_the_kernels(tmp_path):
+    from concurrent.futures import ThreadPoolExecutor
     src = open(os.path.join(CSRC, "hac_kernels.hip")).read()
     assert src.count(KEPT) == 1
-    kept = _asm(os.path.join(CSRC, "hac_kernels.hip"), tmp_path / "kept.s")
-    assert _mul_fed_dpp(kept) == []
-    # the scanner finds the pattern in the removed variant
     var_src = tmp_path / "variant.hip"
     var_src.write_text(src.replace(KEPT, VARIANT))
-    found = _mul_fed_dpp(_asm(var_src, tmp_path / "variant.s"))
+    # both compiles at once (each is one long single-threaded device pass)
+    with ThreadPoolExecutor(2) as ex:
+        kept_f = ex.submit(_asm, os.path.join(CSRC, "hac_kernels.hip"), tmp_path / "kept.s")
+        var_f = ex.submit(_asm, var_src, tmp_path / "variant.s")
+        kept, variant = kept_f.result(), var_f.result()
+    assert _mul_fed_dpp(kept) == []
+    # the scanner finds the pattern in the removed variant
+    found = _mul_fed_dpp(variant)
     assert found and all("v_mul_hi_u32" in a and "_dpp" in b for a, b in found)
