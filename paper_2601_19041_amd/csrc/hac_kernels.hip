@@ -1375,7 +1375,6 @@ struct AntRows {
     uint64_t e[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) e[s] = entry(ra[s]);
-    __builtin_amdgcn_sched_barrier(0);  // the table read goes first: it heads the step's chain
     // mode 1: the int32 geometric list of the current node, needed only if
     // the row is exhausted, loaded now so that its latency hides behind the
     // step (mode 2 loaded the uint16 list at the end of the previous step)
@@ -1476,7 +1475,7 @@ struct AntRows {
         vis_g[wi] = wv;
     }
     j = (int)min((uint32_t)j, (uint32_t)(n - 1));
-    if (exh_mask) {
+    if (__builtin_expect(exh_mask != 0, 0)) {  // rare: keeps the fallback out of the step's straight line
       j = fallback(exhausted, j, gl);
       if (exhausted) set_row(__umul24((uint32_t)j, k8));
     }
