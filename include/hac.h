@@ -87,9 +87,11 @@ typedef struct hac_params {
   int32_t iterations;   /* I                                                */
   int32_t k;            /* candidate-list size (eq. 3), <= HAC_MAX_K        */
   int32_t k_ls;         /* local-search neighbour-list size, <= HAC_MAX_KLS */
-  int32_t local_search; /* 0 none; 1 2-opt on each iteration-best tour;    */
-                        /* 2 2-opt on every ant's tour (Alg. 1), the       */
-                        /* iteration best taken among the improved tours   */
+  int32_t local_search; /* 0 none; 1 local search (ls_op: the 2-opt or   */
+                        /* the 3-opt; the directed 2-opt on an ATSP) on    */
+                        /* each iteration-best tour; 2 on every ant's tour */
+                        /* (Alg. 1), the iteration best then taken among   */
+                        /* the improved tours                              */
   double alpha;         /* pheromone exponent; only 1 is supported          */
   double beta;          /* heuristic exponent                               */
   double rho;           /* evaporation rate, in (0, 1)                      */
