@@ -456,15 +456,16 @@ hac_status prepare_instances(std::vector<HostInst>& hs, InstDesc* d_descs, hipSt
   HAC_HIP(launch_grid(d_descs, count, s));
   HAC_HIP(launch_nn_tour(d_descs, count, max_n, s));
   bool any_ls = false;
-  int32_t all_coords = 1, max_n_dir = 0, max_kls_dir = 0, max_n_sym = 0, max_n3 = 0;  // largest directed / symmetric
+  int32_t all_coords = 1, max_n_dir = 0, max_kls_dir = 0, max_n_sym = 0, max_n3 = 0, all_coords3 = 1;  // largest directed / symmetric
   for (auto& h : hs) {
     any_ls |= h.p.local_search != 0;
     if (h.lay.directed) max_n_dir = std::max(max_n_dir, h.lay.n), max_kls_dir = std::max(max_kls_dir, h.lay.kls);
     else if (h.lay.three_opt) max_n3 = std::max(max_n3, h.lay.n);
     else if (h.p.local_search) max_n_sym = std::max(max_n_sym, h.lay.n);
     if (h.p.local_search && !h.lay.directed && !h.lay.three_opt && !h.lay.coords) all_coords = 0;
+    if (h.lay.three_opt && !h.lay.coords) all_coords3 = 0;
   }
-  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n_sym, all_coords, max_n_dir, max_kls_dir, max_n3, s));
+  if (any_ls) HAC_HIP(launch_two_opt_nn(d_descs, count, max_n_sym, all_coords, max_n_dir, max_kls_dir, max_n3, all_coords3, s));
   std::vector<State> sts(count);
   if (stage) {
     // after the weights' scatter on the same stream: the staging arena is reused
@@ -1186,7 +1187,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
   if (m > 0) {
     bool any_ls = false;
     // max_n: the largest symmetric instance with 2-opt (0: none); max_n_dir: ATSP
-    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0, max_kls_dir = 0, max_n3 = 0;
+    int32_t max_iter = 0, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0, max_kls_dir = 0, max_n3 = 0, all_coords3 = 1;
     for (auto& h : hs) {
       any_ls |= h.p.local_search != 0;
       if (h.p.local_search == 2) ls_tours = std::max(ls_tours, h.p.ants);
@@ -1195,6 +1196,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
       else if (h.lay.three_opt) max_n3 = std::max(max_n3, h.lay.n);
       else if (h.p.local_search) max_n = std::max(max_n, h.lay.n);
       if (h.p.local_search && !h.lay.directed && !h.lay.three_opt && !h.lay.coords) all_coords = 0;
+      if (h.lay.three_opt && !h.lay.coords) all_coords3 = 0;
     }
     LaunchShape shape{4, 0, 16, 4, 0};
     if (noalloc) {
@@ -1232,7 +1234,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
                                       shape.bytes, shape.kmax, lds, shape.geo, shape.grid, s);
       if (e != hipSuccess) return e;
       if (any_ls) {
-        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, max_n3, s);
+        e = launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, max_n3, all_coords3, s);
         if (e != hipSuccess) return e;
       }
       return launch_iter_end(d_descs, m, s);
@@ -1256,7 +1258,7 @@ hac_status run_batch(hac_ctx* c, int32_t count, const hac_instance* insts_in, co
         CTX_HIP(launch_construct(d_descs, d_map, blocks, shape.ants_per_block, shape.rows_per_wave, shape.staged,
                                       shape.bytes, shape.kmax, lds, shape.geo, shape.grid, s));
         CTX_HIP(hipEventRecord(ev[1], s));
-        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, max_n3, s));
+        if (any_ls) CTX_HIP(launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, max_n3, all_coords3, s));
         CTX_HIP(hipEventRecord(ev[2], s));
         CTX_HIP(launch_iter_end(d_descs, m, s));
         CTX_HIP(hipEventRecord(ev[3], s));

@@ -154,9 +154,11 @@ hipError_t launch_nn_tour(const InstDesc* d_insts, int32_t count, int32_t max_n,
 // them); max_n_dir: largest ATSP instance with local search (0: none); such
 // instances take the directed 2-opt (and their neighbour lists are built
 // first); max_kls_dir: their largest k_ls; max_n3: the largest symmetric
-// instance with the 3-opt (0: none; such instances are left out of max_n)
+// instance with the 3-opt (0: none; such instances are left out of max_n);
+// all_coords3 = 1 when every 3-opt instance has coordinates
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
-                             int32_t max_n_dir, int32_t max_kls_dir, int32_t max_n3, hipStream_t s);
+                             int32_t max_n_dir, int32_t max_kls_dir, int32_t max_n3, int32_t all_coords3,
+                             hipStream_t s);
 hipError_t launch_init(const InstDesc* d_insts, int32_t count, hipStream_t s);
 // builds the coordinate grid of every instance that has one
 hipError_t launch_grid(const InstDesc* d_insts, int32_t count, hipStream_t s);
@@ -178,7 +180,7 @@ hipError_t launch_construct(const InstDesc* d_insts, const BlockMap* d_map, int3
 // that search every ant's tour, else 1)
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                int32_t all_coords, int32_t tours_per_inst, int32_t max_n_dir,
-                               int32_t max_kls_dir, int32_t max_n3, hipStream_t s);
+                               int32_t max_kls_dir, int32_t max_n3, int32_t all_coords3, hipStream_t s);
 hipError_t launch_iter_end(const InstDesc* d_insts, int32_t count, hipStream_t s);
 hipError_t launch_finish(const InstDesc* d_insts, int32_t count, int32_t* const* d_out_tours,
                          double* d_out_lens, hipStream_t s);

@@ -17,9 +17,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
 #include <cstdlib>
 #include <mutex>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "hac_internal.h"
 
@@ -926,6 +929,29 @@ static __host__ __device__ inline size_t ls_lds_need(int n, int mode) {
   return 0;
 }
 
+// Mode 2's arrays in LDS: the tour as uint16 and its FP32 coordinates in
+// tour order, loaded from tour_g; returns the largest coordinate magnitude
+// (for the FP32 error bounds).  The positions, queue and flags follow.
+__device__ __forceinline__ double ls_stage_xy(const InstDesc& D, const int32_t* tour_g, uint16_t* tour,
+                                              float2* txy) {
+  __shared__ double sh_m[LS_WAVES];
+  const int n = D.n;
+  double mloc = 0.0;
+  const HAC_AS1 double* xy = as_global(D.xy);
+  for (int s = threadIdx.x; s < n; s += blockDim.x) {
+    const int v = tour_g[s];
+    tour[s] = (uint16_t)v;
+    txy[s] = make_float2((float)xy[2 * v], (float)xy[2 * v + 1]);
+    mloc = fmax(mloc, fmax(fabs(xy[2 * s]), fabs(xy[2 * s + 1])));
+  }
+  for (int off = 32; off >= 1; off >>= 1) mloc = fmax(mloc, __shfl_xor(mloc, off));
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh_m[threadIdx.x / WAVE] = mloc;
+  __syncthreads();
+  double M = 0.0;
+  for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) M = fmax(M, sh_m[w]);
+  return M;
+}
+
 template <int MODE>
 __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain,
                                              int32_t* work) {
@@ -937,21 +963,7 @@ __device__ __forceinline__ void two_opt_tour(const InstDesc& D, int32_t* tour_g,
     uint16_t* queue = pos + n;
     uint8_t* inq = reinterpret_cast<uint8_t*>(ls_lds) + ((size_t)6 * n + 15) / 16 * 16;
     float2* txy = reinterpret_cast<float2*>(reinterpret_cast<uint8_t*>(inq) + ((size_t)n + 15) / 16 * 16);
-    __shared__ double sh_m[LS_WAVES];
-    double mloc = 0.0;
-    const HAC_AS1 double* xy = as_global(D.xy);
-    for (int s = threadIdx.x; s < n; s += blockDim.x) {
-      const int v = tour_g[s];
-      tour[s] = (uint16_t)v;
-      txy[s] = make_float2((float)xy[2 * v], (float)xy[2 * v + 1]);
-      mloc = fmax(mloc, fmax(fabs(xy[2 * s]), fabs(xy[2 * s + 1])));
-    }
-    // largest coordinate magnitude (for the FP32 error bounds)
-    for (int off = 32; off >= 1; off >>= 1) mloc = fmax(mloc, __shfl_xor(mloc, off));
-    if ((threadIdx.x & (WAVE - 1)) == 0) sh_m[threadIdx.x / WAVE] = mloc;
-    __syncthreads();
-    double M = 0.0;
-    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) M = fmax(M, sh_m[w]);
+    const double M = ls_stage_xy(D, tour_g, tour, txy);
     two_opt_block_xy(D, tour, pos, queue, inq, txy, min_gain, M * 0x1p-18, M * 0x1p-17);
     __syncthreads();
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
@@ -1895,6 +1907,132 @@ __device__ Ls3Move ls3_eval(const GDist& G, const HAC_AS1 int32_t* geo, int kg, 
   return Ls3Move{0, 0, a, 0, 0, 0, 0, 0, 0, 0};
 }
 
+// Mode 2 of the 3-opt keeps the 2-opt's mode-2 arrays in LDS (uint16 tour,
+// positions and queue, and the FP32 coordinates in tour order) and decides
+// each test from FP32 distances when the result lies outside its error
+// bound, else in FP64 from global memory, so every decision is the FP64
+// one.  With every distance within 17 u M of its FP64 value (u = 2^-24, M
+// the largest coordinate magnitude) and each FP32 addition rounding a value
+// of at most 2 sqrt(2) M per distance it sums:
+//   g1 = d12 - d13                        (2 distances)  within E1 = 2^-18 M,
+//   g2 = (g1 + d43) - d45                 (4 distances)  within E2 = 2^-17 M,
+//   ((d12 + d43) + d65) - ((d13 + d45) + d62)  (6)       within E3 = 2^-16 M.
+// a's list is read once per node, one entry per lane of each half, with the
+// entry's t3, its steps from t1, its t4 on that half's side and their
+// distances; t3's loop reads them from lane q of the half, and t4's list
+// for the next t3 is loaded while the current one is examined.
+
+__device__ __forceinline__ int side_lane(int v, int q, int dir) {
+  const int s = __builtin_amdgcn_readlane(v, q);
+  const int p = __builtin_amdgcn_readlane(v, q + 32);
+  return dir ? p : s;
+}
+
+__device__ __forceinline__ float side_lane_f(float v, int q, int dir) {
+  return __int_as_float(side_lane(__float_as_int(v), q, dir));
+}
+
+__device__ Ls3Move ls3_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls, int n,
+                               const uint16_t* tour, const uint16_t* pos, const float2* txy, int a,
+                               double min_gain, double e1, double e2, double e3) {
+  const int lane = lane_id();
+  const int dir = lane >= 32 ? 1 : 0;
+  const int step = dir ? -1 : 1;
+  const int q5 = lane & 31;
+  const bool in5 = q5 < kls;
+  const int p1 = pos[a];
+  const int p2 = cyc_step(p1, step, n);
+  const int t2 = tour[p2];
+  const float2 x1 = txy[p1], x2 = txy[p2];
+  const float l12 = ls_len_xy(x1, x2);
+  // list entry q5 of a: t3, its steps from t1 in this half's direction,
+  // the node before it (t4) and the FP32 distances d13, d43
+  const int t3l = geo[(int64_t)a * kg + min(q5, kls - 1)];
+  const int p3l = pos[t3l];
+  int r3l = dir ? p1 - p3l : p3l - p1;
+  if (r3l < 0) r3l += n;
+  const int p4l = cyc_step(p3l, -step, n);
+  const int t4l = tour[p4l];
+  const float2 x3l = txy[p3l], x4l = txy[p4l];
+  const float l13l = ls_len_xy(x1, x3l), l43l = ls_len_xy(x4l, x3l);
+  // g1 > 0 as FP64 decides it; t3 = t2 gives exactly 0
+  const float g1l = l12 - l13l;
+  bool g1pos = t3l != t2 && (double)g1l > e1;
+  if (in5 && t3l != t2 && !((double)g1l > e1) && !((double)g1l < -e1))
+    g1pos = G.len(a, t2) - G.len(a, t3l) > 0.0;
+  // a side stops at the first t3 that cannot gain
+  const uint64_t gstop = __builtin_amdgcn_ballot_w64(in5 && !g1pos);
+  const uint64_t gs = gstop & 0xffffffffull, gp = gstop >> 32;
+  const int lim_s = min(gs ? (int)__builtin_ctzll(gs) : 32, kls);
+  const int lim_p = min(gp ? (int)__builtin_ctzll(gp) : 32, kls);
+  bool p_found = false;
+  Ls3Move pm{0, 1, a, 0, 0, 0, 0, 0, 0, 0};
+  int t5n = 0;  // t4's list entry q5 for the next t3
+  if (lim_s > 0 || lim_p > 0) t5n = geo[(int64_t)side_lane(t4l, 0, dir) * kg + min(q5, kls - 1)];
+  for (int q = 0; q < lim_s || (q < lim_p && !p_found); ++q) {
+    const int t5 = t5n;
+    if (q + 1 < kls) t5n = geo[(int64_t)side_lane(t4l, q + 1, dir) * kg + min(q5, kls - 1)];
+    const bool live = dir ? (q < lim_p && !p_found) : q < lim_s;
+    const int t3 = rd_lane(t3l, q);
+    const int r3 = side_lane(r3l, q, dir);
+    const bool use3 = live && r3 >= 2;
+    int t4 = 0, t6 = 0, r5 = 0, p5 = 0;
+    float l13 = 0.0f, l43 = 0.0f, l45 = 0.0f;
+    float2 x5 = make_float2(0.0f, 0.0f);
+    bool g2pos = false;
+    if (use3) {
+      t4 = side_lane(t4l, q, dir);
+      const float2 x4 = make_float2(side_lane_f(x4l.x, q, dir), side_lane_f(x4l.y, q, dir));
+      l13 = side_lane_f(l13l, q, dir);
+      l43 = side_lane_f(l43l, q, dir);
+      p5 = pos[t5];
+      x5 = txy[p5];
+      l45 = ls_len_xy(x4, x5);
+      const float g2f = ((l12 - l13) + l43) - l45;
+      g2pos = (double)g2f > e2;
+      if (in5 && !g2pos && !((double)g2f < -e2)) {
+        const double g1 = G.len(a, t2) - G.len(a, t3);
+        g2pos = (g1 + G.len(t4, t3)) - G.len(t4, t5) > 0.0;
+      }
+      r5 = dir ? p1 - p5 : p5 - p1;
+      if (r5 < 0) r5 += n;
+    }
+    // t4's list stops at the first entry that cannot gain
+    const uint64_t stop = __builtin_amdgcn_ballot_w64(use3 && in5 && !g2pos);
+    const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
+    const int lim = dir ? (stop_p ? (int)__builtin_ctzll(stop_p) : 32) : (stop_s ? (int)__builtin_ctzll(stop_s) : 32);
+    const bool cand = use3 && in5 && q5 < lim && (r5 > r3 || r5 == 0);
+    bool imp = false;
+    if (cand) {
+      const int p6 = cyc_step(p5, -step, n);
+      t6 = tour[p6];
+      const float2 x6 = txy[p6];
+      const float gf = ((l12 + l43) + ls_len_xy(x6, x5)) - ((l13 + l45) + ls_len_xy(x6, x2));
+      imp = (double)gf > min_gain + e3;
+      if (!imp && !((double)gf < min_gain - e3)) {
+        const double d12 = G.len(a, t2), d13 = G.len(a, t3), d43 = G.len(t4, t3), d45 = G.len(t4, t5);
+        imp = ((d12 + d43) + G.len(t6, t5)) - ((d13 + d45) + G.len(t6, t2)) > min_gain;
+      }
+    }
+    const uint64_t mi = __builtin_amdgcn_ballot_w64(imp);
+    const uint64_t ms = mi & 0xffffffffull, mp = mi >> 32;
+    if (ms) {
+      const int l = (int)__builtin_ctzll(ms);
+      Ls3Move m{1, 0, a, rd_lane(t2, l), t3, rd_lane(t4, l), rd_lane(t5, l), rd_lane(t6, l), rd_lane(r3, l), 0};
+      m.end = (rd_lane(r5, l) == 0 ? n : rd_lane(r5, l)) - 1;
+      return m;
+    }
+    if (mp && !p_found) {
+      const int l = 32 + (int)__builtin_ctzll(mp);
+      pm = Ls3Move{1, 1, a, rd_lane(t2, l), t3, rd_lane(t4, l), rd_lane(t5, l), rd_lane(t6, l), rd_lane(r3, l), 0};
+      pm.end = (rd_lane(r5, l) == 0 ? n : rd_lane(r5, l)) - 1;
+      p_found = true;
+    }
+  }
+  if (p_found) return pm;
+  return Ls3Move{0, 0, a, 0, 0, 0, 0, 0, 0, 0};
+}
+
 // reverse the len tour positions from i on (cyclic), exactly these (no
 // complement); block-wide, ends with a barrier
 template <class IP>
@@ -1914,10 +2052,32 @@ __device__ __forceinline__ void ls_reverse_span(int n, IP tour, IP pos, int i, i
 }
 
 // The move a wave found for its node: kind 0 none, 2 a 2-opt move, 3 a
-// segment exchange.
+// segment exchange.  In mode 2 a 2-opt move also carries the path to
+// reverse (positions i .. j, the shorter side, and half its length).
 struct Ls3Any {
-  int kind, a, b, c, e, dir, t1, t2, t3, t4, t5, t6, r3, end;
+  int kind, a, b, c, e, dir, t1, t2, t3, t4, t5, t6, r3, end, i, j, half;
 };
+
+// Swap tour positions i + s and j - s (cyclic) for s < half, with their
+// FP32 coordinates; block-wide, ends with a barrier.
+__device__ __forceinline__ void ls_reverse_xy(int n, uint16_t* tour, uint16_t* pos, float2* txy, int i, int j,
+                                              int half) {
+  for (int s = threadIdx.x; s < half; s += blockDim.x) {
+    int pi = i + s;
+    if (pi >= n) pi -= n;
+    int pj = j - s;
+    if (pj < 0) pj += n;
+    const int ti = tour[pi], tj = tour[pj];
+    const float2 xi = txy[pi], xj = txy[pj];
+    tour[pi] = (uint16_t)tj;
+    tour[pj] = (uint16_t)ti;
+    txy[pi] = xj;
+    txy[pj] = xi;
+    pos[tj] = (uint16_t)pi;
+    pos[ti] = (uint16_t)pj;
+  }
+  __syncthreads();
+}
 
 // One block of W waves per tour, organised like the 2-opt's: each round the
 // waves evaluate the next queue entries against the same tour (wave 0 takes
@@ -1925,9 +2085,11 @@ struct Ls3Any {
 // examines it again), the first improving result in queue order is
 // applied, and the entries before it are consumed as the sequential search
 // consumes them; the results behind it are dropped.  Thread 0 keeps the
-// queue; the block reverses paths.
-template <class IP, class BP>
-__device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain) {
+// queue; the block reverses paths.  XY: mode 2 (FP32 coordinates in tour
+// order beside the uint16 arrays, and the bounds e1 .. e3 of its filters).
+template <bool XY, class IP, class BP>
+__device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain,
+                                float2* txy = nullptr, double e1 = 0.0, double e2 = 0.0, double e3 = 0.0) {
   __shared__ int sh_head, sh_count;
   __shared__ Ls3Any sh_mv[LS_WAVES];
   const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
@@ -1962,16 +2124,37 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
         if (slot >= n) slot -= n;
         node = queue[slot];
       }
-      Ls3Any r{0, node, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
-      if (m.imp) {
-        r.kind = 2;
-        r.b = m.b;
-        r.c = m.c;
-        r.e = m.e;
-        r.dir = m.dir;
+      Ls3Any r{0, node, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      bool two = false;
+      if constexpr (XY) {
+        const LsMoveXY m = ls_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2);
+        if (m.imp) {
+          two = true;
+          r.kind = 2;
+          r.b = m.b;
+          r.c = m.c;
+          r.e = m.e;
+          r.i = m.i;
+          r.j = m.j;
+          r.half = m.half;
+        }
       } else {
-        const Ls3Move x = ls3_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
+        const LsMove m = ls_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
+        if (m.imp) {
+          two = true;
+          r.kind = 2;
+          r.b = m.b;
+          r.c = m.c;
+          r.e = m.e;
+          r.dir = m.dir;
+        }
+      }
+      if (!two) {
+        Ls3Move x;
+        if constexpr (XY)
+          x = ls3_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2, e3);
+        else
+          x = ls3_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
         if (x.imp) {
           r.kind = 3;
           r.dir = x.dir;
@@ -1999,8 +2182,13 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
     if (f >= 0) {
       mv = sh_mv[f];
       if (mv.kind == 2) {
-        ri = pos[mv.dir == 0 ? mv.b : mv.c];
-        rj = pos[mv.dir == 0 ? mv.c : mv.b];
+        if constexpr (XY) {
+          ri = mv.i;
+          rj = mv.j;
+        } else {
+          ri = pos[mv.dir == 0 ? mv.b : mv.c];
+          rj = pos[mv.dir == 0 ? mv.c : mv.b];
+        }
       } else {
         const int p1 = pos[mv.a];
         ri = mv.dir == 0 ? p1 + 1 : p1 - mv.end;
@@ -2058,16 +2246,27 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
       sh_count = cnt;
     }
     if (mv.kind == 2) {
-      ls_reverse(n, tour, pos, ri, rj);
+      if constexpr (XY)
+        ls_reverse_xy(n, tour, pos, txy, ri, rj, mv.half);
+      else
+        ls_reverse(n, tour, pos, ri, rj);
     } else {
       // the segments t2..t4 (r3 - 1 nodes) and t3..t6 (end - r3 + 1) trade
       // places: reversing both together and then each gives that
       const int first = mv.dir == 0 ? mv.end - mv.r3 + 1 : mv.r3 - 1;  // the segment that ends up first
-      ls_reverse_span(n, tour, pos, ri, mv.end);
-      ls_reverse_span(n, tour, pos, ri, first);
       int st2 = ri + first;
       if (st2 >= n) st2 -= n;
-      ls_reverse_span(n, tour, pos, st2, mv.end - first);
+      if constexpr (XY) {
+        // span (i, len): positions i .. i + len - 1
+        auto last = [n](int i, int len) { const int j = i + len - 1; return j >= n ? j - n : j; };
+        ls_reverse_xy(n, tour, pos, txy, ri, last(ri, mv.end), mv.end / 2);
+        ls_reverse_xy(n, tour, pos, txy, ri, last(ri, first), first / 2);
+        ls_reverse_xy(n, tour, pos, txy, st2, last(st2, mv.end - first), (mv.end - first) / 2);
+      } else {
+        ls_reverse_span(n, tour, pos, ri, mv.end);
+        ls_reverse_span(n, tour, pos, ri, first);
+        ls_reverse_span(n, tour, pos, st2, mv.end - first);
+      }
     }
     ++moves;
     pend = mv.a;
@@ -2075,29 +2274,40 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
   __syncthreads();
 }
 
-// working arrays: MODE 1 int32 tour, positions and queue and byte flags in
-// LDS (13 bytes per node), MODE 0 the tour in place and the rest in the
-// tour's work area
+// working arrays: MODE 2 the 2-opt's mode-2 arrays (uint16 tour, positions
+// and queue, byte flags, FP32 coordinates in tour order; 15 bytes per node),
+// MODE 1 int32 tour, positions and queue and byte flags in LDS (13 bytes per
+// node), MODE 0 the tour in place and the rest in the tour's work area
 template <int MODE>
 __device__ __forceinline__ void three_opt_tour(const InstDesc& D, int32_t* tour_g, double min_gain,
                                                int32_t* work) {
   extern __shared__ int32_t ls_lds[];
   const int n = D.n;
-  if constexpr (MODE == 1) {
+  if constexpr (MODE == 2) {
+    uint16_t* tour = reinterpret_cast<uint16_t*>(ls_lds);
+    uint16_t* pos = tour + n;
+    uint16_t* queue = pos + n;
+    uint8_t* inq = reinterpret_cast<uint8_t*>(ls_lds) + ((size_t)6 * n + 15) / 16 * 16;
+    float2* txy = reinterpret_cast<float2*>(reinterpret_cast<uint8_t*>(inq) + ((size_t)n + 15) / 16 * 16);
+    const double M = ls_stage_xy(D, tour_g, tour, txy);
+    three_opt_block<true>(D, tour, pos, queue, inq, min_gain, txy, M * 0x1p-18, M * 0x1p-17, M * 0x1p-16);
+    __syncthreads();
+    for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
+  } else if constexpr (MODE == 1) {
     int32_t* tour = ls_lds;
     int32_t* pos = tour + n;
     int32_t* queue = pos + n;
     uint8_t* inq = reinterpret_cast<uint8_t*>(queue + n);
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour[s] = tour_g[s];
     __syncthreads();
-    three_opt_block(D, tour, pos, queue, inq, min_gain);
+    three_opt_block<false>(D, tour, pos, queue, inq, min_gain);
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
   } else {
     HAC_AS1 int32_t* tour = as_global(tour_g);
     HAC_AS1 int32_t* pos = as_global(work);
     HAC_AS1 int32_t* queue = pos + n;
     HAC_AS1 uint8_t* inq = reinterpret_cast<HAC_AS1 uint8_t*>(queue + n);
-    three_opt_block(D, tour, pos, queue, inq, min_gain);
+    three_opt_block<false>(D, tour, pos, queue, inq, min_gain);
   }
   __threadfence_block();
   __syncthreads();
@@ -2841,6 +3051,7 @@ static size_t ls_static_lds() {
     size_t m = 0;
     const void* ks[] = {(const void*)two_opt_nn_kernel<2>, (const void*)two_opt_nn_kernel<1>,
                         (const void*)local_search_kernel<2>, (const void*)local_search_kernel<1>,
+                        (const void*)three_opt_nn_kernel<2>, (const void*)three_opt_kernel<2>,
                         (const void*)three_opt_nn_kernel<1>, (const void*)three_opt_kernel<1>};
     for (const void* k : ks) {
       hipFuncAttributes a{};
@@ -2912,35 +3123,87 @@ static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_
   return hipGetLastError();
 }
 
-// Waves per 3-opt block: the most (up to LS_WAVES, a power of two) with
-// which every tour's block is resident at once (8 192 wave slots: 256 CUs x
-// 32); beyond that the speculative evaluations cost more than they save
-// (every ant's tour of 128 n = 1000 instances, per launch: 1 wave 18.1 ms,
-// 2 waves 14.0 ms, 4 waves 15.7 ms).  HAC_LS_WAVES pins the count.
-static int three_opt_waves(int64_t tours) {
+// Waves per 3-opt block: the fewest rounds of resident blocks first (every
+// tour's block resident at once where some W allows it), then the most waves
+// per tour (up to LS_WAVES, a power of two), with residency from the
+// kernel's occupancy at its LDS size (registers and LDS per CU).  Where
+// tours wait for a slot either way, more waves per tour pay; where one wave
+// per tour keeps every tour resident and two would not, one wins (every
+// ant's tour of 128 instances, 200 iterations, per launch: n = 500 1 wave
+// 3.5 ms, 2 waves 3.7 ms, 4 waves 4.2 ms; n = 1000 10.3, 7.9, 9.2 ms).
+// HAC_LS_WAVES pins the count.
+static int three_opt_waves(const void* kernel, size_t lds, int64_t tours) {
   if (const char* env = std::getenv("HAC_LS_WAVES")) {
     const int w = std::atoi(env);
     if (w >= 1 && w <= LS_WAVES) return w;
   }
+  struct Key {
+    const void* k;
+    size_t lds;
+    int dev;
+  };
+  thread_local std::vector<std::pair<Key, std::array<int, 5>>> cache;  // blocks per CU at W = 1, 2, .. 16
+  thread_local int cus = 0, cus_dev = -1;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  if (cus_dev != dev) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    cus_dev = dev;
+  }
+  const std::array<int, 5>* per_cu = nullptr;
+  for (const auto& e : cache)
+    if (e.first.k == kernel && e.first.lds == lds && e.first.dev == dev) per_cu = &e.second;
+  if (!per_cu) {
+    std::array<int, 5> v{};
+    for (int x = 0, w = 1; w <= LS_WAVES; ++x, w *= 2) {
+      int b = 0;
+      v[x] = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, w * WAVE, lds) == hipSuccess ? b : 0;
+    }
+    cache.push_back({Key{kernel, lds, dev}, v});
+    per_cu = &cache.back().second;
+  }
+  int best = 0;
+  int64_t best_rounds = INT64_MAX;
+  for (int x = 0, w = 1; w <= LS_WAVES; ++x, w *= 2) {
+    const int64_t slots = (int64_t)(*per_cu)[x] * cus;
+    if (slots < 1) continue;
+    const int64_t rounds = (tours + slots - 1) / slots;
+    if (rounds <= best_rounds) {
+      best_rounds = rounds;
+      best = w;
+    }
+  }
+  if (best) return best;
+  // no occupancy figure: the most waves with which 8 192 wave slots hold every tour
   int w = LS_WAVES;
   while (w > 1 && tours * w > 8192) w /= 2;
   return w;
 }
 
 // the 3-opt: one block per tour, the working arrays in LDS when they fit
-static hipError_t launch_three_opt(const InstDesc* d_insts, int32_t count, int32_t max_n3, int32_t tpi, bool nn,
-                                   hipStream_t s) {
-  const int mode = ls_mode(max_n3, 0);
-  const size_t lds = mode == 1 ? ls_lds_need(max_n3, 1) : 0;
+// (mode 2 when every 3-opt instance has coordinates), as for the 2-opt
+static hipError_t launch_three_opt(const InstDesc* d_insts, int32_t count, int32_t max_n3, int32_t all_coords3,
+                                   int32_t tpi, bool nn, hipStream_t s) {
+  const int mode = ls_mode(max_n3, all_coords3);
+  const size_t lds = ls_lds_need(max_n3, mode);
   const int t = nn ? 1 : std::max(tpi, 1);
-  const dim3 grid(count, t), block(three_opt_waves((int64_t)count * t) * WAVE);
+  const void* nn_k[3] = {(const void*)three_opt_nn_kernel<0>, (const void*)three_opt_nn_kernel<1>,
+                         (const void*)three_opt_nn_kernel<2>};
+  const void* ls_k[3] = {(const void*)three_opt_kernel<0>, (const void*)three_opt_kernel<1>,
+                         (const void*)three_opt_kernel<2>};
+  const void* kernel = nn ? nn_k[mode] : ls_k[mode];
+  const dim3 grid(count, t), block(three_opt_waves(kernel, lds, (int64_t)count * t) * WAVE);
   if (nn) {
-    if (mode == 1)
+    if (mode == 2)
+      hipLaunchKernelGGL(three_opt_nn_kernel<2>, grid, block, lds, s, d_insts);
+    else if (mode == 1)
       hipLaunchKernelGGL(three_opt_nn_kernel<1>, grid, block, lds, s, d_insts);
     else
       hipLaunchKernelGGL(three_opt_nn_kernel<0>, grid, block, 0, s, d_insts);
   } else {
-    if (mode == 1)
+    if (mode == 2)
+      hipLaunchKernelGGL(three_opt_kernel<2>, grid, block, lds, s, d_insts);
+    else if (mode == 1)
       hipLaunchKernelGGL(three_opt_kernel<1>, grid, block, lds, s, d_insts);
     else
       hipLaunchKernelGGL(three_opt_kernel<0>, grid, block, 0, s, d_insts);
@@ -2949,9 +3212,10 @@ static hipError_t launch_three_opt(const InstDesc* d_insts, int32_t count, int32
 }
 
 hipError_t launch_two_opt_nn(const InstDesc* d_insts, int32_t count, int32_t max_n, int32_t all_coords,
-                             int32_t max_n_dir, int32_t max_kls_dir, int32_t max_n3, hipStream_t s) {
+                             int32_t max_n_dir, int32_t max_kls_dir, int32_t max_n3, int32_t all_coords3,
+                             hipStream_t s) {
   if (max_n3 > 0) {
-    const hipError_t e = launch_three_opt(d_insts, count, max_n3, 1, true, s);
+    const hipError_t e = launch_three_opt(d_insts, count, max_n3, all_coords3, 1, true, s);
     if (e != hipSuccess) return e;
   }
   if (max_n_dir > 0) {
@@ -3168,9 +3432,9 @@ static int ls_block_waves(int32_t max_n, int mode, int64_t tours) {
 
 hipError_t launch_local_search(const InstDesc* d_insts, int32_t count, int32_t max_n,
                                int32_t all_coords, int32_t tours_per_inst, int32_t max_n_dir,
-                               int32_t max_kls_dir, int32_t max_n3, hipStream_t s) {
+                               int32_t max_kls_dir, int32_t max_n3, int32_t all_coords3, hipStream_t s) {
   if (max_n3 > 0) {
-    const hipError_t e = launch_three_opt(d_insts, count, max_n3, tours_per_inst, false, s);
+    const hipError_t e = launch_three_opt(d_insts, count, max_n3, all_coords3, tours_per_inst, false, s);
     if (e != hipSuccess) return e;
   }
   if (max_n_dir > 0) {

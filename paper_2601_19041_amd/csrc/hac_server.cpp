@@ -391,7 +391,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
       dirty = false;
     }
     // max_n: the largest symmetric instance with 2-opt (0: none); max_n_dir: ATSP
-    int32_t remaining = 1 << 30, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0, max_kls_dir = 0, max_n3 = 0;
+    int32_t remaining = 1 << 30, max_n = 0, all_coords = 1, ls_tours = 1, max_n_dir = 0, max_kls_dir = 0, max_n3 = 0, all_coords3 = 1;
     bool any_ls = false;
     for (auto& sl : LN.active) {
       remaining = std::min(remaining, sl.h.p.iterations - sl.done_iters);
@@ -401,6 +401,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
       else if (sl.h.lay.three_opt) max_n3 = std::max(max_n3, sl.h.lay.n);
       else if (sl.h.p.local_search) max_n = std::max(max_n, sl.h.lay.n);
       if (sl.h.p.local_search && !sl.h.lay.directed && !sl.h.lay.three_opt && !sl.h.lay.coords) all_coords = 0;
+      if (sl.h.lay.three_opt && !sl.h.lay.coords) all_coords3 = 0;
     }
     bool queued = false;
     {
@@ -415,7 +416,7 @@ void serve_lane(hac_server* S, Lane* lane_ptr) {
       ok = hip_ok(S, launch_construct(d_descs, d_map, (int32_t)map.size(), shape.ants_per_block,
                                       shape.rows_per_wave, shape.staged, shape.bytes, shape.kmax, lds,
                                       shape.geo, shape.grid, s), "construct");
-      if (ok && any_ls) ok = hip_ok(S, launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, max_n3, s), "local search");
+      if (ok && any_ls) ok = hip_ok(S, launch_local_search(d_descs, m, max_n, all_coords, ls_tours, max_n_dir, max_kls_dir, max_n3, all_coords3, s), "local search");
       if (ok) ok = hip_ok(S, launch_iter_end(d_descs, m, s), "iter end");
     }
     if (ok) ok = hip_ok(S, launch_finish(d_descs, m, d_outs, d_lens, s), "finish");

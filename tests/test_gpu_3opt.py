@@ -1,8 +1,10 @@
 """GPU parity of the 3-opt (symmetric instances): tours, lengths, the last
 iteration's ant tours and the per-iteration trace equal the oracle's, with
-the 3-opt on the iteration best and on every ant, with the working arrays in
-LDS and in global memory, on coordinates and on a symmetric matrix, inside
-mixed batches beside the 2-opt and the directed 2-opt, and among served
+the 3-opt on the iteration best and on every ant, with the working arrays
+in LDS (uint16 with FP32-filtered tests on tour-ordered coordinates, or
+int32 with FP64 tests) and in global memory, on coordinates (near the
+origin, far from it, on a lattice) and on a symmetric matrix, inside mixed
+batches beside the 2-opt and the directed 2-opt, and among served
 requests."""
 
 import dataclasses
@@ -55,14 +57,33 @@ def _three(inst):
     return dataclasses.replace(inst, ls_op=3)
 
 
+MODES = {"lds_fp32": None, "lds_int32": "1", "global": "0"}
+
+
 @pytest.mark.parametrize("ls", [1, 2])
-@pytest.mark.parametrize("mode", ["lds", "global"])
+@pytest.mark.parametrize("mode", list(MODES))
 def test_three_opt_small(ctx, ls, mode, monkeypatch):
     inst = _three(wl.random_instance(120, seed=60 + ls, k=8, ants=8, iterations=15, local_search=ls, k_ls=10))
-    if mode == "global":
-        monkeypatch.setenv("HAC_LS_MODE", "0")
+    if MODES[mode] is not None:
+        monkeypatch.setenv("HAC_LS_MODE", MODES[mode])
     print(f"case 3-opt n=120 local_search {ls} {mode}", flush=True)
     _same(ctx.decode(inst), oracle.decode(inst), f"ls{ls} {mode}")
+    _state(ctx, inst)
+
+
+@pytest.mark.parametrize("where", ["offset", "lattice"])
+def test_three_opt_fp32_filters(ctx, where):
+    """Far from the origin (the FP32 error bounds scale with the largest
+    coordinate) and on a lattice (exact ties, decided in FP64 inside the
+    bounds), with the 3-opt on every ant."""
+    if where == "offset":
+        inst = _three(wl.random_instance(300, seed=66, k=10, ants=8, iterations=12, local_search=2, k_ls=16))
+        inst.coords = inst.coords * 1e5 + 3e6
+    else:
+        inst = _three(wl.random_instance(196, seed=67, grid=14, k=10, ants=8, iterations=12, local_search=2,
+                                         k_ls=16))
+    print(f"case 3-opt FP32 filters {where}", flush=True)
+    _same(ctx.decode(inst), oracle.decode(inst), where)
     _state(ctx, inst)
 
 
