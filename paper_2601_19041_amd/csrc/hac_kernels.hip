@@ -721,6 +721,17 @@ struct LsMoveXY {
   int imp, a, b, c, e, i, j, half;
 };
 
+// What the evaluation of node a leaves for the 3-opt's exchange search (per
+// lane: this half's direction, list entry q): a's position, its tour
+// neighbour b and the list entry c with their positions and FP32
+// coordinates and distances, and whether d(a,b) - d(a,c) > 0 in FP64.
+struct LsNodeXY {
+  int pa, b, c, pc;
+  float2 xa, xb, xc;
+  float lab, lac;
+  bool g1pos;
+};
+
 // the hardware square root (within 1 ulp, inside the bound's allowance)
 // instead of the correctly rounded library sequence
 __device__ __forceinline__ float ls_len_xy(float2 p, float2 q) {
@@ -737,7 +748,7 @@ __device__ __forceinline__ int cyc_step(int p, int step, int n) {
 __device__ __forceinline__ LsMoveXY ls_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls,
                                               int n, const uint16_t* tour, const uint16_t* pos,
                                               const float2* txy, int a, double min_gain, double e1,
-                                              double e2) {
+                                              double e2, LsNodeXY& nd) {
   const int lane = lane_id();
   const bool pred_dir = lane >= 32;
   const int q = lane & 31;
@@ -766,6 +777,7 @@ __device__ __forceinline__ LsMoveXY ls_eval_xy(const GDist& G, const HAC_AS1 int
     have64 = true;
     g1pos = dab - dac > 0.0;
   }
+  nd = LsNodeXY{pa, b, c, pc, xa, xb, xc, lab, lac, g1pos};
   // a direction stops at the first list entry that cannot gain
   const uint64_t stop = __builtin_amdgcn_ballot_w64(in_list && !g1pos);
   const uint64_t stop_s = stop & 0xffffffffull, stop_p = stop >> 32;
@@ -844,7 +856,8 @@ __device__ __forceinline__ void two_opt_block_xy(const InstDesc& D, uint16_t* to
         if (slot >= n) slot -= n;
         node = queue[slot];
       }
-      const LsMoveXY m = ls_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2);
+      LsNodeXY nd;
+      const LsMoveXY m = ls_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2, nd);
       if (lane == 0) sh_mv[wave] = m;
     }
     __syncthreads();
@@ -1917,10 +1930,11 @@ __device__ Ls3Move ls3_eval(const GDist& G, const HAC_AS1 int32_t* geo, int kg, 
 //   g1 = d12 - d13                        (2 distances)  within E1 = 2^-18 M,
 //   g2 = (g1 + d43) - d45                 (4 distances)  within E2 = 2^-17 M,
 //   ((d12 + d43) + d65) - ((d13 + d45) + d62)  (6)       within E3 = 2^-16 M.
-// a's list is read once per node, one entry per lane of each half, with the
-// entry's t3, its steps from t1, its t4 on that half's side and their
-// distances; t3's loop reads them from lane q of the half, and t4's list
-// for the next t3 is loaded while the current one is examined.
+// The 2-opt evaluation of a has just read a's list, one entry per lane of
+// each half, with positions, coordinates, distances and g1 (nd); the
+// exchange search adds each entry's steps from t1 and its t4 on that half's
+// side, and t3's loop reads these from lane q of the half; t4's list for the
+// next t3 is loaded while the current one is examined.
 
 __device__ __forceinline__ int side_lane(int v, int q, int dir) {
   const int s = __builtin_amdgcn_readlane(v, q);
@@ -1934,34 +1948,26 @@ __device__ __forceinline__ float side_lane_f(float v, int q, int dir) {
 
 __device__ Ls3Move ls3_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls, int n,
                                const uint16_t* tour, const uint16_t* pos, const float2* txy, int a,
-                               double min_gain, double e1, double e2, double e3) {
+                               const LsNodeXY& nd, double min_gain, double e2, double e3) {
   const int lane = lane_id();
   const int dir = lane >= 32 ? 1 : 0;
   const int step = dir ? -1 : 1;
   const int q5 = lane & 31;
   const bool in5 = q5 < kls;
-  const int p1 = pos[a];
-  const int p2 = cyc_step(p1, step, n);
-  const int t2 = tour[p2];
-  const float2 x1 = txy[p1], x2 = txy[p2];
-  const float l12 = ls_len_xy(x1, x2);
-  // list entry q5 of a: t3, its steps from t1 in this half's direction,
-  // the node before it (t4) and the FP32 distances d13, d43
-  const int t3l = geo[(int64_t)a * kg + min(q5, kls - 1)];
-  const int p3l = pos[t3l];
+  const int p1 = nd.pa, t2 = nd.b;
+  const float2 x2 = nd.xb;
+  const float l12 = nd.lab;
+  // list entry q5 of a (t3 = nd.c): its steps from t1 in this half's
+  // direction, the node before it (t4) and the FP32 distances d13, d43
+  const int t3l = nd.c, p3l = nd.pc;
   int r3l = dir ? p1 - p3l : p3l - p1;
   if (r3l < 0) r3l += n;
   const int p4l = cyc_step(p3l, -step, n);
   const int t4l = tour[p4l];
-  const float2 x3l = txy[p3l], x4l = txy[p4l];
-  const float l13l = ls_len_xy(x1, x3l), l43l = ls_len_xy(x4l, x3l);
-  // g1 > 0 as FP64 decides it; t3 = t2 gives exactly 0
-  const float g1l = l12 - l13l;
-  bool g1pos = t3l != t2 && (double)g1l > e1;
-  if (in5 && t3l != t2 && !((double)g1l > e1) && !((double)g1l < -e1))
-    g1pos = G.len(a, t2) - G.len(a, t3l) > 0.0;
-  // a side stops at the first t3 that cannot gain
-  const uint64_t gstop = __builtin_amdgcn_ballot_w64(in5 && !g1pos);
+  const float2 x4l = txy[p4l];
+  const float l13l = nd.lac, l43l = ls_len_xy(x4l, nd.xc);
+  // a side stops at the first t3 that cannot gain (g1 as FP64 decides it)
+  const uint64_t gstop = __builtin_amdgcn_ballot_w64(in5 && !nd.g1pos);
   const uint64_t gs = gstop & 0xffffffffull, gp = gstop >> 32;
   const int lim_s = min(gs ? (int)__builtin_ctzll(gs) : 32, kls);
   const int lim_p = min(gp ? (int)__builtin_ctzll(gp) : 32, kls);
@@ -2126,8 +2132,9 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
       }
       Ls3Any r{0, node, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       bool two = false;
+      LsNodeXY nd;
       if constexpr (XY) {
-        const LsMoveXY m = ls_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2);
+        const LsMoveXY m = ls_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2, nd);
         if (m.imp) {
           two = true;
           r.kind = 2;
@@ -2152,7 +2159,7 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
       if (!two) {
         Ls3Move x;
         if constexpr (XY)
-          x = ls3_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2, e3);
+          x = ls3_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, nd, min_gain, e2, e3);
         else
           x = ls3_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
         if (x.imp) {
