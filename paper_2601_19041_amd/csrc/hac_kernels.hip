@@ -2093,14 +2093,16 @@ __device__ __forceinline__ void ls_reverse_xy(int n, uint16_t* tour, uint16_t* p
 // consumes them; the results behind it are dropped.  Thread 0 keeps the
 // queue; the block reverses paths.  XY: mode 2 (FP32 coordinates in tour
 // order beside the uint16 arrays, and the bounds e1 .. e3 of its filters).
+// Returns rot: the final array is the sequential search's tour rotated,
+// tour[x] = its [(x + rot) mod n] (see the segment exchange below).
 template <bool XY, class IP, class BP>
-__device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain,
-                                float2* txy = nullptr, double e1 = 0.0, double e2 = 0.0, double e3 = 0.0) {
+__device__ int three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain,
+                               float2* txy = nullptr, double e1 = 0.0, double e2 = 0.0, double e3 = 0.0) {
   __shared__ int sh_head, sh_count;
   __shared__ Ls3Any sh_mv[LS_WAVES];
   const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
   const int nw = (int)(blockDim.x / WAVE);
-  if (n < 5 || kls < 1) return;
+  if (n < 5 || kls < 1) return 0;
   const GDist G(D);
   const HAC_AS1 int32_t* geo = as_global(D.geo);
   for (int s = threadIdx.x; s < n; s += blockDim.x) {
@@ -2117,6 +2119,7 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
   const int64_t max_moves = 64 * (int64_t)n;
   int64_t moves = 0;
   int pend = -1;
+  int rot = 0;  // the array holds the sequential search's tour rotated: tour[x] = its [(x + rot) mod n]
   while (moves < max_moves) {
     const int head = sh_head, count = sh_count;
     const int re = pend >= 0 ? 1 : 0;
@@ -2258,27 +2261,52 @@ __device__ void three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP
       else
         ls_reverse(n, tour, pos, ri, rj);
     } else {
-      // the segments t2..t4 (r3 - 1 nodes) and t3..t6 (end - r3 + 1) trade
-      // places: reversing both together and then each gives that
-      const int first = mv.dir == 0 ? mv.end - mv.r3 + 1 : mv.r3 - 1;  // the segment that ends up first
-      int st2 = ri + first;
-      if (st2 >= n) st2 -= n;
-      if constexpr (XY) {
-        // span (i, len): positions i .. i + len - 1
-        auto last = [n](int i, int len) { const int j = i + len - 1; return j >= n ? j - n : j; };
-        ls_reverse_xy(n, tour, pos, txy, ri, last(ri, mv.end), mv.end / 2);
-        ls_reverse_xy(n, tour, pos, txy, ri, last(ri, first), first / 2);
-        ls_reverse_xy(n, tour, pos, txy, st2, last(st2, mv.end - first), (mv.end - first) / 2);
+      // The segments t2..t4 (r3 - 1 nodes) and t3..t6 (end - r3 + 1) trade
+      // places.  In array order from ri they are blocks P (pa nodes) and Q
+      // (qb nodes); the rest of the tour, t1 among it, is block Z.  Swapping
+      // any two of the three adjacent blocks gives the same cyclic tour in
+      // the same direction, so the swap that moves the fewest nodes is made
+      // (P with Q is the sequential search's); swapping Q with Z leaves the
+      // array rotated by qb positions against it, Z with P by -pa, which rot
+      // accumulates.  Later moves depend only on the cyclic tour, and the
+      // rotation is undone when the tour is written back.
+      const int qb = mv.dir == 0 ? mv.end - mv.r3 + 1 : mv.r3 - 1;  // the block that ends up first
+      const int pa = mv.end - qb, zc = n - mv.end;
+      // reverse the len positions from i (i < 2n, cyclic)
+      auto span = [&](int i, int len) {
+        if (i >= n) i -= n;
+        if constexpr (XY) {
+          int j = i + len - 1;
+          if (j >= n) j -= n;
+          ls_reverse_xy(n, tour, pos, txy, i, j, len / 2);
+        } else {
+          ls_reverse_span(n, tour, pos, i, len);
+        }
+      };
+      // blocks [s, s + x) and [s + x, s + x + y) trade places
+      auto swap_blocks = [&](int s0, int x, int y) {
+        if (s0 >= n) s0 -= n;
+        span(s0, x + y);
+        span(s0, y);
+        span(s0 + y, x);
+      };
+      if (mv.end <= n - pa && mv.end <= n - qb) {
+        swap_blocks(ri, pa, qb);
+      } else if (n - pa <= n - qb) {
+        swap_blocks(ri + pa, qb, zc);
+        rot += qb;
+        if (rot >= n) rot -= n;
       } else {
-        ls_reverse_span(n, tour, pos, ri, mv.end);
-        ls_reverse_span(n, tour, pos, ri, first);
-        ls_reverse_span(n, tour, pos, st2, mv.end - first);
+        swap_blocks(ri + pa + qb, zc, pa);
+        rot -= pa;
+        if (rot < 0) rot += n;
       }
     }
     ++moves;
     pend = mv.a;
   }
   __syncthreads();
+  return rot;
 }
 
 // working arrays: MODE 2 the 2-opt's mode-2 arrays (uint16 tour, positions
@@ -2297,9 +2325,10 @@ __device__ __forceinline__ void three_opt_tour(const InstDesc& D, int32_t* tour_
     uint8_t* inq = reinterpret_cast<uint8_t*>(ls_lds) + ((size_t)6 * n + 15) / 16 * 16;
     float2* txy = reinterpret_cast<float2*>(reinterpret_cast<uint8_t*>(inq) + ((size_t)n + 15) / 16 * 16);
     const double M = ls_stage_xy(D, tour_g, tour, txy);
-    three_opt_block<true>(D, tour, pos, queue, inq, min_gain, txy, M * 0x1p-18, M * 0x1p-17, M * 0x1p-16);
+    const int rot = three_opt_block<true>(D, tour, pos, queue, inq, min_gain, txy, M * 0x1p-18, M * 0x1p-17,
+                                          M * 0x1p-16);
     __syncthreads();
-    for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
+    for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s - rot < 0 ? s - rot + n : s - rot];
   } else if constexpr (MODE == 1) {
     int32_t* tour = ls_lds;
     int32_t* pos = tour + n;
@@ -2307,14 +2336,20 @@ __device__ __forceinline__ void three_opt_tour(const InstDesc& D, int32_t* tour_
     uint8_t* inq = reinterpret_cast<uint8_t*>(queue + n);
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour[s] = tour_g[s];
     __syncthreads();
-    three_opt_block<false>(D, tour, pos, queue, inq, min_gain);
-    for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s];
+    const int rot = three_opt_block<false>(D, tour, pos, queue, inq, min_gain);
+    for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s - rot < 0 ? s - rot + n : s - rot];
   } else {
     HAC_AS1 int32_t* tour = as_global(tour_g);
     HAC_AS1 int32_t* pos = as_global(work);
     HAC_AS1 int32_t* queue = pos + n;
     HAC_AS1 uint8_t* inq = reinterpret_cast<HAC_AS1 uint8_t*>(queue + n);
-    three_opt_block<false>(D, tour, pos, queue, inq, min_gain);
+    const int rot = three_opt_block<false>(D, tour, pos, queue, inq, min_gain);
+    if (rot) {  // undo the rotation through the queue array, free by now
+      for (int s = threadIdx.x; s < n; s += blockDim.x) queue[s] = tour[s];
+      __threadfence_block();
+      __syncthreads();
+      for (int s = threadIdx.x; s < n; s += blockDim.x) tour[s] = queue[s - rot < 0 ? s - rot + n : s - rot];
+    }
   }
   __threadfence_block();
   __syncthreads();

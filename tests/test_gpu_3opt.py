@@ -152,3 +152,15 @@ def test_three_opt_served(ctx, hac):
     for x, inst in enumerate(insts):
         assert np.array_equal(res[x][0], alone[x][0]) and res[x][1] == alone[x][1], x
         _same(alone[x], oracle.decode(inst), f"served{x}")
+
+
+def test_three_opt_tsp10k_sampled(ctx):
+    """n = 10 000 (the tour-ordered arrays take 150 KB of LDS): the 3-opt on
+    the NN tour and on the iteration best of two instances decoded in one
+    batch, the first two iterations of one compared with the oracle."""
+    insts = [_three(x) for x in wl.tsp10k(2, iterations=2)]
+    print("case 3-opt tsp10k sampled", flush=True)
+    got = ctx.decode_batch(insts)
+    _same(got[1], oracle.decode(insts[1]), "tsp10k")
+    t, L = got[0]
+    assert sorted(t.tolist()) == list(range(insts[0].n))
