@@ -1933,8 +1933,8 @@ __device__ Ls3Move ls3_eval(const GDist& G, const HAC_AS1 int32_t* geo, int kg, 
 // The 2-opt evaluation of a has just read a's list, one entry per lane of
 // each half, with positions, coordinates, distances and g1 (nd); the
 // exchange search adds each entry's steps from t1 and its t4 on that half's
-// side, and t3's loop reads these from lane q of the half; t4's list for the
-// next t3 is loaded while the current one is examined.
+// side, and t3's loop reads these from lane q of the half; t4's list is
+// loaded two t3 ahead of its use.
 
 __device__ __forceinline__ int side_lane(int v, int q, int dir) {
   const int s = __builtin_amdgcn_readlane(v, q);
@@ -1973,11 +1973,16 @@ __device__ Ls3Move ls3_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int k
   const int lim_p = min(gp ? (int)__builtin_ctzll(gp) : 32, kls);
   bool p_found = false;
   Ls3Move pm{0, 1, a, 0, 0, 0, 0, 0, 0, 0};
-  int t5n = 0;  // t4's list entry q5 for the next t3
-  if (lim_s > 0 || lim_p > 0) t5n = geo[(int64_t)side_lane(t4l, 0, dir) * kg + min(q5, kls - 1)];
+  // t4's list entry q5 for the next two t3, loaded two steps ahead of use
+  const int qmax = max(lim_s, lim_p);
+  const int q5c = min(q5, kls - 1);
+  int t5n = 0, t5nn = 0;
+  if (qmax > 0) t5n = geo[(int64_t)side_lane(t4l, 0, dir) * kg + q5c];
+  if (qmax > 1) t5nn = geo[(int64_t)side_lane(t4l, 1, dir) * kg + q5c];
   for (int q = 0; q < lim_s || (q < lim_p && !p_found); ++q) {
     const int t5 = t5n;
-    if (q + 1 < kls) t5n = geo[(int64_t)side_lane(t4l, q + 1, dir) * kg + min(q5, kls - 1)];
+    t5n = t5nn;
+    if (q + 2 < qmax) t5nn = geo[(int64_t)side_lane(t4l, q + 2, dir) * kg + q5c];
     const bool live = dir ? (q < lim_p && !p_found) : q < lim_s;
     const int t3 = rd_lane(t3l, q);
     const int r3 = side_lane(r3l, q, dir);
