@@ -1946,9 +1946,11 @@ __device__ __forceinline__ float side_lane_f(float v, int q, int dir) {
   return __int_as_float(side_lane(__float_as_int(v), q, dir));
 }
 
+template <bool ABORT>
 __device__ Ls3Move ls3_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int kg, int kls, int n,
                                const uint16_t* tour, const uint16_t* pos, const float2* txy, int a,
-                               const LsNodeXY& nd, double min_gain, double e2, double e3) {
+                               const LsNodeXY& nd, double min_gain, double e2, double e3, int* first,
+                               int wave) {
   const int lane = lane_id();
   const int dir = lane >= 32 ? 1 : 0;
   const int step = dir ? -1 : 1;
@@ -1966,6 +1968,9 @@ __device__ Ls3Move ls3_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int k
   const int t4l = tour[p4l];
   const float2 x4l = txy[p4l];
   const float l13l = nd.lac, l43l = ls_len_xy(x4l, nd.xc);
+  // ABORT: the lowest wave of the round with an improving move so far; once
+  // it is ahead of this one, this wave's result will be dropped, so it stops
+  const int fl0 = ABORT ? *(volatile int*)first : LS_WAVES;
   // a side stops at the first t3 that cannot gain (g1 as FP64 decides it)
   const uint64_t gstop = __builtin_amdgcn_ballot_w64(in5 && !nd.g1pos);
   const uint64_t gs = gstop & 0xffffffffull, gp = gstop >> 32;
@@ -1973,6 +1978,7 @@ __device__ Ls3Move ls3_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int k
   const int lim_p = min(gp ? (int)__builtin_ctzll(gp) : 32, kls);
   bool p_found = false;
   Ls3Move pm{0, 1, a, 0, 0, 0, 0, 0, 0, 0};
+  if (ABORT && fl0 < wave) return pm;  // no move (imp 0)
   // t4's list entry q5 for the next two t3, loaded two steps ahead of use
   const int qmax = max(lim_s, lim_p);
   const int q5c = min(q5, kls - 1);
@@ -1983,6 +1989,7 @@ __device__ Ls3Move ls3_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int k
     const int t5 = t5n;
     t5n = t5nn;
     if (q + 2 < qmax) t5nn = geo[(int64_t)side_lane(t4l, q + 2, dir) * kg + q5c];
+    const int fl = ABORT ? *(volatile int*)first : LS_WAVES;
     const bool live = dir ? (q < lim_p && !p_found) : q < lim_s;
     const int t3 = rd_lane(t3l, q);
     const int r3 = side_lane(r3l, q, dir);
@@ -2038,7 +2045,9 @@ __device__ Ls3Move ls3_eval_xy(const GDist& G, const HAC_AS1 int32_t* geo, int k
       pm = Ls3Move{1, 1, a, rd_lane(t2, l), t3, rd_lane(t4, l), rd_lane(t5, l), rd_lane(t6, l), rd_lane(r3, l), 0};
       pm.end = (rd_lane(r5, l) == 0 ? n : rd_lane(r5, l)) - 1;
       p_found = true;
+      if (ABORT && lane == 0) atomicMin(first, wave);  // this wave returns a move
     }
+    if (ABORT && fl < wave) break;  // dropped either way
   }
   if (p_found) return pm;
   return Ls3Move{0, 0, a, 0, 0, 0, 0, 0, 0, 0};
@@ -2100,10 +2109,14 @@ __device__ __forceinline__ void ls_reverse_xy(int n, uint16_t* tour, uint16_t* p
 // order beside the uint16 arrays, and the bounds e1 .. e3 of its filters).
 // Returns rot: the final array is the sequential search's tour rotated,
 // tour[x] = its [(x + rot) mod n] (see the segment exchange below).
-template <bool XY, class IP, class BP>
+template <bool XY, bool ABORT, class IP, class BP>
 __device__ int three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP inq, double min_gain,
                                float2* txy = nullptr, double e1 = 0.0, double e2 = 0.0, double e3 = 0.0) {
   __shared__ int sh_head, sh_count;
+  // ABORT (mode 2 only): the lowest wave of the round that has found an
+  // improving move; a wave behind it stops its exchange search, whose result
+  // the round drops.  It pays with many waves per block and costs registers.
+  __shared__ int sh_first;
   __shared__ Ls3Any sh_mv[LS_WAVES];
   const int n = D.n, kls = D.kls, kg = D.kg, lane = lane_id(), wave = threadIdx.x / WAVE;
   const int nw = (int)(blockDim.x / WAVE);
@@ -2119,6 +2132,7 @@ __device__ int three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP 
   if (threadIdx.x == 0) {
     sh_head = 0;
     sh_count = n;
+    if (ABORT) sh_first = LS_WAVES;
   }
   __syncthreads();
   const int64_t max_moves = 64 * (int64_t)n;
@@ -2144,6 +2158,7 @@ __device__ int three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP 
       if constexpr (XY) {
         const LsMoveXY m = ls_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, min_gain, e1, e2, nd);
         if (m.imp) {
+          if (ABORT && lane == 0) atomicMin(&sh_first, wave);
           two = true;
           r.kind = 2;
           r.b = m.b;
@@ -2167,7 +2182,7 @@ __device__ int three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP 
       if (!two) {
         Ls3Move x;
         if constexpr (XY)
-          x = ls3_eval_xy(G, geo, kg, kls, n, tour, pos, txy, node, nd, min_gain, e2, e3);
+          x = ls3_eval_xy<ABORT>(G, geo, kg, kls, n, tour, pos, txy, node, nd, min_gain, e2, e3, &sh_first, wave);
         else
           x = ls3_eval(G, geo, kg, kls, n, tour, pos, node, min_gain);
         if (x.imp) {
@@ -2189,6 +2204,7 @@ __device__ int three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP 
     // the first improving result in batch order (one entry per lane)
     const uint64_t fm = __builtin_amdgcn_ballot_w64(lane < nb && sh_mv[min(lane, LS_WAVES - 1)].kind != 0);
     const int f = fm ? (int)__builtin_ctzll(fm) : -1;
+    if (ABORT && threadIdx.x == 0) sh_first = LS_WAVES;  // every wave is past its evaluation
     // queue entries consumed as a sequential scan would: all of them if no
     // move improves, else those up to and including the improving one
     const int used = f < 0 ? nq : max(0, f + 1 - re);
@@ -2316,6 +2332,7 @@ __device__ int three_opt_block(const InstDesc& D, IP tour, IP pos, IP queue, BP 
 
 // working arrays: MODE 2 the 2-opt's mode-2 arrays (uint16 tour, positions
 // and queue, byte flags, FP32 coordinates in tour order; 15 bytes per node),
+// MODE 3 the same with waves that stop once their result will be dropped,
 // MODE 1 int32 tour, positions and queue and byte flags in LDS (13 bytes per
 // node), MODE 0 the tour in place and the rest in the tour's work area
 template <int MODE>
@@ -2323,14 +2340,14 @@ __device__ __forceinline__ void three_opt_tour(const InstDesc& D, int32_t* tour_
                                                int32_t* work) {
   extern __shared__ int32_t ls_lds[];
   const int n = D.n;
-  if constexpr (MODE == 2) {
+  if constexpr (MODE >= 2) {
     uint16_t* tour = reinterpret_cast<uint16_t*>(ls_lds);
     uint16_t* pos = tour + n;
     uint16_t* queue = pos + n;
     uint8_t* inq = reinterpret_cast<uint8_t*>(ls_lds) + ((size_t)6 * n + 15) / 16 * 16;
     float2* txy = reinterpret_cast<float2*>(reinterpret_cast<uint8_t*>(inq) + ((size_t)n + 15) / 16 * 16);
     const double M = ls_stage_xy(D, tour_g, tour, txy);
-    const int rot = three_opt_block<true>(D, tour, pos, queue, inq, min_gain, txy, M * 0x1p-18, M * 0x1p-17,
+    const int rot = three_opt_block<true, MODE == 3>(D, tour, pos, queue, inq, min_gain, txy, M * 0x1p-18, M * 0x1p-17,
                                           M * 0x1p-16);
     __syncthreads();
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s - rot < 0 ? s - rot + n : s - rot];
@@ -2341,14 +2358,14 @@ __device__ __forceinline__ void three_opt_tour(const InstDesc& D, int32_t* tour_
     uint8_t* inq = reinterpret_cast<uint8_t*>(queue + n);
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour[s] = tour_g[s];
     __syncthreads();
-    const int rot = three_opt_block<false>(D, tour, pos, queue, inq, min_gain);
+    const int rot = three_opt_block<false, false>(D, tour, pos, queue, inq, min_gain);
     for (int s = threadIdx.x; s < n; s += blockDim.x) tour_g[s] = tour[s - rot < 0 ? s - rot + n : s - rot];
   } else {
     HAC_AS1 int32_t* tour = as_global(tour_g);
     HAC_AS1 int32_t* pos = as_global(work);
     HAC_AS1 int32_t* queue = pos + n;
     HAC_AS1 uint8_t* inq = reinterpret_cast<HAC_AS1 uint8_t*>(queue + n);
-    const int rot = three_opt_block<false>(D, tour, pos, queue, inq, min_gain);
+    const int rot = three_opt_block<false, false>(D, tour, pos, queue, inq, min_gain);
     if (rot) {  // undo the rotation through the queue array, free by now
       for (int s = threadIdx.x; s < n; s += blockDim.x) queue[s] = tour[s];
       __threadfence_block();
@@ -2376,12 +2393,13 @@ __global__ void __launch_bounds__(LS_WAVES * WAVE) three_opt_nn_kernel(const Ins
 
 // local_search = 1: block (i, 0) improves a copy of the iteration best;
 // local_search = 2: block (i, y) improves ant tours y, y + gridDim.y, ...
-// Held to 96 VGPRs (five waves per SIMD; mode 2 would take 106, four): with
-// the 3-opt on every ant the tours outnumber the resident blocks, and at
-// n = 1000 one wave more per SIMD makes the launch 5% faster (7.85 ->
-// 7.45 ms for 4 096 tours) for a 12-byte spill.
+// Modes 0-2 are held to 96 VGPRs (five waves per SIMD; mode 2 would take
+// 106, four): with the 3-opt on every ant the tours outnumber the resident
+// blocks, and at n = 1000 one wave more per SIMD makes the launch 5% faster
+// (7.85 -> 7.45 ms for 4 096 tours) for a small spill.  Mode 3 (blocks of
+// four or more waves) keeps four waves per SIMD and its registers.
 template <int MODE>
-__global__ void __launch_bounds__(LS_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(LS_WAVES * WAVE) __attribute__((amdgpu_waves_per_eu(MODE == 3 ? 4 : 5)))
 three_opt_kernel(const InstDesc* insts) {
   const InstDesc& D = insts[blockIdx.x];
   if (!D.local_search || !D.sym || D.ls_op != 3 || D.st->t > D.iterations || D.st->err) return;
@@ -3103,6 +3121,7 @@ static size_t ls_static_lds() {
     size_t m = 0;
     const void* ks[] = {(const void*)two_opt_nn_kernel<2>, (const void*)two_opt_nn_kernel<1>,
                         (const void*)local_search_kernel<2>, (const void*)local_search_kernel<1>,
+                        (const void*)three_opt_nn_kernel<3>, (const void*)three_opt_kernel<3>,
                         (const void*)three_opt_nn_kernel<2>, (const void*)three_opt_kernel<2>,
                         (const void*)three_opt_nn_kernel<1>, (const void*)three_opt_kernel<1>};
     for (const void* k : ks) {
@@ -3183,8 +3202,9 @@ static hipError_t launch_directed(const InstDesc* d_insts, int32_t count, int32_
 // per tour keeps every tour resident and two would not, one wins (every
 // ant's tour of 128 instances, 200 iterations, per launch: n = 500 1 wave
 // 3.5 ms, 2 waves 3.7 ms, 4 waves 4.2 ms; n = 1000 10.3, 7.9, 9.2 ms).
-// HAC_LS_WAVES pins the count.
-static int three_opt_waves(const void* kernel, size_t lds, int64_t tours) {
+// HAC_LS_WAVES pins the count.  kernel_wide: the kernel that blocks of four
+// or more waves run (their residency is that kernel's).
+static int three_opt_waves(const void* kernel, const void* kernel_wide, size_t lds, int64_t tours) {
   if (const char* env = std::getenv("HAC_LS_WAVES")) {
     const int w = std::atoi(env);
     if (w >= 1 && w <= LS_WAVES) return w;
@@ -3209,7 +3229,10 @@ static int three_opt_waves(const void* kernel, size_t lds, int64_t tours) {
     std::array<int, 5> v{};
     for (int x = 0, w = 1; w <= LS_WAVES; ++x, w *= 2) {
       int b = 0;
-      v[x] = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, w * WAVE, lds) == hipSuccess ? b : 0;
+      v[x] = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, w >= 4 ? kernel_wide : kernel, w * WAVE, lds) ==
+                     hipSuccess
+                 ? b
+                 : 0;
     }
     cache.push_back({Key{kernel, lds, dev}, v});
     per_cu = &cache.back().second;
@@ -3233,29 +3256,37 @@ static int three_opt_waves(const void* kernel, size_t lds, int64_t tours) {
 }
 
 // the 3-opt: one block per tour, the working arrays in LDS when they fit
-// (mode 2 when every 3-opt instance has coordinates), as for the 2-opt
+// (mode 2 when every 3-opt instance has coordinates, as for the 2-opt; in
+// blocks of four or more waves mode 2 runs as mode 3, whose waves stop once
+// their result will be dropped)
 static hipError_t launch_three_opt(const InstDesc* d_insts, int32_t count, int32_t max_n3, int32_t all_coords3,
                                    int32_t tpi, bool nn, hipStream_t s) {
   const int mode = ls_mode(max_n3, all_coords3);
   const size_t lds = ls_lds_need(max_n3, mode);
   const int t = nn ? 1 : std::max(tpi, 1);
-  const void* nn_k[3] = {(const void*)three_opt_nn_kernel<0>, (const void*)three_opt_nn_kernel<1>,
-                         (const void*)three_opt_nn_kernel<2>};
-  const void* ls_k[3] = {(const void*)three_opt_kernel<0>, (const void*)three_opt_kernel<1>,
-                         (const void*)three_opt_kernel<2>};
-  const void* kernel = nn ? nn_k[mode] : ls_k[mode];
-  const dim3 grid(count, t), block(three_opt_waves(kernel, lds, (int64_t)count * t) * WAVE);
+  const void* nn_k[4] = {(const void*)three_opt_nn_kernel<0>, (const void*)three_opt_nn_kernel<1>,
+                         (const void*)three_opt_nn_kernel<2>, (const void*)three_opt_nn_kernel<3>};
+  const void* ls_k[4] = {(const void*)three_opt_kernel<0>, (const void*)three_opt_kernel<1>,
+                         (const void*)three_opt_kernel<2>, (const void*)three_opt_kernel<3>};
+  const void* const* ks = nn ? nn_k : ls_k;
+  const int waves = three_opt_waves(ks[mode], ks[mode == 2 ? 3 : mode], lds, (int64_t)count * t);
+  const int km = mode == 2 && waves >= 4 ? 3 : mode;
+  const dim3 grid(count, t), block(waves * WAVE);
   if (nn) {
-    if (mode == 2)
+    if (km == 3)
+      hipLaunchKernelGGL(three_opt_nn_kernel<3>, grid, block, lds, s, d_insts);
+    else if (km == 2)
       hipLaunchKernelGGL(three_opt_nn_kernel<2>, grid, block, lds, s, d_insts);
-    else if (mode == 1)
+    else if (km == 1)
       hipLaunchKernelGGL(three_opt_nn_kernel<1>, grid, block, lds, s, d_insts);
     else
       hipLaunchKernelGGL(three_opt_nn_kernel<0>, grid, block, 0, s, d_insts);
   } else {
-    if (mode == 2)
+    if (km == 3)
+      hipLaunchKernelGGL(three_opt_kernel<3>, grid, block, lds, s, d_insts);
+    else if (km == 2)
       hipLaunchKernelGGL(three_opt_kernel<2>, grid, block, lds, s, d_insts);
-    else if (mode == 1)
+    else if (km == 1)
       hipLaunchKernelGGL(three_opt_kernel<1>, grid, block, lds, s, d_insts);
     else
       hipLaunchKernelGGL(three_opt_kernel<0>, grid, block, 0, s, d_insts);

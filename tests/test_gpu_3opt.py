@@ -57,15 +57,22 @@ def _three(inst):
     return dataclasses.replace(inst, ls_op=3)
 
 
-MODES = {"lds_fp32": None, "lds_int32": "1", "global": "0"}
+# working arrays (HAC_LS_MODE) and waves per block (HAC_LS_WAVES): FP32 mode
+# blocks of four or more waves stop waves whose result will be dropped,
+# narrower ones do not
+MODES = {"lds_fp32": (None, None), "lds_fp32_2_waves": (None, "2"), "lds_int32": ("1", None),
+         "global": ("0", None)}
 
 
 @pytest.mark.parametrize("ls", [1, 2])
 @pytest.mark.parametrize("mode", list(MODES))
 def test_three_opt_small(ctx, ls, mode, monkeypatch):
     inst = _three(wl.random_instance(120, seed=60 + ls, k=8, ants=8, iterations=15, local_search=ls, k_ls=10))
-    if MODES[mode] is not None:
-        monkeypatch.setenv("HAC_LS_MODE", MODES[mode])
+    ls_mode, waves = MODES[mode]
+    if ls_mode is not None:
+        monkeypatch.setenv("HAC_LS_MODE", ls_mode)
+    if waves is not None:
+        monkeypatch.setenv("HAC_LS_WAVES", waves)
     print(f"case 3-opt n=120 local_search {ls} {mode}", flush=True)
     _same(ctx.decode(inst), oracle.decode(inst), f"ls{ls} {mode}")
     _state(ctx, inst)
@@ -109,11 +116,14 @@ def test_three_opt_ties(ctx):
     _same(ctx.decode(inst), oracle.decode(inst), "ties")
 
 
-def test_three_opt_paper_setting(ctx):
+@pytest.mark.parametrize("waves", [None, "1"])
+def test_three_opt_paper_setting(ctx, waves, monkeypatch):
     """n = 1000 with the paper's k = 20, k_ls = 20, 32 ants, rho = 0.8, the
-    3-opt on every ant's tour."""
+    3-opt on every ant's tour (16-wave blocks, and one wave per tour)."""
+    if waves is not None:
+        monkeypatch.setenv("HAC_LS_WAVES", waves)
     inst = _three(wl.paper_budget(1000, count=1, local_search=2, iterations=6)[0])
-    print("case 3-opt paper setting n=1000", flush=True)
+    print(f"case 3-opt paper setting n=1000 waves {waves}", flush=True)
     _same(ctx.decode(inst), oracle.decode(inst), "paper1000")
     _state(ctx, inst)
 
