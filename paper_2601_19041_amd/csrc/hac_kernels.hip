@@ -21,8 +21,6 @@
 #include <cstdlib>
 #include <mutex>
 #include <type_traits>
-#include <utility>
-#include <vector>
 
 #include "hac_internal.h"
 
@@ -3209,12 +3207,16 @@ static int three_opt_waves(const void* kernel, const void* kernel_wide, size_t l
     const int w = std::atoi(env);
     if (w >= 1 && w <= LS_WAVES) return w;
   }
-  struct Key {
+  // blocks per CU at W = 1, 2, .. 16, per (kernel, LDS size, device); a
+  // fixed table, so that no launch allocates (a full table recomputes)
+  struct Entry {
     const void* k;
     size_t lds;
     int dev;
+    std::array<int, 5> per_cu;
   };
-  thread_local std::vector<std::pair<Key, std::array<int, 5>>> cache;  // blocks per CU at W = 1, 2, .. 16
+  thread_local std::array<Entry, 16> cache;
+  thread_local int cached = 0;
   thread_local int cus = 0, cus_dev = -1;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
@@ -3222,11 +3224,14 @@ static int three_opt_waves(const void* kernel, const void* kernel_wide, size_t l
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     cus_dev = dev;
   }
-  const std::array<int, 5>* per_cu = nullptr;
-  for (const auto& e : cache)
-    if (e.first.k == kernel && e.first.lds == lds && e.first.dev == dev) per_cu = &e.second;
-  if (!per_cu) {
-    std::array<int, 5> v{};
+  std::array<int, 5> v{};
+  bool found = false;
+  for (int x = 0; x < cached && !found; ++x)
+    if (cache[x].k == kernel && cache[x].lds == lds && cache[x].dev == dev) {
+      v = cache[x].per_cu;
+      found = true;
+    }
+  if (!found) {
     for (int x = 0, w = 1; w <= LS_WAVES; ++x, w *= 2) {
       int b = 0;
       v[x] = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, w >= 4 ? kernel_wide : kernel, w * WAVE, lds) ==
@@ -3234,9 +3239,9 @@ static int three_opt_waves(const void* kernel, const void* kernel_wide, size_t l
                  ? b
                  : 0;
     }
-    cache.push_back({Key{kernel, lds, dev}, v});
-    per_cu = &cache.back().second;
+    if (cached < (int)cache.size()) cache[cached++] = Entry{kernel, lds, dev, v};
   }
+  const std::array<int, 5>* per_cu = &v;
   int best = 0;
   int64_t best_rounds = INT64_MAX;
   for (int x = 0, w = 1; w <= LS_WAVES; ++x, w *= 2) {
